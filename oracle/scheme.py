@@ -1,0 +1,165 @@
+"""TS2-GauSum time splitting in rotating Lagrangian coordinates, float64.
+
+Oracle (test infrastructure only).  Follows Section 4.2 of the paper:
+
+* The rotating Lagrangian coordinates x = A(t) x~ (eqs. Amatrix, transform)
+  remove the rotation term; the potential becomes W(x~, t) = V(A(t) x~)
+  (eq. FSE1_Rot).
+* Linear sub-step (eq. 1step): i phi_t = (1/2)(-Lap + m^2)^s phi, integrated
+  exactly in Fourier space on the periodic box: multiply the DFT coefficients
+  by exp(-i tau (|mu|^2 + m^2)^s / 2).
+* Nonlinear sub-step (eqs. 2stepA/B): the density is constant in time, so
+  the solution is phi * exp(-i[tau beta rho + lam * K~ * rho + P]) with
+  K~ = tau * U for a Coulomb kernel or a dipole along z (the rotating axis
+  m(t) = A^{-1} n equals n then), and P = int V(A(s) x~) ds (eq. int_poten).
+* TS2-GauSum (eqs. tssp1-tssp3): half linear step, full nonlinear step,
+  half linear step.
+
+Readings of the paper's text:
+* Grid: N points per axis, x_l = -L + l h, h = 2L/N (the periodic endpoint
+  of the paper's index set is dropped); frequencies mu_p = 2 pi p / (2L) in
+  the order p = 0..N/2-1, -N/2..-1, the Nyquist index kept as p = -N/2.
+* Half step: the paper's factor dt/4 is half a step of (1/2)(-Lap+m^2)^s, so
+  a linear step of length tau multiplies by exp(-i tau omega / 2).
+* Density of the nonlinear step: rho = |phi^(1)|^2, the state entering the
+  nonlinear sub-step (the sub-problem conserves that density; reading the
+  displayed |phi^n|^2 literally would make the scheme first order).
+* Exact solution of the nonlinear sub-step: phi(t) = phi(t_n) * exp(...) (the
+  displayed formula drops the factor phi(t_n)).
+* P for the harmonic trap (derived here, theta = Omega t):
+      V(A x~) = ((gx^2+gy^2)/4)(x~^2+y~^2) + (gz^2/2) z~^2
+                + ((gx^2-gy^2)/4)[(x~^2-y~^2) cos 2theta + 2 x~ y~ sin 2theta]
+  integrated over [t, t+tau]:
+      int cos(2 Omega s) ds = cos(Omega(2t+tau)) sin(Omega tau)/Omega,
+      int sin(2 Omega s) ds = sin(Omega(2t+tau)) sin(Omega tau)/Omega.
+
+Parity: pinned by the exact free-evolution identity, the s = 1 free Gaussian
+closed form, quadrature of P, unitarity (mass), reversibility, second-order
+convergence, the s = 1 centre-of-mass ODE and conservation of <Lz>
+(tests/oracle).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import gausum
+
+
+def axes(N, L):
+    return [-float(Lj) + np.arange(int(Nj)) * (2.0 * float(Lj) / int(Nj)) for Nj, Lj in zip(N, L)]
+
+
+def freqs(N, L):
+    """mu_{j,p} = 2 pi p / (2 L_j) in DFT order."""
+    return [2.0 * math.pi * np.fft.fftfreq(int(Nj), d=2.0 * float(Lj) / int(Nj)) for Nj, Lj in zip(N, L)]
+
+
+def _bcast(v, j, d):
+    shape = [1] * d
+    shape[j] = -1
+    return v.reshape(shape)
+
+
+def kinetic_symbol(N, L, s, m=0.0):
+    """omega(mu) = (|mu|^2 + m^2)^s on the DFT grid."""
+    d = len(N)
+    mu = freqs(N, L)
+    k2 = np.zeros(tuple(int(n) for n in N))
+    for j in range(d):
+        k2 = k2 + _bcast(mu[j], j, d) ** 2
+    return (k2 + m * m) ** s
+
+
+def kinetic(psi, N, L, s, tau, m=0.0):
+    """Linear sub-step over time tau (eq. 1step, exact in Fourier space)."""
+    om = kinetic_symbol(N, L, s, m)
+    return np.fft.ifftn(np.exp(-1j * tau * 0.5 * om) * np.fft.fftn(psi))
+
+
+def trap(N, L, gamma, Omega, t):
+    """W(x~, t) = V(A(t) x~) on the grid (rotating frame, eq. FSE1_Rot)."""
+    d = len(N)
+    X = np.meshgrid(*axes(N, L), indexing="ij")
+    th = Omega * t
+    c, s_ = math.cos(th), math.sin(th)
+    x = c * X[0] + s_ * X[1]
+    y = -s_ * X[0] + c * X[1]
+    V = 0.5 * (gamma[0] ** 2 * x ** 2 + gamma[1] ** 2 * y ** 2)
+    if d == 3:
+        V = V + 0.5 * gamma[2] ** 2 * X[2] ** 2
+    return V
+
+
+def trap_integral(N, L, gamma, Omega, t, tau):
+    """P(x~; t, t+tau) = int_t^{t+tau} V(A(s) x~) ds, closed form (eq. int_poten)."""
+    d = len(N)
+    X = np.meshgrid(*axes(N, L), indexing="ij")
+    gx2, gy2 = gamma[0] ** 2, gamma[1] ** 2
+    if Omega == 0.0:
+        sc_int = math.cos(0.0) * tau
+        ss_int = 0.0
+    else:
+        f = math.sin(Omega * tau) / Omega
+        sc_int = math.cos(Omega * (2.0 * t + tau)) * f
+        ss_int = math.sin(Omega * (2.0 * t + tau)) * f
+    P = tau * (gx2 + gy2) / 4.0 * (X[0] ** 2 + X[1] ** 2)
+    P = P + (gx2 - gy2) / 4.0 * ((X[0] ** 2 - X[1] ** 2) * sc_int + 2.0 * X[0] * X[1] * ss_int)
+    if d == 3:
+        P = P + tau * 0.5 * gamma[2] ** 2 * X[2] ** 2
+    return P
+
+
+class Problem:
+    """Parameters of one instance plus its GauSum multiplier (built once)."""
+
+    def __init__(self, d, N, L, s, Omega, gamma, beta, lam, kernel="coulomb", mu=1.0, c=1.0,
+                 m=0.0, delta=None):
+        self.d, self.N, self.L = int(d), tuple(int(n) for n in N), tuple(float(x) for x in L)
+        self.s, self.Omega, self.gamma = float(s), float(Omega), tuple(float(g) for g in gamma)
+        self.beta, self.lam, self.kernel = float(beta), float(lam), kernel
+        self.mu, self.c, self.m = float(mu), float(c), float(m)
+        self.delta = delta
+        self._K = None
+
+    @classmethod
+    def from_params(cls, p):
+        return cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kernel=p.kernel,
+                   mu=p.mu, c=p.c, m=p.m)
+
+    @property
+    def h(self):
+        return tuple(2.0 * L / N for L, N in zip(self.L, self.N))
+
+    @property
+    def K(self):
+        if self._K is None and self.kernel != "none" and self.lam != 0.0:
+            self._K = gausum.symbol(self.N, self.L, self.kernel, mu=self.mu, c=self.c,
+                                    delta=self.delta)
+        return self._K
+
+    def potential(self, rho):
+        """Untimed nonlocal potential Phi[rho] = U * rho (zero if there is no kernel)."""
+        if self.kernel == "none" or self.lam == 0.0:
+            return np.zeros(self.N)
+        return gausum.convolve(rho, self.K)
+
+    def nonlinear(self, phi, t, tau):
+        """Nonlinear sub-step over [t, t+tau] (eqs. 2stepA, 2stepB, solu_step2)."""
+        rho = np.abs(phi) ** 2
+        theta = tau * self.beta * rho + self.lam * tau * self.potential(rho)
+        theta = theta + trap_integral(self.N, self.L, self.gamma, self.Omega, t, tau)
+        return phi * np.exp(-1j * theta)
+
+    def step(self, psi, t, dt):
+        """One TS2-GauSum step (eqs. tssp1-tssp3); returns (psi, t + dt)."""
+        p1 = kinetic(psi, self.N, self.L, self.s, 0.5 * dt, self.m)
+        p2 = self.nonlinear(p1, t, dt)
+        p3 = kinetic(p2, self.N, self.L, self.s, 0.5 * dt, self.m)
+        return p3, t + dt
+
+    def run(self, psi, nsteps, dt, t=0.0):
+        for _ in range(int(nsteps)):
+            psi, t = self.step(psi, t, dt)
+        return psi, t
