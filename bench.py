@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""Benchmark of the TS2-GauSum split step on one MI355X.
+
+Default workload: the 3D 256^3 split step (grid [-12,12]^3, s = 0.8,
+Omega = 0.7, gamma = (1,1,2), beta = 200, lambda = 50, dipole along z via
+GauSum on 512^3 padding, dt = 5e-4), complex128, synthetic seeded Gaussian
+initial state resident in HBM before the timed region.  One step = one pass
+of the whole hot path (linear half steps merged across steps, GauSum
+potential, nonlinear phase).  The timed region is one fse_step call of K
+steps after W warm-up steps.
+
+Prints one JSON line: the headline value is complex128 grid-point-steps/s;
+the complex64 path is reported under "variants"; per-pass average durations
+(HIP events on the launch stream) give the roofline of the dominant kernel;
+the FP64 CPU oracle, timed on a bounded sample, is "cpu_baseline".
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "grid-point-steps/s and % HBM roofline, 3D 256³ split step, FP32-batched vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def pass_bytes(p, csize):
+    """Algorithmic HBM bytes per launch of each pass kind (compulsory reads + writes)."""
+    rsize = csize // 2
+    n = p.npts
+    if p.d == 3:
+        N0, N1, N2 = p.N
+        X1 = (N0 + 1) * N1 * N2
+        X2 = (N0 + 1) * 2 * N1 * N2
+        K = (N0 + 1) * (N1 + 1) * (N2 + 1)
+        kin = (N0 // 2 + 1) * (N1 // 2 + 1) * (N2 // 2 + 1)
+        return {
+            "r2c": (n + X1) * csize,
+            "pad_fwd": (X1 + X2) * csize,
+            "conv": 2 * X2 * csize + K * rsize,
+            "crop_inv": (X2 + X1) * csize,
+            "c2r_phase": (X1 + 2 * n) * csize,
+            "f1": 2 * n * csize,
+            "kin": 2 * n * csize + kin * csize,
+            "i1": 2 * n * csize,
+            "edge": 2 * n * csize,
+        }
+    N0, N1 = p.N
+    X1 = (N0 + 1) * N1
+    K = (N0 + 1) * (N1 + 1)
+    kin = (N0 // 2 + 1) * (N1 // 2 + 1)
+    return {
+        "r2c": (n + X1) * csize,
+        "conv": 2 * X1 * csize + K * rsize,
+        "c2r_phase": (X1 + 2 * n) * csize,
+        "kin": 2 * n * csize + kin * csize,
+        "edge": 2 * n * csize,
+    }
+
+
+def run_precision(p, prec, steps, warmup, prof_steps):
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    psi0 = W.initial_state(p, seed=0)
+    dtype = np.complex128 if prec == fse.C128 else np.complex64
+    csize = 16 if prec == fse.C128 else 8
+    plan = fse.Plan.from_params(p, prec)
+    x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
+    del psi0
+    if warmup > 0:
+        plan.step(x, warmup, p.dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    plan.step(x, steps, p.dt)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    mass = plan.mass(x).item()
+    # per-pass durations: HIP events around every launch, on the launch stream
+    plan.set_profiling(True)
+    plan.step(x, prof_steps, p.dt)
+    torch.cuda.synchronize()
+    prof = plan.profile()
+    plan.set_profiling(False)
+    by = pass_bytes(p, csize)
+    passes = {}
+    for name, (ms, cnt) in prof.items():
+        avg = ms / cnt
+        passes[name] = {
+            "launches": cnt,
+            "avg_ms": round(avg, 5),
+            "bytes_per_launch": by[name],
+            "gbs": round(by[name] / (avg * 1e-3) / 1e9, 1),
+            "share": None,
+        }
+    tot = sum(v["avg_ms"] * v["launches"] for k, v in passes.items() if k != "edge")
+    for k, v in passes.items():
+        if k != "edge":
+            v["share"] = round(v["avg_ms"] * v["launches"] / tot, 4)
+    step_bytes = sum(v for k, v in by.items() if k != "edge")
+    t_step = ev_ms * 1e-3 / steps
+    del x, plan
+    torch.cuda.empty_cache()
+    return {
+        "value": p.npts * steps / (ev_ms * 1e-3),
+        "ms_per_step": ev_ms / steps,
+        "wall_s": wall,
+        "mass_after": mass,
+        "model_bytes_per_point": step_bytes / p.npts,
+        "step_hbm_gbs": step_bytes / t_step / 1e9,
+        "step_hbm_frac": step_bytes / t_step / 1e9 / HBM_PEAK_GBS,
+        "passes": passes,
+    }
+
+
+def cpu_baseline(p, nsteps=1):
+    """The FP64 oracle on a bounded sample: nsteps steps of the same workload."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import scheme
+
+    psi = W.initial_state(p, seed=0)
+    pr = scheme.Problem.from_params(p)
+    # The multiplier's values do not change the cost of a step; building the
+    # oracle's own multiplier is plan-time work that takes minutes at 512^3.
+    pr._K = np.ones(tuple(2 * n for n in p.N))
+    t0 = time.perf_counter()
+    t = 0.0
+    for _ in range(nsteps):
+        psi, t = pr.step(psi, t, p.dt)
+    sec = time.perf_counter() - t0
+    return {
+        "value": p.npts * nsteps / sec,
+        "unit": "grid-point-steps/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{nsteps} step(s) of the {p.N[0]}^3 workload by oracle.scheme.Problem.step "
+                   f"(numpy float64, single thread), {sec:.1f} s; GauSum multiplier replaced by a "
+                   f"same-shape array (plan-time work excluded)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="m0", choices=["m0", "cfg2", "cfg1"])
+    ap.add_argument("--prof-steps", type=int, default=20)
+    ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: the split step of one grid is not sharded here "
+              f"(--gpus {args.gpus} requested)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    p = W.preset(args.workload)
+    print(f"[bench] {p.name} N={p.N} c128: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
+          flush=True)
+    r64 = run_precision(p, fse.C128, args.steps, args.warmup, args.prof_steps)
+    print(f"[bench] c128 {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    variants = {}
+    if not args.no_c64:
+        r32 = run_precision(p, fse.C64, args.steps, args.warmup, args.prof_steps)
+        print(f"[bench] c64 {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        variants["c64"] = {
+            "value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "c64 (FP64 reductions)",
+            "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
+            "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"],
+        }
+    dom = max((k for k in r64["passes"] if k != "edge"),
+              key=lambda k: r64["passes"][k]["avg_ms"] * r64["passes"][k]["launches"])
+    dp = r64["passes"][dom]
+    roof = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": dp["gbs"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(dp["gbs"] / HBM_PEAK_GBS, 4),
+        "traffic": None,
+        "bytes_per_launch": dp["bytes_per_launch"],
+        "avg_ms": dp["avg_ms"],
+    }
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(p)
+    out = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "grid-point-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{p.name}: {'x'.join(map(str, p.N))} grid on [-{p.L[0]:g},{p.L[0]:g}]^{p.d}, "
+                         f"s={p.s}, Omega={p.Omega}, gamma={p.gamma}, beta={p.beta}, lambda={p.lam}, "
+                         f"kernel={p.kernel} GauSum on {'x'.join(str(2 * n) for n in p.N)} padding, dt={p.dt}"),
+            "grid": list(p.N),
+            "precision": "complex128",
+        },
+        "step_hbm_frac": r64["step_hbm_frac"],
+        "model_bytes_per_point": r64["model_bytes_per_point"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "passes": r64["passes"],
+        "mass_after": r64["mass_after"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

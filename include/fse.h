@@ -1,0 +1,175 @@
+/*
+ * fse.h -- C ABI of the MI355X split-step library for the rotating
+ * space-fractional nonlinear Schroedinger / Gross-Pitaevskii equation with a
+ * GauSum nonlocal potential.
+ *
+ * Method (Antoine, Tang, Zhang, arXiv:1512.03210):
+ *   i psi_t = [ (1/2)(-Lap + m^2)^s + V + beta|psi|^2 + lambda Phi - Omega Lz ] psi,
+ *   Phi = U * |psi|^2                                   (eqs. SFSE, NonLocalPot)
+ * solved in rotating Lagrangian coordinates x = A(t) x~ (eqs. Amatrix,
+ * transform, FSE1_Rot) by the TS2-GauSum time splitting (eqs. tssp1-tssp3):
+ * half a linear step, exact in Fourier space; a full nonlinear step whose
+ * density is constant, with the nonlocal potential from the Gaussian-sum
+ * method of Section 2; half a linear step.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Grid.   d = 2 or 3 axes; axis 0 is the slowest (x~), axis d-1 the
+ *         contiguous one.  N[j] points on [-L[j], L[j]), x_l = -L + l h,
+ *         h = 2L/N (the periodic endpoint is not stored).  Each N[j] is even,
+ *         16 <= N[j] <= 512, and has no prime factor other than 2 and 3.
+ * Arrays. psi: C-contiguous [N0][N1]([N2]) interleaved complex, complex128
+ *         (FSE_C128) or complex64 (FSE_C64) per the plan's precision; real
+ *         arrays (rho, Phi) are double or float in the same layout.  All
+ *         array arguments are DEVICE pointers owned by the caller; the
+ *         library never frees them.  Scalar outputs are double, written to
+ *         DEVICE memory (read them after synchronising the stream).
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *         Calls are asynchronous on that stream; only fse_plan_create and
+ *         fse_plan_destroy synchronise.  A plan must not be used from two
+ *         host threads at once.
+ * Time.   The plan keeps the time t of the state (host side, FP64); the
+ *         rotating-frame trap W(x~,t) = V(A(t) x~) depends on it.
+ *         fse_step advances it by nsteps*dt.
+ * Errors. Every call returns an fse_status; nothing is thrown across the ABI.
+ *         fse_last_error() returns a message for the calling thread's last
+ *         failure.
+ */
+#ifndef FSE_H
+#define FSE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fse_plan_s* fse_plan; /* opaque; owned by the library */
+
+typedef enum {
+    FSE_OK = 0,
+    FSE_ERR_ARG = -1,          /* invalid argument (dimension, size, parameter) */
+    FSE_ERR_UNSUPPORTED = -2,  /* valid physics the library does not implement */
+    FSE_ERR_NOMEM = -3,        /* device or host allocation failed */
+    FSE_ERR_HIP = -4,          /* a HIP runtime call failed */
+    FSE_ERR_NUMERIC = -5,      /* non-finite parameter or result */
+    FSE_ERR_STATE = -6         /* call not valid in the plan's current state */
+} fse_status;
+
+typedef enum { FSE_C128 = 0, FSE_C64 = 1 } fse_precision;
+
+/* Nonlocal kernel U (eq. Kernel):
+ *   FSE_K_NONE    -- no nonlocal term (lambda is ignored);
+ *   FSE_K_COULOMB -- U = prefactor / |x|^mu, 0 < mu <= d-1; the paper's
+ *                    Coulomb-type kernel has prefactor 1/(2^{d-1} pi);
+ *   FSE_K_DDI3    -- d = 3 dipole-dipole kernel -delta - 3 d_nn (1/(4 pi |x|))
+ *                    with dipole axis n; only n = (0,0,1) is implemented. */
+typedef enum { FSE_K_NONE = 0, FSE_K_COULOMB = 1, FSE_K_DDI3 = 2 } fse_kernel_kind;
+
+typedef struct {
+    int kind;          /* fse_kernel_kind */
+    double mu;         /* Coulomb exponent (ignored for DDI3) */
+    double prefactor;  /* c in U = c/|x|^mu (ignored for DDI3, which uses 1/(4 pi)) */
+    double n[3];       /* dipole axis for DDI3 */
+    double delta;      /* near-field radius of the GauSum split; <= 0 selects 1e-4 * max L */
+    double ht;         /* sinc-quadrature step of the Gaussian sum; <= 0 selects 0.14 */
+} fse_kernel;
+
+/* Host-only validation of a problem description; no device work.
+ * Returns FSE_OK, FSE_ERR_ARG or FSE_ERR_UNSUPPORTED (message in fse_last_error). */
+fse_status fse_plan_check(int d, const int* N, const double* L, double s, double Omega,
+                          const double* gamma, double beta, double lambda,
+                          const fse_kernel* kernel, int precision);
+
+/* Build a plan for one grid and parameter set (eqs. SFSE, NonLocalPot, harm_poten).
+ * gamma[d] are the trap frequencies of V = sum_v gamma_v^2 v^2 / 2; m >= 0 is
+ * the mass term of (-Lap + m^2)^s.  Precomputes on the host, in FP64, the
+ * GauSum multiplier (Section 2: the Gaussian sum eq. GS-Gene, the tensor
+ * eq. tensor, the near-field correction eq. taylor) and the FFT twiddles,
+ * and allocates the device workspace.  Synchronises `stream`.
+ * The plan's time starts at 0. */
+fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, double s,
+                           double Omega, const double* gamma, double beta, double lambda,
+                           const fse_kernel* kernel, int precision, double m, void* stream);
+
+fse_status fse_plan_destroy(fse_plan plan);
+
+/* Device bytes held by the plan (multiplier, twiddles, workspace). */
+fse_status fse_workspace_size(fse_plan plan, size_t* bytes);
+
+fse_status fse_set_time(fse_plan plan, double t);
+fse_status fse_get_time(fse_plan plan, double* t);
+
+/* nsteps TS2-GauSum steps of size dt (eqs. tssp1-tssp3), in place on psi
+ * (rotating Lagrangian coordinates).  Adjacent half linear steps of
+ * consecutive steps are merged into one full step, which is exact algebra.
+ * dt may be negative (backward in time); nsteps >= 0.  t += nsteps*dt. */
+fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
+
+/* H psi in the lab frame (the operator of eq. SFSE; with a frozen density it
+ * is the operator A^{BE,n} of Section 3.2 without its I/dt part):
+ *   H psi = (1/2)(-Lap+m^2)^s psi + (V + beta rho + lambda Phi[rho]) psi - Omega Lz psi,
+ * rho = |psi|^2, or rho_frozen (real array) when it is not NULL.
+ * psi and Hpsi must not alias. */
+fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* rho_frozen,
+                       void* stream);
+
+/* Phi = U * |psi|^2 on the grid (Section 2; eq. NonLocalPot), written as a
+ * real array.  Zero when the plan has no kernel. */
+fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, void* stream);
+
+/* Mass h^d sum |psi|^2 (eq. mass) -> out_dev[0]. */
+fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* stream);
+
+/* Energy parts (eq. energy), in rotating coordinates at the plan's time with
+ * W(x~,t) = V(A(t)x~):
+ * out_dev[0..5] = E_kin, E_pot, E_int, E_non, E_rot = -Omega <Lz>, E_total.
+ * Sums are accumulated in FP64 for both precisions. */
+fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* stream);
+
+/* <Lz> = h^d sum psi^* (-i)(x D_y - y D_x) psi (eq. AME) -> out_dev[0]. */
+fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev, void* stream);
+
+/* Host-only: the GauSum multiplier Khat (before any FFT normalisation) on the
+ * non-negative frequency octant, out[(k0*(N1+1)+k1)*(N2+1)+k2] for d = 3
+ * (out[k0*(N1+1)+k1] for d = 2), kappa_j = pi k_j / (2 L_j), k_j = 0..N_j.
+ * The caller owns `out` (host memory, prod(N_j+1) doubles).  This is the
+ * table the plan uploads; it needs no GPU. */
+fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fse_kernel* kernel,
+                                  double* out);
+
+/* Copies the plan's multiplier (as fse_gausum_symbol_host lays it out) to
+ * host memory.  FSE_ERR_STATE if the plan has no kernel. */
+fse_status fse_get_symbol(fse_plan plan, double* host_out);
+
+/* Per-pass timing for benchmarking.  While enabled, fse_step records a HIP
+ * event pair on its stream around every kernel launch.  fse_get_profile
+ * synchronises those events, adds the elapsed milliseconds per pass kind
+ * into ms[k] and the launch counts into count[k] for k < npass (kinds:
+ * FSE_PASS_*), and clears the record. */
+enum {
+    FSE_PASS_EDGE = 0,      /* entry/exit passes of a call */
+    FSE_PASS_R2C = 1,       /* axis-0 inverse, density, padded real-to-complex FFT */
+    FSE_PASS_PAD_FWD = 2,   /* 3D: padded forward FFT of axis 1 */
+    FSE_PASS_CONV = 3,      /* contiguous axis: padded FFT, GauSum multiplier, inverse */
+    FSE_PASS_CROP_INV = 4,  /* 3D: cropped inverse FFT of axis 1 */
+    FSE_PASS_C2R_PHASE = 5, /* axis-0 complex-to-real, nonlinear phase, forward FFT */
+    FSE_PASS_F1 = 6,        /* 3D: forward FFT of axis 1 */
+    FSE_PASS_KIN = 7,       /* contiguous axis: FFT, kinetic phase, inverse */
+    FSE_PASS_I1 = 8,        /* 3D: inverse FFT of axis 1 */
+    FSE_NPASS = 9
+};
+fse_status fse_set_profiling(fse_plan plan, int enable);
+fse_status fse_get_profile(fse_plan plan, double* ms, int* count, int npass);
+
+/* Message describing the calling thread's last error ("" if none). */
+const char* fse_last_error(void);
+
+/* Library version string. */
+const char* fse_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FSE_H */

@@ -1,0 +1,723 @@
+// C ABI of the split-step library: validation, plan set-up and the pass
+// schedules of fse_step, fse_nonlocal_potential, fse_apply_H and the
+// diagnostics.
+//
+// Pass schedule of fse_step (rotating Lagrangian coordinates, TS2-GauSum,
+// eqs. tssp1-tssp3, with adjacent half linear steps merged).  Between steps
+// the state S is psi with every axis in physical space except axis 0, whose
+// inverse FFT is still pending:
+//   entry:  F0, [F1], line(F_last * kin(dt/2) * I_last), [I1]          -> S
+//   step:   r2c      I0(S) -> psi -> rho -> padded R2C along axis 0 -> X1
+//           3D:  F1 padded (X1 -> X2), line conv (X2), I1 cropped (X2 -> X1)
+//           2D:  line conv (X1)
+//           c2r_phase  C2R along axis 0 -> Phi; I0(S) -> psi;
+//                      psi *= exp(-i[dt beta rho + lam dt Phi + P]); F0 -> S
+//           [F1], line(F_last * kin(dt, or dt/2 after the last step) * I_last), [I1]
+//   exit:   I0                                                     -> psi
+// ([..] = 3D only.)  The kinetic table carries 1/prod(N_j), the GauSum
+// multiplier 1/prod(2 N_j); every FFT is unnormalised.
+#include "../../include/fse.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fse_host.hpp"
+#include "fse_launch.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+fse_status fail(fse_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kRedBlocks = 1024;
+constexpr int kRedSlots = 8;
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(FSE_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+bool factors_23(int n) {
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+}  // namespace
+
+struct fse_plan_s {
+    int d = 0;
+    int N[3] = {1, 1, 1};
+    double L[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+    double s = 1, Omega = 0, gamma[3] = {0, 0, 0}, beta = 0, lambda = 0, m = 0;
+    fse_kernel kernel{};
+    int prec = FSE_C128;
+    bool nl = false;  // nonlocal term present
+    double t = 0.0;
+    long n = 0;       // grid points
+    int C0 = 0;       // columns of the axis-0 passes (n / N0)
+    size_t csize = 16, rsize = 8;
+    std::map<int, void*> tw;  // device twiddles exp(-2 pi i m/M), by M
+    void* khat = nullptr;
+    std::vector<double> khat_host;
+    void* X1 = nullptr;
+    void* X2 = nullptr;
+    void* kin[2] = {nullptr, nullptr};
+    double kin_tau[2] = {NAN, NAN};
+    void* diag = nullptr;  // 2 n complex + n real, allocated on first use
+    double* partials = nullptr;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+    // profiling: event pairs recorded around launches, by pass kind
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+
+    int last() const { return N[d - 1]; }
+    long lines_last() const { return n / N[d - 1]; }
+};
+
+namespace {
+
+fse_status dev_alloc(fse_plan p, void** ptr, size_t bytes) {
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e != hipSuccess) return fail(FSE_ERR_NOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+    p->allocs.push_back(*ptr);
+    p->bytes += bytes;
+    return FSE_OK;
+}
+
+fse_status check_args(int d, const int* N, const double* L, double s, double Omega, const double* gamma, double beta,
+                      double lambda, const fse_kernel* kernel, int precision) {
+    if (d != 2 && d != 3) return fail(FSE_ERR_ARG, "d must be 2 or 3 (got %d)", d);
+    if (!N || !L || !gamma) return fail(FSE_ERR_ARG, "N, L and gamma must not be NULL");
+    const int nmax = (d == 3) ? 256 : 512;
+    for (int j = 0; j < d; ++j) {
+        if (N[j] < 16 || N[j] > nmax || (N[j] % 2) != 0 || !factors_23(N[j]))
+            return fail(FSE_ERR_ARG, "N[%d] = %d: need an even size in [16, %d] with prime factors 2 and 3 only", j,
+                        N[j], nmax);
+        if (!fse::strided_size_ok(N[j]))
+            return fail(FSE_ERR_UNSUPPORTED, "N[%d] = %d has no compiled FFT length", j, N[j]);
+        if (!(L[j] > 0.0) || !std::isfinite(L[j])) return fail(FSE_ERR_ARG, "L[%d] must be finite and > 0", j);
+        if (!std::isfinite(gamma[j])) return fail(FSE_ERR_ARG, "gamma[%d] must be finite", j);
+    }
+    if (!(s > 0.0) || !std::isfinite(s)) return fail(FSE_ERR_ARG, "s must be finite and > 0");
+    if (!std::isfinite(Omega) || !std::isfinite(beta) || !std::isfinite(lambda))
+        return fail(FSE_ERR_ARG, "Omega, beta and lambda must be finite");
+    if (precision != FSE_C128 && precision != FSE_C64) return fail(FSE_ERR_ARG, "unknown precision %d", precision);
+    if (kernel) {
+        if (kernel->kind == FSE_K_COULOMB) {
+            if (!(kernel->mu > 0.0) || kernel->mu > d - 1 + 1e-15)
+                return fail(FSE_ERR_ARG, "Coulomb exponent mu must lie in (0, d-1]");
+            if (!std::isfinite(kernel->prefactor)) return fail(FSE_ERR_ARG, "kernel prefactor must be finite");
+        } else if (kernel->kind == FSE_K_DDI3) {
+            if (d != 3) return fail(FSE_ERR_ARG, "the 3D dipolar kernel needs d = 3");
+            const double nn = kernel->n[0] * kernel->n[0] + kernel->n[1] * kernel->n[1] + kernel->n[2] * kernel->n[2];
+            if (std::fabs(nn - 1.0) > 1e-12) return fail(FSE_ERR_ARG, "dipole axis must be a unit vector");
+            if (kernel->n[0] != 0.0 || kernel->n[1] != 0.0)
+                return fail(FSE_ERR_UNSUPPORTED, "only the dipole axis (0,0,1) is implemented");
+        } else if (kernel->kind != FSE_K_NONE) {
+            return fail(FSE_ERR_ARG, "unknown kernel kind %d", kernel->kind);
+        }
+        if (!std::isfinite(kernel->delta) || !std::isfinite(kernel->ht))
+            return fail(FSE_ERR_ARG, "kernel delta and ht must be finite");
+    }
+    if (kernel && kernel->kind != FSE_K_NONE) {
+        for (int j = 0; j < d; ++j)
+            if (!fse::line_size_ok(2 * N[j]))
+                return fail(FSE_ERR_UNSUPPORTED, "padded length %d has no compiled FFT length", 2 * N[j]);
+    }
+    return FSE_OK;
+}
+
+template <typename T> std::vector<T> twiddles(int M) {
+    std::vector<T> v(M);
+    for (int k = 0; k < M; ++k) {
+        const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)M;
+        v[k].x = (decltype(v[k].x))cosl(a);
+        v[k].y = (decltype(v[k].y))sinl(a);
+    }
+    return v;
+}
+
+fse_status upload_twiddles(fse_plan p, int M) {
+    if (p->tw.count(M)) return FSE_OK;
+    void* ptr = nullptr;
+    fse_status st = dev_alloc(p, &ptr, (size_t)M * p->csize);
+    if (st != FSE_OK) return st;
+    if (p->prec == FSE_C128) {
+        auto v = twiddles<double2>(M);
+        HIPCHK(hipMemcpy(ptr, v.data(), (size_t)M * sizeof(double2), hipMemcpyHostToDevice));
+    } else {
+        auto v = twiddles<float2>(M);
+        HIPCHK(hipMemcpy(ptr, v.data(), (size_t)M * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    p->tw[M] = ptr;
+    return FSE_OK;
+}
+
+// Record the start event of a launch of pass kind k (no-op unless profiling).
+fse_status prof_begin(fse_plan p, int k, hipStream_t st) {
+    if (!p->prof) return FSE_OK;
+    if (p->ev_used + 2 > p->ev.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            p->ev.push_back(e);
+        }
+        p->ev_kind.resize(p->ev.size() / 2);
+    }
+    p->ev_kind[p->ev_used / 2] = k;
+    HIPCHK(hipEventRecord(p->ev[p->ev_used], st));
+    return FSE_OK;
+}
+
+fse_status prof_end(fse_plan p, hipStream_t st) {
+    if (!p->prof) return FSE_OK;
+    HIPCHK(hipEventRecord(p->ev[p->ev_used + 1], st));
+    p->ev_used += 2;
+    return FSE_OK;
+}
+
+// Launch wrapped in profiling events.
+#define PLAUNCH(p, kind, st, expr)                     \
+    do {                                               \
+        fse_status ps_ = prof_begin((p), (kind), (st)); \
+        if (ps_ != FSE_OK) return ps_;                 \
+        HIPCHK(expr);                                  \
+        ps_ = prof_end((p), (st));                     \
+        if (ps_ != FSE_OK) return ps_;                 \
+    } while (0)
+
+fse::GridGeom geom(const fse_plan p) {
+    fse::GridGeom g;
+    g.d = p->d;
+    g.N0 = p->N[0];
+    g.N1 = p->N[1];
+    g.N2 = (p->d == 3) ? p->N[2] : 1;
+    g.x0 = -p->L[0];
+    g.hx = p->h[0];
+    g.y0 = -p->L[1];
+    g.hy = p->h[1];
+    g.z0 = (p->d == 3) ? -p->L[2] : 0.0;
+    g.hz = (p->d == 3) ? p->h[2] : 0.0;
+    return g;
+}
+
+double dmu(const fse_plan p, int j) { return (j < p->d) ? 2.0 * kPi / (2.0 * p->L[j]) : 0.0; }
+
+// Kinetic table for step length tau; slot 0 holds the half step, slot 1 the
+// full step, each rebuilt only when its tau changes.
+template <typename R> fse_status kin_table(fse_plan p, double tau, int slot, void** out, hipStream_t st) {
+    if (p->kin[slot] && p->kin_tau[slot] == tau) {
+        *out = p->kin[slot];
+        return FSE_OK;
+    }
+    const int T0 = p->N[0] / 2 + 1, T1 = (p->d == 3) ? p->N[1] / 2 + 1 : 1;
+    const int T2 = p->last() / 2 + 1;
+    const double dm1 = (p->d == 3) ? dmu(p, 1) : 0.0;
+    const double dm2 = dmu(p, p->d - 1);
+    if (!p->kin[slot]) {
+        fse_status s = dev_alloc(p, &p->kin[slot], (size_t)T0 * T1 * T2 * p->csize);
+        if (s != FSE_OK) return s;
+    }
+    HIPCHK(fse::Launch<R>::build_kin(p->kin[slot], T0, T1, T2, dmu(p, 0), dm1, dm2, p->s, p->m * p->m, tau,
+                                     1.0 / (double)p->n, st));
+    p->kin_tau[slot] = tau;
+    *out = p->kin[slot];
+    return FSE_OK;
+}
+
+fse::LineIdx kin_index(const fse_plan p) {
+    fse::LineIdx li;
+    if (p->d == 3) {
+        li.D1 = p->N[1];
+        li.F0 = p->N[0];
+        li.F1 = p->N[1];
+        li.T1 = p->N[1] / 2 + 1;
+        li.T2 = p->N[2] / 2 + 1;
+    } else {
+        li.D1 = 1;
+        li.F0 = p->N[0];
+        li.F1 = 0;
+        li.T1 = 1;
+        li.T2 = p->N[1] / 2 + 1;
+    }
+    return li;
+}
+
+fse::LineIdx conv_index(const fse_plan p) {
+    fse::LineIdx li;
+    if (p->d == 3) {
+        li.D1 = 2 * p->N[1];
+        li.F0 = 0;
+        li.F1 = 2 * p->N[1];
+        li.T1 = p->N[1] + 1;
+        li.T2 = p->N[2] + 1;
+    } else {
+        li.D1 = 1;
+        li.F0 = 0;
+        li.F1 = 0;
+        li.T1 = 1;
+        li.T2 = p->N[1] + 1;
+    }
+    return li;
+}
+
+fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
+    fse::PhaseArgs a;
+    a.x0 = -p->L[0];
+    a.hx = p->h[0];
+    a.y0 = -p->L[1];
+    a.hy = p->h[1];
+    a.z0 = (p->d == 3) ? -p->L[2] : 0.0;
+    a.hz = (p->d == 3) ? p->h[2] : 0.0;
+    a.N2 = (p->d == 3) ? p->N[2] : 0;
+    const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
+    const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
+    // int_{tn}^{tn+dt} cos/sin(2 Omega s) ds
+    const double f = (p->Omega == 0.0) ? dt : std::sin(p->Omega * dt) / p->Omega;
+    const double sc = (p->Omega == 0.0) ? dt : std::cos(p->Omega * (2.0 * tn + dt)) * f;
+    const double ss = (p->Omega == 0.0) ? 0.0 : std::sin(p->Omega * (2.0 * tn + dt)) * f;
+    a.ca = dt * (gx2 + gy2) / 4.0;
+    a.cz = dt * gz2 / 2.0;
+    a.cc = (gx2 - gy2) / 4.0 * sc;
+    a.cs = (gx2 - gy2) / 4.0 * ss;
+    a.bdt = p->beta * dt;
+    a.ldt = p->lambda * dt;
+    return a;
+}
+
+// Zero-padded GauSum convolution of the density held in X1 (after r2c), result back in X1.
+template <typename R> fse_status conv_passes(fse_plan p, hipStream_t st) {
+    using L = fse::Launch<R>;
+    if (p->d == 3) {
+        const int M1 = 2 * p->N[1], M2 = 2 * p->N[2];
+        HIPCHK(L::strided(M1, false, 1, p->X1, p->X2, p->N[0] + 1, p->N[2], p->tw[M1], st));
+        HIPCHK(L::line(M2, 0, p->X2, (p->N[0] + 1) * M1, p->khat, conv_index(p), p->tw[M2], st));
+        HIPCHK(L::strided(M1, true, 2, p->X2, p->X1, p->N[0] + 1, p->N[2], p->tw[M1], st));
+    } else {
+        const int M1 = 2 * p->N[1];
+        HIPCHK(L::line(M1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[M1], st));
+    }
+    return FSE_OK;
+}
+
+// Phi[rho] into a real array; src 1: rho = |psi|^2, 2: rho given.
+template <typename R> fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, hipStream_t st) {
+    using L = fse::Launch<R>;
+    if (!p->nl) {
+        HIPCHK(hipMemsetAsync(Phi, 0, (size_t)p->n * p->rsize, st));
+        return FSE_OK;
+    }
+    const int N0 = p->N[0];
+    HIPCHK(L::r2c(N0, srckind, src, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
+    fse_status s = conv_passes<R>(p, st);
+    if (s != FSE_OK) return s;
+    fse::PhaseArgs pa = phase_args(p, p->t, 0.0);
+    HIPCHK(L::c2r_phase(N0, 2, p->X1, nullptr, Phi, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+    return FSE_OK;
+}
+
+template <typename R> fse_status fft_forward(fse_plan p, void* a, hipStream_t st) {
+    using L = fse::Launch<R>;
+    HIPCHK(L::strided(p->N[0], false, 0, a, a, 1, p->C0, p->tw[p->N[0]], st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], st));
+    HIPCHK(L::line(p->last(), 2, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()], st));
+    return FSE_OK;
+}
+
+template <typename R> fse_status fft_inverse(fse_plan p, void* a, hipStream_t st) {
+    using L = fse::Launch<R>;
+    HIPCHK(L::line(p->last(), 3, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()], st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], st));
+    HIPCHK(L::strided(p->N[0], true, 0, a, a, 1, p->C0, p->tw[p->N[0]], st));
+    return FSE_OK;
+}
+
+fse_status ensure_diag(fse_plan p) {
+    if (p->diag) return FSE_OK;
+    return dev_alloc(p, &p->diag, (size_t)p->n * (2 * p->csize + p->rsize));
+}
+
+template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, hipStream_t st) {
+    using L = fse::Launch<R>;
+    void *kh = nullptr, *kf = nullptr;
+    fse_status s = kin_table<R>(p, 0.5 * dt, 0, &kh, st);
+    if (s != FSE_OK) return s;
+    if (nsteps > 1) {
+        s = kin_table<R>(p, dt, 1, &kf, st);
+        if (s != FSE_OK) return s;
+    }
+    const int N0 = p->N[0];
+    const int NL = p->last();
+    const int nlines = (int)p->lines_last();
+    const fse::LineIdx ki = kin_index(p);
+    const int N1 = p->N[1], N2 = (p->d == 3) ? p->N[2] : 1;
+    // entry: half linear step, leaving the axis-0 inverse pending
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], st));
+    if (p->d == 3) PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], st));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], st));
+    if (p->d == 3) PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], st));
+    for (int k = 0; k < nsteps; ++k) {
+        const double tn = p->t + k * dt;
+        const fse::PhaseArgs pa = phase_args(p, tn, dt);
+        if (p->nl) {
+            PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
+            if (p->d == 3) {
+                const int M1 = 2 * N1, M2 = 2 * N2;
+                PLAUNCH(p, FSE_PASS_PAD_FWD, st, L::strided(M1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[M1], st));
+                PLAUNCH(p, FSE_PASS_CONV, st,
+                        L::line(M2, 0, p->X2, (N0 + 1) * M1, p->khat, conv_index(p), p->tw[M2], st));
+                PLAUNCH(p, FSE_PASS_CROP_INV, st, L::strided(M1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[M1], st));
+            } else {
+                const int M1 = 2 * N1;
+                PLAUNCH(p, FSE_PASS_CONV, st, L::line(M1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[M1], st));
+            }
+            PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
+                    L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+        } else {
+            PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
+                    L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+        }
+        if (p->d == 3) PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], st));
+        PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, (k == nsteps - 1) ? kh : kf, ki, p->tw[NL], st));
+        if (p->d == 3) PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], st));
+    }
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], st));
+    p->t += nsteps * dt;
+    return FSE_OK;
+}
+
+// Energy / mass / Lz reductions; kind 0 mass, 1 energy, 2 Lz.
+template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int kind, double* out, hipStream_t st) {
+    using L = fse::Launch<R>;
+    const fse::GridGeom g = geom(p);
+    const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
+    if (kind == 0) {
+        HIPCHK(L::red_local(psi, nullptr, p->n, g, 0, 0, 0, 0, p->partials, 0, kRedBlocks, st));
+        HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, 1, 0, vol, (double)p->n, p->beta, p->lambda, p->Omega,
+                                     out, st));
+        return FSE_OK;
+    }
+    fse_status s = ensure_diag(p);
+    if (s != FSE_OK) return s;
+    char* base = static_cast<char*>(p->diag);
+    void* A = base;
+    void* B = base + (size_t)p->n * p->csize;
+    void* Phi = base + (size_t)p->n * 2 * p->csize;
+    int nslot = 7;
+    if (kind == 1) {
+        const bool use_phi = p->nl;
+        if (use_phi) {
+            s = potential_impl<R>(p, psi, 1, Phi, st);
+            if (s != FSE_OK) return s;
+        }
+        const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
+        const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
+        const double th = 2.0 * p->Omega * p->t;
+        HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
+                            (gx2 - gy2) / 4.0 * std::cos(th), (gx2 - gy2) / 4.0 * std::sin(th), p->partials, 0,
+                            kRedBlocks, st));
+    } else {
+        // slots 0..4 unused for Lz; keep them defined
+        HIPCHK(hipMemsetAsync(p->partials, 0, sizeof(double) * kRedBlocks * 5, st));
+    }
+    HIPCHK(hipMemcpyAsync(A, psi, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
+    s = fft_forward<R>(p, A, st);
+    if (s != FSE_OK) return s;
+    if (kind == 1)
+        HIPCHK(L::red_kin(A, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, p->partials, 4, kRedBlocks,
+                          st));
+    // D_y psi against x, D_x psi against y
+    for (int pass = 0; pass < 2; ++pass) {
+        const int axis = (pass == 0) ? 1 : 0;
+        HIPCHK(L::fourier_mult(A, B, p->n, g, 0, axis, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
+                               1.0 / (double)p->n, st));
+        s = fft_inverse<R>(p, B, st);
+        if (s != FSE_OK) return s;
+        HIPCHK(L::red_lz(psi, B, p->n, g, pass == 0 ? 0 : 1, p->partials, 5 + pass, kRedBlocks, st));
+    }
+    HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, nslot, kind, vol, (double)p->n, p->beta, p->lambda, p->Omega,
+                                 out, st));
+    return FSE_OK;
+}
+
+template <typename R>
+fse_status apply_H_impl(fse_plan p, const void* psi, void* H, const void* rho, hipStream_t st) {
+    using L = fse::Launch<R>;
+    fse_status s = ensure_diag(p);
+    if (s != FSE_OK) return s;
+    const fse::GridGeom g = geom(p);
+    char* base = static_cast<char*>(p->diag);
+    void* A = base;
+    void* B = base + (size_t)p->n * p->csize;
+    void* Phi = base + (size_t)p->n * 2 * p->csize;
+    if (p->nl) {
+        s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, st);
+        if (s != FSE_OK) return s;
+    }
+    HIPCHK(hipMemcpyAsync(A, psi, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
+    s = fft_forward<R>(p, A, st);
+    if (s != FSE_OK) return s;
+    HIPCHK(L::fourier_mult(A, H, p->n, g, 1, 0, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
+                           1.0 / (double)p->n, st));
+    s = fft_inverse<R>(p, H, st);
+    if (s != FSE_OK) return s;
+    if (p->Omega != 0.0) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const int axis = (pass == 0) ? 1 : 0;
+            HIPCHK(L::fourier_mult(A, B, p->n, g, 0, axis, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
+                                   1.0 / (double)p->n, st));
+            s = fft_inverse<R>(p, B, st);
+            if (s != FSE_OK) return s;
+            HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, pass, p->Omega, 0, 0, 0, 0, 0, st));
+        }
+    }
+    HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, p->n, g, 2, p->Omega, p->beta, p->lambda,
+                      p->gamma[0], p->gamma[1], (p->d == 3) ? p->gamma[2] : 0.0, st));
+    return FSE_OK;
+}
+
+void destroy(fse_plan p) {
+    if (!p) return;
+    for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    for (void* a : p->allocs) (void)hipFree(a);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fse_last_error(void) { return g_err.c_str(); }
+
+const char* fse_version(void) { return "fse-mi355x 0.1 (gfx950)"; }
+
+fse_status fse_plan_check(int d, const int* N, const double* L, double s, double Omega, const double* gamma,
+                          double beta, double lambda, const fse_kernel* kernel, int precision) {
+    g_err.clear();
+    return check_args(d, N, L, s, Omega, gamma, beta, lambda, kernel, precision);
+}
+
+fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fse_kernel* kernel, double* out) {
+    g_err.clear();
+    if (!kernel || !out) return fail(FSE_ERR_ARG, "kernel and out must not be NULL");
+    if (kernel->kind == FSE_K_NONE) return fail(FSE_ERR_ARG, "no kernel");
+    const double gam[3] = {0, 0, 0};
+    fse_status st = check_args(d, N, L, 1.0, 0.0, gam, 0.0, 1.0, kernel, FSE_C128);
+    if (st != FSE_OK) return st;
+    std::vector<double> k = fse::gausum_symbol(d, N, L, kernel->kind, kernel->mu, kernel->prefactor, kernel->delta,
+                                               kernel->ht);
+    std::memcpy(out, k.data(), k.size() * sizeof(double));
+    return FSE_OK;
+}
+
+fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, double s, double Omega,
+                           const double* gamma, double beta, double lambda, const fse_kernel* kernel, int precision,
+                           double m, void* stream) {
+    g_err.clear();
+    if (!out) return fail(FSE_ERR_ARG, "out must not be NULL");
+    *out = nullptr;
+    fse_status st = check_args(d, N, L, s, Omega, gamma, beta, lambda, kernel, precision);
+    if (st != FSE_OK) return st;
+    if (!(m >= 0.0) || !std::isfinite(m)) return fail(FSE_ERR_ARG, "m must be finite and >= 0");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FSE_ERR_HIP, "no HIP device available");
+    fse_plan p = new fse_plan_s();
+    p->d = d;
+    p->n = 1;
+    for (int j = 0; j < d; ++j) {
+        p->N[j] = N[j];
+        p->L[j] = L[j];
+        p->h[j] = 2.0 * L[j] / N[j];
+        p->gamma[j] = gamma[j];
+        p->n *= N[j];
+    }
+    p->s = s;
+    p->Omega = Omega;
+    p->beta = beta;
+    p->lambda = lambda;
+    p->m = m;
+    p->prec = precision;
+    p->csize = (precision == FSE_C128) ? 16 : 8;
+    p->rsize = p->csize / 2;
+    if (kernel) p->kernel = *kernel;
+    else p->kernel.kind = FSE_K_NONE;
+    p->nl = (p->kernel.kind != FSE_K_NONE) && (lambda != 0.0);
+    p->C0 = (int)(p->n / N[0]);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    auto bail = [&](fse_status e) {
+        destroy(p);
+        return e;
+    };
+    // twiddles: N_j for every axis, 2 N0 (real-to-complex), 2 N_j for the padded axes
+    for (int j = 0; j < d; ++j) {
+        if ((st = upload_twiddles(p, N[j])) != FSE_OK) return bail(st);
+    }
+    if ((st = upload_twiddles(p, 2 * N[0])) != FSE_OK) return bail(st);
+    if (p->nl) {
+        for (int j = 1; j < d; ++j)
+            if ((st = upload_twiddles(p, 2 * N[j])) != FSE_OK) return bail(st);
+        p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor, p->kernel.delta,
+                                          p->kernel.ht);
+        double scale = 1.0;
+        for (int j = 0; j < d; ++j) scale /= (2.0 * N[j]);
+        const size_t nk = p->khat_host.size();
+        if ((st = dev_alloc(p, &p->khat, nk * p->rsize)) != FSE_OK) return bail(st);
+        if (precision == FSE_C128) {
+            std::vector<double> v(nk);
+            for (size_t i = 0; i < nk; ++i) v[i] = p->khat_host[i] * scale;
+            if (hipMemcpy(p->khat, v.data(), nk * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(FSE_ERR_HIP, "copy of the GauSum multiplier failed"));
+        } else {
+            std::vector<float> v(nk);
+            for (size_t i = 0; i < nk; ++i) v[i] = (float)(p->khat_host[i] * scale);
+            if (hipMemcpy(p->khat, v.data(), nk * sizeof(float), hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(FSE_ERR_HIP, "copy of the GauSum multiplier failed"));
+        }
+        const size_t x1 = (size_t)(N[0] + 1) * p->C0;
+        if ((st = dev_alloc(p, &p->X1, x1 * p->csize)) != FSE_OK) return bail(st);
+        if (d == 3) {
+            const size_t x2 = (size_t)(N[0] + 1) * 2 * N[1] * N[2];
+            if ((st = dev_alloc(p, &p->X2, x2 * p->csize)) != FSE_OK) return bail(st);
+        }
+    }
+    if ((st = dev_alloc(p, (void**)&p->partials, sizeof(double) * kRedBlocks * kRedSlots)) != FSE_OK) return bail(st);
+    if (hipStreamSynchronize(hs) != hipSuccess) return bail(fail(FSE_ERR_HIP, "stream synchronisation failed"));
+    *out = p;
+    return FSE_OK;
+}
+
+fse_status fse_plan_destroy(fse_plan plan) {
+    g_err.clear();
+    if (!plan) return FSE_OK;
+    (void)hipDeviceSynchronize();
+    destroy(plan);
+    return FSE_OK;
+}
+
+fse_status fse_workspace_size(fse_plan plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(FSE_ERR_ARG, "plan and bytes must not be NULL");
+    *bytes = plan->bytes;
+    return FSE_OK;
+}
+
+fse_status fse_set_time(fse_plan plan, double t) {
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    if (!std::isfinite(t)) return fail(FSE_ERR_ARG, "t must be finite");
+    plan->t = t;
+    return FSE_OK;
+}
+
+fse_status fse_get_time(fse_plan plan, double* t) {
+    if (!plan || !t) return fail(FSE_ERR_ARG, "plan and t must not be NULL");
+    *t = plan->t;
+    return FSE_OK;
+}
+
+fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream) {
+    g_err.clear();
+    if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
+    if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
+    if (nsteps == 0) return FSE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, st)
+                                  : step_impl<float>(plan, psi, nsteps, dt, st);
+}
+
+fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* rho_frozen, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !Hpsi) return fail(FSE_ERR_ARG, "plan, psi and Hpsi must not be NULL");
+    if (psi == Hpsi) return fail(FSE_ERR_ARG, "psi and Hpsi must not alias");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? apply_H_impl<double>(plan, psi, Hpsi, rho_frozen, st)
+                                  : apply_H_impl<float>(plan, psi, Hpsi, rho_frozen, st);
+}
+
+fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !Phi) return fail(FSE_ERR_ARG, "plan, psi and Phi must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? potential_impl<double>(plan, psi, 1, Phi, st)
+                                  : potential_impl<float>(plan, psi, 1, Phi, st);
+}
+
+fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 0, out_dev, st)
+                                  : reduce_impl<float>(plan, psi, 0, out_dev, st);
+}
+
+fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 1, out_dev, st)
+                                  : reduce_impl<float>(plan, psi, 1, out_dev, st);
+}
+
+fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 2, out_dev, st)
+                                  : reduce_impl<float>(plan, psi, 2, out_dev, st);
+}
+
+fse_status fse_set_profiling(fse_plan plan, int enable) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    plan->prof = enable != 0;
+    plan->ev_used = 0;
+    return FSE_OK;
+}
+
+fse_status fse_get_profile(fse_plan plan, double* ms, int* count, int npass) {
+    g_err.clear();
+    if (!plan || !ms || !count || npass < 0) return fail(FSE_ERR_ARG, "invalid arguments");
+    for (size_t i = 0; i + 1 < plan->ev_used; i += 2) {
+        HIPCHK(hipEventSynchronize(plan->ev[i + 1]));
+        float t = 0.0f;
+        HIPCHK(hipEventElapsedTime(&t, plan->ev[i], plan->ev[i + 1]));
+        const int k = plan->ev_kind[i / 2];
+        if (k < npass) {
+            ms[k] += t;
+            count[k] += 1;
+        }
+    }
+    plan->ev_used = 0;
+    return FSE_OK;
+}
+
+fse_status fse_get_symbol(fse_plan plan, double* host_out) {
+    g_err.clear();
+    if (!plan || !host_out) return fail(FSE_ERR_ARG, "plan and host_out must not be NULL");
+    if (!plan->nl) return fail(FSE_ERR_STATE, "the plan has no nonlocal kernel");
+    std::memcpy(host_out, plan->khat_host.data(), plan->khat_host.size() * sizeof(double));
+    return FSE_OK;
+}
+
+}  // extern "C"

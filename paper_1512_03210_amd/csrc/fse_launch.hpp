@@ -1,0 +1,49 @@
+// Host-side launchers of the split-step kernels, one explicit instantiation
+// per precision (fse_launch_f64.hip, fse_launch_f32.hip).  Every launcher
+// maps a runtime FFT length onto the kernel template compiled for it and
+// returns the launch status.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fse_types.hpp"
+
+namespace fse {
+
+// Lengths compiled for the strided passes and the density/potential passes
+// of axis 0 (N), and for the contiguous line passes (N and 2N).
+bool strided_size_ok(int M);
+bool line_size_ok(int M);
+
+template <typename R> struct Launch {
+    // Strided FFT over [B0][rows][B2]; mode 0 plain, 1 padded forward (M/2 rows in), 2 cropped inverse.
+    static hipError_t strided(int M, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* tw,
+                              hipStream_t st);
+    // Contiguous line pass; mode 0 conv (lines of M/2, real multiplier), 1 kinetic (complex table), 2 fwd, 3 inv.
+    static hipError_t line(int M, int mode, void* data, int nlines, const void* mult, LineIdx li, const void* tw,
+                           hipStream_t st);
+    // Axis-0 density + padded real-to-complex FFT; src 0 pending state, 1 physical psi, 2 real density.
+    static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
+                          hipStream_t st);
+    // Axis-0 complex-to-real + nonlinear phase; mode 0 full, 1 phase only, 2 potential output only.
+    static hipError_t c2r_phase(int N0, int mode, const void* X1, void* S, void* Phi, int C, const PhaseArgs& pa,
+                                const void* twN, const void* tw2N, hipStream_t st);
+    static hipError_t build_kin(void* Q, int T0, int T1, int T2, double dmu0, double dmu1, double dmu2, double s,
+                                double m2, double tau, double scale, hipStream_t st);
+    static hipError_t red_local(const void* psi, const void* Phi, long n, const GridGeom& g, double wa, double wz,
+                                double wc, double ws, double* partials, int slot0, int nblk, hipStream_t st);
+    static hipError_t red_kin(const void* ph, long n, const GridGeom& g, double dmu0, double dmu1, double dmu2,
+                              double s, double m2, double* partials, int slot0, int nblk, hipStream_t st);
+    static hipError_t red_lz(const void* psi, const void* D, long n, const GridGeom& g, int coord_axis,
+                             double* partials, int slot0, int nblk, hipStream_t st);
+    static hipError_t fourier_mult(const void* in, void* out, long n, const GridGeom& g, int what, int axis,
+                                   double dmu0, double dmu1, double dmu2, double s, double m2, double scale,
+                                   hipStream_t st);
+    static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi, long n,
+                              const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
+                              double g1, double g2, hipStream_t st);
+};
+
+hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
+                            double beta, double lam, double Omega, double* out, hipStream_t st);
+
+}  // namespace fse

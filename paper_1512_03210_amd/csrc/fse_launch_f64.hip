@@ -1,0 +1,29 @@
+// Complex128 instantiation of the split-step kernels.
+#define FSE_REAL double
+#include "fse_launch.inc"
+
+namespace fse {
+
+static bool in_list(int M, const int* l, int n) {
+    for (int i = 0; i < n; ++i)
+        if (l[i] == M) return true;
+    return false;
+}
+
+bool strided_size_ok(int M) {
+    static const int l[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    return in_list(M, l, sizeof(l) / sizeof(l[0]));
+}
+
+bool line_size_ok(int M) {
+    static const int l[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
+    return in_list(M, l, sizeof(l) / sizeof(l[0]));
+}
+
+hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
+                            double beta, double lam, double Omega, double* out, hipStream_t st) {
+    k_red_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, nslot, kind, vol, n, beta, lam, Omega, out);
+    return hipGetLastError();
+}
+
+}  // namespace fse

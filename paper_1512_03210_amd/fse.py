@@ -1,0 +1,256 @@
+"""Thin ctypes binding of libfse.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts torch
+tensors to device pointers and HIP streams, and status codes to exceptions.
+There is no CPU fallback: if libfse.so is missing the import of the library
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfse.so")
+
+FSE_OK = 0
+STATUS = {0: "FSE_OK", -1: "FSE_ERR_ARG", -2: "FSE_ERR_UNSUPPORTED", -3: "FSE_ERR_NOMEM",
+          -4: "FSE_ERR_HIP", -5: "FSE_ERR_NUMERIC", -6: "FSE_ERR_STATE"}
+C128, C64 = 0, 1
+K_NONE, K_COULOMB, K_DDI3 = 0, 1, 2
+KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3}
+
+EXPORTS = [
+    "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
+    "fse_set_time", "fse_get_time", "fse_step", "fse_apply_H", "fse_nonlocal_potential",
+    "fse_mass", "fse_energy", "fse_angular_momentum", "fse_gausum_symbol_host",
+    "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
+]
+PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
+
+
+class FseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("mu", ctypes.c_double), ("prefactor", ctypes.c_double),
+                ("n", ctypes.c_double * 3), ("delta", ctypes.c_double), ("ht", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfse.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1512_03210_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, st = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int
+    ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    kp = ctypes.POINTER(Kernel)
+    sig = {
+        "fse_plan_check": (st, [i, ip, dp, d, d, dp, d, d, kp, i]),
+        "fse_plan_create": (st, [ctypes.POINTER(vp), i, ip, dp, d, d, dp, d, d, kp, i, d, vp]),
+        "fse_plan_destroy": (st, [vp]),
+        "fse_workspace_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "fse_set_time": (st, [vp, d]),
+        "fse_get_time": (st, [vp, dp]),
+        "fse_step": (st, [vp, vp, i, d, vp]),
+        "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
+        "fse_nonlocal_potential": (st, [vp, vp, vp, vp]),
+        "fse_mass": (st, [vp, vp, vp, vp]),
+        "fse_energy": (st, [vp, vp, vp, vp]),
+        "fse_angular_momentum": (st, [vp, vp, vp, vp]),
+        "fse_gausum_symbol_host": (st, [i, ip, dp, kp, dp]),
+        "fse_get_symbol": (st, [vp, dp]),
+        "fse_last_error": (ctypes.c_char_p, []),
+        "fse_version": (ctypes.c_char_p, []),
+        "fse_set_profiling": (st, [vp, i]),
+        "fse_get_profile": (st, [vp, dp, ip, i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != FSE_OK:
+        raise FseError(status, lib().fse_last_error().decode())
+
+
+def make_kernel(kind: str = "coulomb", mu: float = 1.0, prefactor: float = 1.0,
+                axis=(0.0, 0.0, 1.0), delta: float = 0.0, ht: float = 0.0) -> Kernel:
+    k = Kernel()
+    k.kind = KERNEL_KINDS[kind]
+    k.mu = mu
+    k.prefactor = prefactor
+    k.n = (ctypes.c_double * 3)(*axis)
+    k.delta = delta
+    k.ht = ht
+    return k
+
+
+def _iarr(v):
+    return (ctypes.c_int * len(v))(*[int(x) for x in v])
+
+
+def _darr(v):
+    return (ctypes.c_double * len(v))(*[float(x) for x in v])
+
+
+def plan_check(d, N, L, s, Omega, gamma, beta, lam, kernel: Optional[Kernel], precision=C128) -> int:
+    """Host-only validation; returns the status code (no exception)."""
+    return lib().fse_plan_check(d, _iarr(N), _darr(L), s, Omega, _darr(gamma), beta, lam,
+                                ctypes.byref(kernel) if kernel is not None else None, precision)
+
+
+def gausum_symbol_host(d, N, L, kernel: Kernel) -> np.ndarray:
+    """The multiplier on the non-negative frequency octant, shape (N_j + 1,) per axis (host)."""
+    shape = tuple(int(n) + 1 for n in N)
+    out = np.zeros(int(np.prod(shape)), dtype=np.float64)
+    _check(lib().fse_gausum_symbol_host(d, _iarr(N), _darr(L), ctypes.byref(kernel),
+                                        out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.reshape(shape)
+
+
+def version() -> str:
+    return lib().fse_version().decode()
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One grid + parameter set; wraps fse_plan (device memory owned by the library).
+
+    psi tensors are torch complex128 (precision C128) or complex64 (C64) on the
+    current HIP device, C-contiguous with shape N.
+    """
+
+    def __init__(self, d: int, N: Sequence[int], L: Sequence[float], s: float, Omega: float,
+                 gamma: Sequence[float], beta: float, lam: float, kernel: Optional[Kernel] = None,
+                 precision: int = C128, m: float = 0.0, stream=None):
+        import torch
+        self.d, self.N, self.L = int(d), tuple(int(n) for n in N), tuple(float(x) for x in L)
+        self.precision = precision
+        self.cdtype = torch.complex128 if precision == C128 else torch.complex64
+        self.rdtype = torch.float64 if precision == C128 else torch.float32
+        self._h = ctypes.c_void_p()
+        _check(lib().fse_plan_create(ctypes.byref(self._h), self.d, _iarr(self.N), _darr(self.L), s, Omega,
+                                     _darr(gamma), beta, lam,
+                                     ctypes.byref(kernel) if kernel is not None else None,
+                                     precision, m, _stream(stream)))
+
+    @classmethod
+    def from_params(cls, p, precision=C128, stream=None, **kw):
+        kern = None if p.kernel == "none" else make_kernel(p.kernel, mu=p.mu, prefactor=p.c, **kw)
+        return cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kern, precision, p.m, stream)
+
+    def close(self):
+        if self._h:
+            _check(lib().fse_plan_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check_psi(self, psi):
+        if psi.dtype != self.cdtype or tuple(psi.shape) != self.N or not psi.is_contiguous() or not psi.is_cuda:
+            raise ValueError(f"psi must be a contiguous {self.cdtype} device tensor of shape {self.N}")
+
+    @property
+    def time(self) -> float:
+        t = ctypes.c_double()
+        _check(lib().fse_get_time(self._h, ctypes.byref(t)))
+        return t.value
+
+    @time.setter
+    def time(self, t: float):
+        _check(lib().fse_set_time(self._h, float(t)))
+
+    def workspace_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().fse_workspace_size(self._h, ctypes.byref(b)))
+        return b.value
+
+    def step(self, psi, nsteps: int, dt: float, stream=None):
+        self._check_psi(psi)
+        _check(lib().fse_step(self._h, _ptr(psi), int(nsteps), float(dt), _stream(stream)))
+        return psi
+
+    def apply_H(self, psi, out=None, rho_frozen=None, stream=None):
+        import torch
+        self._check_psi(psi)
+        out = torch.empty_like(psi) if out is None else out
+        self._check_psi(out)
+        rp = None
+        if rho_frozen is not None:
+            if rho_frozen.dtype != self.rdtype or tuple(rho_frozen.shape) != self.N or not rho_frozen.is_contiguous():
+                raise ValueError("rho_frozen must be a contiguous real tensor of the plan's precision and shape")
+            rp = _ptr(rho_frozen)
+        _check(lib().fse_apply_H(self._h, _ptr(psi), _ptr(out), rp, _stream(stream)))
+        return out
+
+    def nonlocal_potential(self, psi, out=None, stream=None):
+        import torch
+        self._check_psi(psi)
+        out = torch.empty(self.N, dtype=self.rdtype, device=psi.device) if out is None else out
+        _check(lib().fse_nonlocal_potential(self._h, _ptr(psi), _ptr(out), _stream(stream)))
+        return out
+
+    def _scalar(self, fn, psi, n, stream):
+        import torch
+        self._check_psi(psi)
+        out = torch.empty(n, dtype=torch.float64, device=psi.device)
+        _check(fn(self._h, _ptr(psi), _ptr(out), _stream(stream)))
+        return out
+
+    def mass(self, psi, stream=None):
+        return self._scalar(lib().fse_mass, psi, 1, stream)
+
+    def energy(self, psi, stream=None):
+        """Device tensor [E_kin, E_pot, E_int, E_non, E_rot, E_total]."""
+        return self._scalar(lib().fse_energy, psi, 6, stream)
+
+    def angular_momentum(self, psi, stream=None):
+        return self._scalar(lib().fse_angular_momentum, psi, 1, stream)
+
+    def set_profiling(self, enable: bool):
+        _check(lib().fse_set_profiling(self._h, 1 if enable else 0))
+
+    def profile(self):
+        """{pass name: (total ms, launches)} accumulated since profiling was enabled."""
+        n = len(PASS_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int * n)()
+        _check(lib().fse_get_profile(self._h, ms, cnt, n))
+        return {PASS_NAMES[k]: (ms[k], cnt[k]) for k in range(n) if cnt[k] > 0}
+
+    def symbol(self) -> np.ndarray:
+        shape = tuple(n + 1 for n in self.N)
+        out = np.zeros(int(np.prod(shape)), dtype=np.float64)
+        _check(lib().fse_get_symbol(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.reshape(shape)

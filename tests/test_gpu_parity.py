@@ -1,0 +1,335 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 against the oracle): 1e-12 for complex128 and 1e-5
+for complex64 after one step; multi-step drift is bounded loosely and
+printed.  Sizes span several tiles and ragged tails (odd line counts of the
+padded passes, 24-column tiles in complex64).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import diagnostics as dg
+from oracle import gausum, scheme
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1512_03210_amd import fse  # noqa: E402
+
+
+def _note(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fse.lib()
+
+
+def _dev(a, prec=fse.C128):
+    dt = np.complex128 if prec == fse.C128 else np.complex64
+    return torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to("cuda:0")
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.complex128 if t.is_complex() else np.float64)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_K_CACHE = {}
+
+
+def _oracle_problem(p):
+    pr = scheme.Problem.from_params(p)
+    key = (p.N, p.L, p.kernel, p.mu, p.c)
+    if pr.kernel != "none" and pr.lam != 0.0:
+        if key not in _K_CACHE:
+            _K_CACHE[key] = pr.K
+        pr._K = _K_CACHE[key]
+    return pr
+
+
+def P(name, **kw):
+    base = dict(
+        cfg1=W.preset("cfg1"),
+        aniso2d=W.Params(d=2, N=(48, 96), L=(6.0, 9.0), s=1.2, Omega=0.6, gamma=(1.0, 1.4), beta=30.0, lam=2.0,
+                         kernel="coulomb", coef=1.0, dt=2e-3, name="aniso2d"),
+        coul3d=W.Params(d=3, N=(32, 24, 16), L=(6.0, 5.0, 4.0), s=0.8, Omega=0.7, gamma=(1.0, 1.3, 2.0),
+                        beta=50.0, lam=5.0, kernel="coulomb", dt=1e-3, name="coul3d"),
+        ddi3d=W.Params(d=3, N=(32, 32, 24), L=(6.0, 6.0, 5.0), s=0.8, Omega=0.7, gamma=(1.0, 1.0, 2.0),
+                       beta=200.0, lam=50.0, kernel="ddi3", dt=5e-4, name="ddi3d"),
+        local2d=W.Params(d=2, N=(64, 48), L=(8.0, 6.0), s=0.6, Omega=0.9, gamma=(1.0, 1.2), beta=80.0, lam=0.0,
+                         kernel="none", dt=1e-3, name="local2d"),
+        local3d=W.Params(d=3, N=(24, 32, 48), L=(5.0, 6.0, 7.0), s=1.5, Omega=0.3, gamma=(1.1, 1.0, 1.5),
+                         beta=20.0, lam=0.0, kernel="none", dt=1e-3, name="local3d"),
+    )[name]
+    return base.replace(**kw) if kw else base
+
+
+def _psi0(p, seed=0):
+    if p.d == 2:
+        return W.harmonic_vortex_2d(p.N, p.L, seed=seed)
+    return W.anisotropic_gaussian(p.N, p.L, p.gamma, seed=seed)
+
+
+CASES = ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_one_step_c128(name):
+    p = P(name)
+    _note(f"[parity] one step c128 {name} N={p.N}")
+    psi0 = _psi0(p)
+    pr = _oracle_problem(p)
+    ref, _ = pr.step(psi0, 0.0, p.dt)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0)
+    plan.step(x, 1, p.dt)
+    err = _rel(_host(x), ref)
+    _note(f"  rel L2 = {err:.3e}")
+    assert err < 1e-12
+    assert abs(plan.time - p.dt) < 1e-15
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_one_step_c64(name):
+    p = P(name)
+    _note(f"[parity] one step c64 {name} N={p.N}")
+    psi0 = _psi0(p)
+    ref, _ = _oracle_problem(p).step(psi0, 0.0, p.dt)
+    plan = fse.Plan.from_params(p, fse.C64)
+    x = _dev(psi0, fse.C64)
+    plan.step(x, 1, p.dt)
+    err = _rel(_host(x), ref)
+    _note(f"  rel L2 = {err:.3e}")
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d"])
+def test_many_steps_fsal_against_plain_oracle(name):
+    # merged half steps inside one call vs the oracle's plain scheme; the
+    # anisotropic rotating cases exercise the time-dependent trap integral.
+    p = P(name)
+    n = 100 if name == "cfg1" else 20
+    _note(f"[parity] {n} steps c128 {name}")
+    psi0 = _psi0(p)
+    ref, t = _oracle_problem(p).run(psi0, n, p.dt)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0)
+    plan.step(x, n, p.dt)
+    err = _rel(_host(x), ref)
+    _note(f"  drift after {n} steps: rel L2 = {err:.3e}")
+    assert err < 1e-10
+    assert abs(plan.time - t) < 1e-12
+
+
+def test_split_calls_continue_the_trajectory():
+    # 3 + 4 steps in two calls equal 7 steps: the plan's clock carries t.
+    p = P("aniso2d")
+    psi0 = _psi0(p, seed=3)
+    plan = fse.Plan.from_params(p, fse.C128)
+    a = _dev(psi0)
+    plan.step(a, 3, p.dt)
+    plan.step(a, 4, p.dt)
+    ref, _ = _oracle_problem(p).run(psi0, 7, p.dt)
+    assert _rel(_host(a), ref) < 1e-11
+
+
+@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d"])
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_nonlocal_potential(name, prec):
+    p = P(name)
+    psi0 = _psi0(p, seed=1)
+    pr = _oracle_problem(p)
+    ref = pr.potential(np.abs(psi0) ** 2)
+    plan = fse.Plan.from_params(p, prec)
+    phi = _host(plan.nonlocal_potential(_dev(psi0, prec)))
+    err = _rel(phi, ref)
+    _note(f"[parity] potential {name} prec={prec}: {err:.3e}")
+    assert err < (1e-12 if prec == fse.C128 else 1e-5)
+
+
+def test_symbol_of_plan_matches_oracle():
+    p = P("ddi3d")
+    plan = fse.Plan.from_params(p, fse.C128)
+    K = plan.symbol()
+    Ko = gausum.ddi3_symbol(p.N, p.L)[tuple(slice(0, n + 1) for n in p.N)]
+    assert np.max(np.abs(K - Ko)) < 1e-11 * np.max(np.abs(Ko))
+
+
+@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "local3d"])
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_diagnostics(name, prec):
+    p = P(name)
+    psi0 = _psi0(p, seed=2)
+    pr = _oracle_problem(p)
+    plan = fse.Plan.from_params(p, prec)
+    plan.time = 0.37  # the rotating-frame trap W(x~, t) depends on t
+    x = _dev(psi0, prec)
+    e = plan.energy(x).cpu().numpy()
+    m = plan.mass(x).cpu().numpy()[0]
+    lz = plan.angular_momentum(x).cpu().numpy()[0]
+    xin = _host(x)  # the rounded input for c64
+    eo = np.array(dg.energy_parts(pr, xin, t=0.37))
+    tol = 1e-11 if prec == fse.C128 else 1e-5
+    _note(f"[parity] diagnostics {name} prec={prec}: max dE = {np.max(np.abs(e - eo)):.3e}")
+    assert np.all(np.abs(e - eo) <= tol * np.maximum(1.0, np.abs(eo)))
+    assert abs(m - dg.mass(xin, p.N, p.L)) < tol
+    assert abs(lz - dg.angular_momentum(xin, p.N, p.L)) < tol
+
+
+@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d"])
+@pytest.mark.parametrize("frozen", [False, True])
+def test_apply_H(name, frozen):
+    p = P(name)
+    psi0 = _psi0(p, seed=4)
+    pr = _oracle_problem(p)
+    rho = None
+    if frozen:
+        rho = 0.7 * np.abs(W.harmonic_vortex_2d(p.N, p.L, seed=9) if p.d == 2 else psi0) ** 2
+    ref = dg.apply_H(pr, psi0, rho_frozen=rho)
+    plan = fse.Plan.from_params(p, fse.C128)
+    rt = None if rho is None else torch.from_numpy(rho).to("cuda:0")
+    out = _host(plan.apply_H(_dev(psi0), rho_frozen=rt))
+    err = _rel(out, ref)
+    _note(f"[parity] apply_H {name} frozen={frozen}: {err:.3e}")
+    assert err < 1e-12
+
+
+def test_apply_H_c64():
+    p = P("cfg1")
+    psi0 = _psi0(p, seed=4)
+    ref = dg.apply_H(_oracle_problem(p), psi0)
+    plan = fse.Plan.from_params(p, fse.C64)
+    assert _rel(_host(plan.apply_H(_dev(psi0, fse.C64))), ref) < 1e-5
+
+
+def test_reversibility_and_mass():
+    p = P("ddi3d")
+    psi0 = _psi0(p, seed=5)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0)
+    plan.step(x, 10, p.dt)
+    m = plan.mass(x).item()
+    plan.step(x, 10, -p.dt)
+    assert abs(m - 1.0) < 1e-12
+    assert _rel(_host(x), psi0) < 1e-11
+    assert abs(plan.time) < 1e-15
+
+
+def test_deterministic_rerun():
+    p = P("coul3d")
+    psi0 = _psi0(p, seed=6)
+    outs = []
+    for _ in range(2):
+        plan = fse.Plan.from_params(p, fse.C128)
+        x = _dev(psi0)
+        plan.step(x, 3, p.dt)
+        outs.append(_host(x))
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_invalid_calls_raise():
+    p = P("cfg1")
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(_psi0(p))
+    with pytest.raises(fse.FseError):
+        fse._check(fse.lib().fse_step(plan._h, fse._ptr(x), -1, 1e-3, None))
+    with pytest.raises(fse.FseError):
+        fse._check(fse.lib().fse_step(plan._h, fse._ptr(x), 1, 0.0, None))
+    with pytest.raises(fse.FseError):
+        fse._check(fse.lib().fse_apply_H(plan._h, fse._ptr(x), fse._ptr(x), None, None))
+    with pytest.raises(ValueError):
+        plan.step(x.to(torch.complex64), 1, 1e-3)
+
+
+# ---------------------------------------------------------------------------
+# Full-size checks at the benchmarked configuration (256^3, 512^3 padding).
+# The oracle cannot run a full nonlinear step there in seconds, so these use
+# properties that hold at any size and one oracle linear step.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_full_size_free_evolution(prec):
+    p = W.preset("m0").replace(beta=0.0, lam=0.0, kernel="none", gamma=(0.0, 0.0, 0.0))
+    _note(f"[full] free evolution 256^3 prec={prec}")
+    psi0 = W.anisotropic_gaussian(p.N, p.L, (1.0, 1.0, 2.0), seed=0)
+    plan = fse.Plan.from_params(p, prec)
+    x = _dev(psi0, prec)
+    plan.step(x, 4, p.dt)
+    ref = scheme.kinetic(psi0, p.N, p.L, p.s, 4 * p.dt)
+    err = _rel(_host(x), ref)
+    _note(f"  rel L2 = {err:.3e}")
+    assert err < (1e-12 if prec == fse.C128 else 1e-5)
+
+
+def test_full_size_potential_closed_form():
+    # erf(r)/r potential of a Gaussian density on the 256^3 grid (c = 1).
+    N, L = (256, 256, 256), (12.0, 12.0, 12.0)
+    p = W.Params(d=3, N=N, L=L, s=1.0, Omega=0.0, gamma=(0, 0, 0), beta=0.0, lam=1.0, kernel="coulomb", coef=1.0)
+    X = W.mesh(N, L)
+    r = np.sqrt(X[0] ** 2 + X[1] ** 2 + X[2] ** 2)
+    psi = (math.pi ** -0.75 * np.exp(-r ** 2 / 2)).astype(np.complex128)
+    plan = fse.Plan.from_params(p, fse.C128)
+    phi = _host(plan.nonlocal_potential(_dev(psi)))
+    rs = np.where(r > 0, r, 1.0)
+    from scipy import special
+    exact = np.where(r > 0, special.erf(rs) / rs, 2 / math.sqrt(math.pi))
+    err = _rel(phi, exact)
+    _note(f"[full] 256^3 Coulomb closed form: {err:.3e}")
+    assert err < 1e-12
+
+
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_full_size_step_invariants(prec):
+    p = W.preset("m0")
+    _note(f"[full] m0 invariants prec={prec}")
+    psi0 = W.initial_state(p, seed=0)
+    plan = fse.Plan.from_params(p, prec)
+    x = _dev(psi0, prec)
+    m0 = plan.mass(x).item()
+    plan.step(x, 5, p.dt)
+    m1 = plan.mass(x).item()
+    _note(f"  mass drift {m1 - m0:.3e}")
+    assert abs(m1 - m0) < (1e-12 if prec == fse.C128 else 1e-5)
+    plan.step(x, 5, -p.dt)
+    err = _rel(_host(x), psi0)
+    _note(f"  reversibility {err:.3e}")
+    assert err < (1e-11 if prec == fse.C128 else 1e-5)
+
+
+def test_full_size_fsal_split_equals_single_call():
+    p = W.preset("m0")
+    psi0 = W.initial_state(p, seed=1)
+    a = _dev(psi0)
+    b = _dev(psi0)
+    pa = fse.Plan.from_params(p, fse.C128)
+    pb = fse.Plan.from_params(p, fse.C128)
+    pa.step(a, 4, p.dt)
+    pb.step(b, 2, p.dt)
+    pb.step(b, 2, p.dt)
+    err = _rel(_host(a), _host(b))
+    _note(f"[full] m0 4 steps vs 2+2: {err:.3e}")
+    assert err < 1e-13
+
+
+def test_cfg2_against_oracle_two_steps():
+    p = W.preset("cfg2")
+    _note("[full] cfg2 128^3 two steps vs oracle")
+    psi0 = W.initial_state(p, seed=0)
+    ref, _ = _oracle_problem(p).run(psi0, 2, p.dt)
+    for prec, tol in [(fse.C128, 1e-12), (fse.C64, 1e-5)]:
+        plan = fse.Plan.from_params(p, prec)
+        x = _dev(psi0, prec)
+        plan.step(x, 2, p.dt)
+        err = _rel(_host(x), ref)
+        _note(f"  prec={prec}: {err:.3e}")
+        assert err < tol

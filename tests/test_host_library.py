@@ -1,0 +1,97 @@
+"""CPU tests of libfse.so: it loads, exports every declared entry point, its
+host-side validation returns the documented codes, and its host FP64 GauSum
+multiplier agrees with the oracle's (independent implementations)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1512_03210_amd import fse
+from oracle import gausum
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "fse.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:fse_status|const char\*)\s+(fse_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = fse.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 16
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(fse.EXPORTS) == declared
+    assert "gfx950" in fse.version()
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(d=4), -1),
+    (dict(N=(64, 62)), -1),           # 62 = 2 * 31
+    (dict(N=(64, 8)), -1),            # below the minimum size
+    (dict(N=(64, 1024)), -1),         # above the maximum size
+    (dict(L=(8.0, -1.0)), -1),
+    (dict(s=0.0), -1),
+    (dict(s=float("nan")), -1),
+    (dict(beta=float("inf")), -1),
+    (dict(kernel=fse.make_kernel("coulomb", mu=1.5)), -1),   # mu > d - 1 in 2D
+    (dict(kernel=fse.make_kernel("ddi3")), -1),               # dipole needs d = 3
+    (dict(precision=7), -1),
+    (dict(), 0),
+    (dict(N=(96, 48)), 0),
+])
+def test_plan_check_codes(args, code):
+    a = dict(d=2, N=(64, 64), L=(8.0, 8.0), s=0.75, Omega=0.5, gamma=(1.0, 1.0), beta=100.0, lam=1.0,
+             kernel=fse.make_kernel("coulomb", prefactor=1 / (2 * math.pi)), precision=fse.C128)
+    a.update(args)
+    st = fse.plan_check(a["d"], a["N"], a["L"], a["s"], a["Omega"], a["gamma"] + (1.0,) * 2, a["beta"], a["lam"],
+                        a["kernel"], a["precision"])
+    assert st == code, fse.lib().fse_last_error()
+
+
+def test_plan_check_3d_and_unsupported_axis():
+    k = fse.make_kernel("ddi3", axis=(0.0, 0.0, 1.0))
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k) == 0
+    k2 = fse.make_kernel("ddi3", axis=(1.0, 0.0, 0.0))
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k2) == -2
+    assert fse.plan_check(3, (512, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k) == -1
+
+
+@pytest.mark.parametrize("d,N,L,kind,c", [
+    (2, (64, 64), (8.0, 8.0), "coulomb", 1 / (2 * math.pi)),
+    (2, (48, 96), (6.0, 9.0), "coulomb", 1.0),
+    (3, (32, 24, 16), (6.0, 5.0, 4.0), "coulomb", 1 / (4 * math.pi)),
+    (2, (32, 32), (4.0, 4.0), "coulomb-mu0.5", 1.0),
+])
+def test_host_coulomb_symbol_matches_oracle(d, N, L, kind, c):
+    mu = 0.5 if kind.endswith("0.5") else 1.0
+    K = fse.gausum_symbol_host(d, N, L, fse.make_kernel("coulomb", mu=mu, prefactor=c))
+    Ko = gausum.coulomb_symbol(N, L, mu=mu, c=c)[tuple(slice(0, n + 1) for n in N)]
+    assert np.max(np.abs(K - Ko)) < 1e-14 * np.max(np.abs(Ko))
+
+
+def test_host_ddi3_symbol_matches_oracle():
+    N, L = (32, 32, 24), (6.0, 6.0, 5.0)
+    K = fse.gausum_symbol_host(3, N, L, fse.make_kernel("ddi3"))
+    Ko = gausum.ddi3_symbol(N, L)[tuple(slice(0, n + 1) for n in N)]
+    # the dipole multiplier is -1 + 3 kz^2 Khat_C: round-off of Khat_C is
+    # amplified by 3 kz^2, so compare on that scale
+    KC = gausum.coulomb_symbol(N, L, mu=1.0, c=1 / (4 * math.pi))
+    kz = math.pi * np.arange(N[2] + 1) / (2 * L[2])
+    scale = 1.0 + 3.0 * kz[None, None, :] ** 2 * np.max(np.abs(KC))
+    assert np.max(np.abs(K - Ko) / scale) < 1e-14
+    assert abs(K[0, 0, 0] + 1.0) < 1e-15  # kappa = 0: -1
+
+
+def test_gpu_entry_points_fail_cleanly_without_device():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = fse.ctypes.c_void_p()
+    st = fse.lib().fse_plan_create(fse.ctypes.byref(h), 2, fse._iarr((64, 64)), fse._darr((8.0, 8.0)), 0.75, 0.5,
+                                   fse._darr((1.0, 1.0)), 1.0, 1.0, None, 0, 0.0, None)
+    assert st == -4 and not h.value
