@@ -128,6 +128,28 @@ def run_precision(p, prec, steps, warmup, prof_steps):
     }
 
 
+def copy_bandwidth(nbytes=2 << 30, reps=10):
+    """Achieved bandwidth of the library's plain copy kernel (read + write bytes / time)."""
+    import torch
+
+    from paper_1512_03210_amd import fse
+
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    fse.device_copy(b, a, nbytes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fse.device_copy(b, a, nbytes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(p, nsteps=1):
     """The FP64 oracle on a bounded sample: nsteps steps of the same workload."""
     import numpy as np
@@ -207,6 +229,9 @@ def main():
         "bytes_per_launch": dp["bytes_per_launch"],
         "avg_ms": dp["avg_ms"],
     }
+    copy_gbs = copy_bandwidth()
+    print(f"[bench] copy kernel {copy_gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    roof["frac_of_copy"] = round(dp["gbs"] / copy_gbs, 4)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
@@ -232,6 +257,7 @@ def main():
             "precision": "complex128",
         },
         "step_hbm_frac": r64["step_hbm_frac"],
+        "copy_kernel_gbs": copy_gbs,
         "model_bytes_per_point": r64["model_bytes_per_point"],
         "roofline": roof,
         "cpu_baseline": cpu,

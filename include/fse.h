@@ -162,6 +162,12 @@ enum {
 fse_status fse_set_profiling(fse_plan plan, int enable);
 fse_status fse_get_profile(fse_plan plan, double* ms, int* count, int npass);
 
+/* Streaming device-to-device copy of `bytes` bytes (a multiple of 16, both
+ * pointers 16-byte aligned) by a plain vector-load/vector-store kernel.  Used
+ * to measure the achievable HBM bandwidth and to calibrate the memory
+ * counters against a kernel of known traffic. */
+fse_status fse_device_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Message describing the calling thread's last error ("" if none). */
 const char* fse_last_error(void);
 

@@ -15,13 +15,15 @@ import sys
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-BUILD = os.path.join(PKG, "_build")
-LIB = os.path.join(PKG, "libfse.so")
+BUILD = os.environ.get("FSE_BUILD_DIR", os.path.join(PKG, "_build"))
+LIB = os.environ.get("FSE_LIB_OUT", os.path.join(PKG, "libfse.so"))
 
 ARCH = os.environ.get("FSE_OFFLOAD_ARCH", "gfx950")
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.join(ROOT, "include")]
+# Extra compile definitions (kernel variants for tuning), e.g. FSE_DEFINES="FSE_TWFULL FSE_PADFULL".
+EXTRA = [f"-D{d}" for d in os.environ.get("FSE_DEFINES", "").split() if d]
 
 SOURCES = [
     "fse_launch_f64.hip",
@@ -40,7 +42,7 @@ def hipcc() -> str:
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + COMMON + DEVICE_FLAGS
+    cmd = [hipcc()] + COMMON + DEVICE_FLAGS + EXTRA
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <string>
@@ -141,11 +142,9 @@ fse_status check_args(int d, const int* N, const double* L, double s, double Ome
         if (!std::isfinite(kernel->delta) || !std::isfinite(kernel->ht))
             return fail(FSE_ERR_ARG, "kernel delta and ht must be finite");
     }
-    if (kernel && kernel->kind != FSE_K_NONE) {
-        for (int j = 0; j < d; ++j)
-            if (!fse::line_size_ok(2 * N[j]))
-                return fail(FSE_ERR_UNSUPPORTED, "padded length %d has no compiled FFT length", 2 * N[j]);
-    }
+    // 3D: the padded transform of axis 1 runs at length 2 N1 (at most 512 since N <= 256).
+    if (kernel && kernel->kind != FSE_K_NONE && d == 3 && !fse::strided_size_ok(2 * N[1]))
+        return fail(FSE_ERR_UNSUPPORTED, "padded length %d has no compiled FFT length", 2 * N[1]);
     return FSE_OK;
 }
 
@@ -311,13 +310,13 @@ fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
 template <typename R> fse_status conv_passes(fse_plan p, hipStream_t st) {
     using L = fse::Launch<R>;
     if (p->d == 3) {
-        const int M1 = 2 * p->N[1], M2 = 2 * p->N[2];
-        HIPCHK(L::strided(M1, false, 1, p->X1, p->X2, p->N[0] + 1, p->N[2], p->tw[M1], st));
-        HIPCHK(L::line(M2, 0, p->X2, (p->N[0] + 1) * M1, p->khat, conv_index(p), p->tw[M2], st));
-        HIPCHK(L::strided(M1, true, 2, p->X2, p->X1, p->N[0] + 1, p->N[2], p->tw[M1], st));
+        const int N1 = p->N[1], N2 = p->N[2];
+        HIPCHK(L::strided(N1, false, 1, p->X1, p->X2, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
+        HIPCHK(L::line(N2, 0, p->X2, (p->N[0] + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2], st));
+        HIPCHK(L::strided(N1, true, 2, p->X2, p->X1, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
     } else {
-        const int M1 = 2 * p->N[1];
-        HIPCHK(L::line(M1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[M1], st));
+        const int N1 = p->N[1];
+        HIPCHK(L::line(N1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
     }
     return FSE_OK;
 }
@@ -340,17 +339,19 @@ template <typename R> fse_status potential_impl(fse_plan p, const void* src, int
 
 template <typename R> fse_status fft_forward(fse_plan p, void* a, hipStream_t st) {
     using L = fse::Launch<R>;
-    HIPCHK(L::strided(p->N[0], false, 0, a, a, 1, p->C0, p->tw[p->N[0]], st));
-    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], st));
-    HIPCHK(L::line(p->last(), 2, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()], st));
+    HIPCHK(L::strided(p->N[0], false, 0, a, a, 1, p->C0, p->tw[p->N[0]], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::line(p->last(), 2, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()],
+                   nullptr, st));
     return FSE_OK;
 }
 
 template <typename R> fse_status fft_inverse(fse_plan p, void* a, hipStream_t st) {
     using L = fse::Launch<R>;
-    HIPCHK(L::line(p->last(), 3, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()], st));
-    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], st));
-    HIPCHK(L::strided(p->N[0], true, 0, a, a, 1, p->C0, p->tw[p->N[0]], st));
+    HIPCHK(L::line(p->last(), 3, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()],
+                   nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::strided(p->N[0], true, 0, a, a, 1, p->C0, p->tw[p->N[0]], nullptr, st));
     return FSE_OK;
 }
 
@@ -374,24 +375,28 @@ template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, do
     const fse::LineIdx ki = kin_index(p);
     const int N1 = p->N[1], N2 = (p->d == 3) ? p->N[2] : 1;
     // entry: half linear step, leaving the axis-0 inverse pending
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], st));
-    if (p->d == 3) PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], st));
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], st));
-    if (p->d == 3) PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], st));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
+    if (p->d == 3)
+        PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], nullptr, st));
+    if (p->d == 3)
+        PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     for (int k = 0; k < nsteps; ++k) {
         const double tn = p->t + k * dt;
         const fse::PhaseArgs pa = phase_args(p, tn, dt);
         if (p->nl) {
             PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
             if (p->d == 3) {
-                const int M1 = 2 * N1, M2 = 2 * N2;
-                PLAUNCH(p, FSE_PASS_PAD_FWD, st, L::strided(M1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[M1], st));
+                PLAUNCH(p, FSE_PASS_PAD_FWD, st,
+                        L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
                 PLAUNCH(p, FSE_PASS_CONV, st,
-                        L::line(M2, 0, p->X2, (N0 + 1) * M1, p->khat, conv_index(p), p->tw[M2], st));
-                PLAUNCH(p, FSE_PASS_CROP_INV, st, L::strided(M1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[M1], st));
+                        L::line(N2, 0, p->X2, (N0 + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2],
+                                st));
+                PLAUNCH(p, FSE_PASS_CROP_INV, st,
+                        L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
             } else {
-                const int M1 = 2 * N1;
-                PLAUNCH(p, FSE_PASS_CONV, st, L::line(M1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[M1], st));
+                PLAUNCH(p, FSE_PASS_CONV, st,
+                        L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
             }
             PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
                     L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
@@ -399,11 +404,14 @@ template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, do
             PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
                     L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
         }
-        if (p->d == 3) PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], st));
-        PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, (k == nsteps - 1) ? kh : kf, ki, p->tw[NL], st));
-        if (p->d == 3) PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], st));
+        if (p->d == 3)
+            PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+        PLAUNCH(p, FSE_PASS_KIN, st,
+                L::line(NL, 1, psi, nlines, (k == nsteps - 1) ? kh : kf, ki, p->tw[NL], nullptr, st));
+        if (p->d == 3)
+            PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     }
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], st));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
     p->t += nsteps * dt;
     return FSE_OK;
 }
@@ -578,6 +586,8 @@ fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, 
     if (p->nl) {
         for (int j = 1; j < d; ++j)
             if ((st = upload_twiddles(p, 2 * N[j])) != FSE_OK) return bail(st);
+        for (int j = 0; j < d; ++j)
+            if ((st = upload_twiddles(p, N[j])) != FSE_OK) return bail(st);
         p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor, p->kernel.delta,
                                           p->kernel.ht);
         double scale = 1.0;
@@ -709,6 +719,16 @@ fse_status fse_get_profile(fse_plan plan, double* ms, int* count, int npass) {
         }
     }
     plan->ev_used = 0;
+    return FSE_OK;
+}
+
+fse_status fse_device_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    g_err.clear();
+    if (!dst || !src) return fail(FSE_ERR_ARG, "dst and src must not be NULL");
+    if ((bytes % 16) != 0 || ((uintptr_t)dst % 16) != 0 || ((uintptr_t)src % 16) != 0)
+        return fail(FSE_ERR_ARG, "bytes and both pointers must be multiples of 16");
+    if (bytes == 0) return FSE_OK;
+    HIPCHK(fse::launch_copy16(dst, src, (long)(bytes / 16), static_cast<hipStream_t>(stream)));
     return FSE_OK;
 }
 

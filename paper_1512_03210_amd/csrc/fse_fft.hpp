@@ -1,13 +1,20 @@
 // Device-side FFT building blocks for gfx950 (CDNA4, wave64).
 //
-// A workgroup owns a tile of LPB lines of one axis, resident in LDS.  Each
-// line is transformed by a mixed-radix Stockham autosort FFT (radices
-// 2, 3, 4, 8, 16): in every stage a thread reads R elements strided by M/R,
-// applies the twiddles W_{Ns R}^{k r}, does a radix-R DFT in registers and
-// writes the results to positions (j/Ns)*Ns*R + j%Ns + r*Ns.  The LDS
-// layout inserts one pad element every 16 (complex double) or 32 (complex
-// float) elements and gives each line an odd pitch, so the strided Stockham
-// writes and the column-wise tile loads spread over the 64 LDS banks.
+// A line of length M is transformed by a mixed-radix Stockham autosort FFT
+// with radices 2, 3, 4, 8, 16.  In stage s (radix R, Ns = product of the
+// earlier radices) the thread owning butterfly j takes the R inputs at
+// j + r*M/R, multiplies them by the twiddles W_{Ns R}^{(j mod Ns) r}, does a
+// radix-R DFT in registers and produces outputs for positions
+// (j/Ns)*Ns*R + j%Ns + r*Ns.
+//
+// Register-resident ends: the first stage takes its inputs from registers
+// (loaded straight from HBM by the caller) and the last stage leaves its
+// outputs in registers at positions j + r*M/R_last, which is also the input
+// pattern of a first stage of radix R_last.  A forward transform with radix
+// order (R0..Rk) followed by an inverse with the reversed order (Rk..R0)
+// therefore needs no LDS traffic between them: a pointwise multiplier is
+// applied in registers.  Only the exchanges between consecutive stages go
+// through LDS.
 //
 // All transforms are unnormalised; forward uses exp(-2 pi i nk/M).
 #pragma once
@@ -145,7 +152,7 @@ template <bool INV> struct DFT<16, INV> {
 };
 
 // ---------------------------------------------------------------------------
-// Radix schedules (products equal M).
+// Radix schedules (products equal M) and type-level helpers.
 // ---------------------------------------------------------------------------
 template <int... Rs> struct RList {};
 template <int M> struct Radix;
@@ -160,83 +167,184 @@ template <> struct Radix<192> { using L = RList<16, 4, 3>; };
 template <> struct Radix<256> { using L = RList<16, 16>; };
 template <> struct Radix<384> { using L = RList<16, 8, 3>; };
 template <> struct Radix<512> { using L = RList<8, 8, 8>; };
-template <> struct Radix<768> { using L = RList<16, 16, 3>; };
-template <> struct Radix<1024> { using L = RList<16, 16, 4>; };
+
+template <typename L> struct Head;
+template <int R0, int... Rs> struct Head<RList<R0, Rs...>> { static constexpr int value = R0; };
+
+template <typename L> struct Last;
+template <int R0> struct Last<RList<R0>> { static constexpr int value = R0; };
+template <int R0, int R1, int... Rs> struct Last<RList<R0, R1, Rs...>> {
+    static constexpr int value = Last<RList<R1, Rs...>>::value;
+};
+
+template <typename L> struct Len;
+template <int... Rs> struct Len<RList<Rs...>> { static constexpr int value = sizeof...(Rs); };
+
+template <typename A, typename B> struct Cat;
+template <int... As, int... Bs> struct Cat<RList<As...>, RList<Bs...>> { using L = RList<As..., Bs...>; };
+
+template <typename L> struct Rev;
+template <> struct Rev<RList<>> { using L = RList<>; };
+template <int R0, int... Rs> struct Rev<RList<R0, Rs...>> {
+    using L = typename Cat<typename Rev<RList<Rs...>>::L, RList<R0>>::L;
+};
+
+// Radices strictly between the first and the last.
+template <typename L> struct Mid;
+template <int R0> struct Mid<RList<R0>> { using L = RList<>; };
+template <int R0, int R1> struct Mid<RList<R0, R1>> { using L = RList<>; };
+template <int R0, int R1, int R2, int... Rs> struct Mid<RList<R0, R1, R2, Rs...>> {
+    using L = typename Cat<RList<R1>, typename Mid<RList<R1, R2, Rs...>>::L>::L;
+};
 
 // ---------------------------------------------------------------------------
-// LDS layout.
+// LDS layout: one pad element every 16 elements; the line pitch is chosen by
+// the kernel for its lane order.
 // ---------------------------------------------------------------------------
-template <typename R> struct LdsPad;
-template <> struct LdsPad<double> { static constexpr int SHIFT = 4; };
-template <> struct LdsPad<float> { static constexpr int SHIFT = 5; };
+__device__ __forceinline__ int padx(int e) { return e + (e >> 4); }
 
-template <typename R> __device__ __forceinline__ int padx(int e) { return e + (e >> LdsPad<R>::SHIFT); }
+constexpr int round_up(int x, int m) { return ((x + m - 1) / m) * m; }
+// Lanes that differ in the line index first (column tiles): pitch = 2 mod 32.
+constexpr int pitch_cols(int E) { return round_up(E + E / 16 + 1, 32) + 2; }
+// Lanes that differ in the position first (whole lines): pitch = 16 mod 32.
+constexpr int pitch_lines(int E) { return round_up(E + E / 16, 32) + 16; }
 
-// Line pitch (in elements) for lines holding up to E elements: padded length, made odd.
-template <typename R> constexpr int line_pitch(int E) {
-    return ((E + (E >> LdsPad<R>::SHIFT) + 1) | 1);
+// ---------------------------------------------------------------------------
+// Stage primitives.  A thread owns butterflies j = jt + b*TPL (b < B) of its
+// line; stages with fewer butterflies than TPL*B leave the extra lanes idle.
+// ---------------------------------------------------------------------------
+template <int M, int TPL, int RAD> struct Shape {
+    static constexpr int NB = M / RAD;
+    static constexpr int B = (NB + TPL - 1) / TPL;
+    __device__ __forceinline__ static bool active(int j) { return (NB % TPL) == 0 || j < NB; }
+};
+
+// Twiddle W^r for r < RAD from the loaded powers W, W^2, W^4, W^8 (binary
+// decomposition of r: at most three roundings per twiddle, and only four
+// table reads per butterfly).
+template <bool INV, typename T, int RAD>
+__device__ __forceinline__ T twpow(const T (&p)[4], int r) {
+    T w{};
+    bool have = false;
+#pragma unroll
+    for (int bit = 0; bit < 4; ++bit) {
+        if ((r >> bit) & 1) {
+            w = have ? cmul(w, p[bit]) : p[bit];
+            have = true;
+        }
+    }
+    return w;
 }
 
-// ---------------------------------------------------------------------------
-// One Stockham stage on every line of the tile.  Thread (line, jt) handles
-// butterflies j = jt, jt + TPL, ...; callers pass the line's LDS base.
-// The stage begins with a barrier (previous writes visible) and has one
-// between its reads and writes (in-place buffer).
-// ---------------------------------------------------------------------------
-template <typename R, int M, bool INV, int TPL, int NS, int RAD>
-__device__ __forceinline__ void fft_stage(typename CT<R>::T* line, int jt,
-                                          const typename CT<R>::T* __restrict__ tw) {
-    using T = typename CT<R>::T;
-    constexpr int NB = M / RAD;
-    constexpr int B = (NB + TPL - 1) / TPL;
+// Twiddles (stage with Ns > 1) and the radix-RAD DFT, in registers.
+template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
+__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const T* __restrict__ tw) {
+    using S = Shape<M, TPL, RAD>;
+    static_assert(B == S::B, "register array shape");
     constexpr int TWS = M / (NS * RAD);
-    T v[B][RAD];
-    __syncthreads();
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
+    for (int b = 0; b < S::B; ++b) {
         const int j = jt + b * TPL;
-        if ((NB % TPL) == 0 || j < NB) {
-#pragma unroll
-            for (int r = 0; r < RAD; ++r) v[b][r] = line[padx<R>(j + r * NB)];
+        if (S::active(j)) {
             if (NS > 1) {
                 const int k = j % NS;
+                T p[4];
 #pragma unroll
-                for (int r = 1; r < RAD; ++r) v[b][r] = twmul<INV>(v[b][r], tw[k * r * TWS]);
+                for (int bit = 0; bit < 4; ++bit)
+                    if ((1 << bit) < RAD) p[bit] = tw[(k << bit) * TWS];
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) v[b][r] = twmul<INV>(v[b][r], twpow<INV, T, RAD>(p, r));
             }
             DFT<RAD, INV>::run(v[b]);
         }
     }
-    __syncthreads();
+}
+
+// Write the stage outputs to their Stockham positions in LDS.
+template <typename T, int M, int TPL, int NS, int RAD, int B>
+__device__ __forceinline__ void put(const T (&v)[B][RAD], T* line, int jt) {
+    using S = Shape<M, TPL, RAD>;
+    static_assert(B == S::B, "register array shape");
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
+    for (int b = 0; b < S::B; ++b) {
         const int j = jt + b * TPL;
-        if ((NB % TPL) == 0 || j < NB) {
-            const int k = j % NS;
-            const int base = (j / NS) * NS * RAD + k;
+        if (S::active(j)) {
+            const int base = (j / NS) * NS * RAD + j % NS;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) line[padx<R>(base + r * NS)] = v[b][r];
+            for (int r = 0; r < RAD; ++r) line[padx(base + r * NS)] = v[b][r];
         }
     }
 }
 
-template <typename R, int M, bool INV, int TPL, int NS, typename L> struct Stages;
-template <typename R, int M, bool INV, int TPL, int NS> struct Stages<R, M, INV, TPL, NS, RList<>> {
-    __device__ __forceinline__ static void run(typename CT<R>::T*, int, const typename CT<R>::T*) {}
+// Read a stage's inputs (positions j + r*M/RAD) from LDS.
+template <typename T, int M, int TPL, int RAD, int B>
+__device__ __forceinline__ void get(T (&v)[B][RAD], const T* line, int jt) {
+    using S = Shape<M, TPL, RAD>;
+    static_assert(B == S::B, "register array shape");
+#pragma unroll
+    for (int b = 0; b < S::B; ++b) {
+        const int j = jt + b * TPL;
+        if (S::active(j)) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) v[b][r] = line[padx(j + r * S::NB)];
+        }
+    }
+}
+
+// Middle stages entirely in LDS (each: barrier, read, barrier, compute, write).
+template <typename T, int M, bool INV, int TPL, int NS, typename L> struct MidStages;
+template <typename T, int M, bool INV, int TPL, int NS> struct MidStages<T, M, INV, TPL, NS, RList<>> {
+    __device__ __forceinline__ static void run(T*, int, const T*) {}
 };
-template <typename R, int M, bool INV, int TPL, int NS, int R0, int... Rs>
-struct Stages<R, M, INV, TPL, NS, RList<R0, Rs...>> {
-    __device__ __forceinline__ static void run(typename CT<R>::T* line, int jt,
-                                               const typename CT<R>::T* __restrict__ tw) {
-        fft_stage<R, M, INV, TPL, NS, R0>(line, jt, tw);
-        Stages<R, M, INV, TPL, NS * R0, RList<Rs...>>::run(line, jt, tw);
+template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs>
+struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>> {
+    __device__ __forceinline__ static void run(T* line, int jt, const T* __restrict__ tw) {
+        T v[Shape<M, TPL, R0>::B][R0];
+        __syncthreads();
+        get<T, M, TPL, R0>(v, line, jt);
+        __syncthreads();
+        bfly<T, M, INV, TPL, NS, R0>(v, jt, tw);
+        put<T, M, TPL, NS, R0>(v, line, jt);
+        MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>>::run(line, jt, tw);
     }
 };
 
-// Full length-M transform of the calling thread's line (all threads of the
-// block must call it).  Ends after the last stage's writes, without a barrier.
-template <typename R, int M, bool INV, int TPL>
-__device__ __forceinline__ void fft_line(typename CT<R>::T* line, int jt, const typename CT<R>::T* __restrict__ tw) {
-    Stages<R, M, INV, TPL, 1, typename Radix<M>::L>::run(line, jt, tw);
-}
+// Whole transform with register-resident ends.
+//   in:  v = inputs at positions j + r*M/R0 (first radix R0 of the plan L)
+//   out: u = outputs at positions j + r*M/Rk (last radix Rk)
+// The caller guarantees that no thread still reads the line's LDS when this
+// starts; on return other threads may still be reading it (barrier before
+// reuse).  Single-stage plans use no LDS.
+template <typename T, int M, bool INV, int TPL, typename L> struct Fft {
+    static constexpr int R0 = Head<L>::value;
+    static constexpr int RK = Last<L>::value;
+    static constexpr int B0 = Shape<M, TPL, R0>::B;
+    static constexpr int BK = Shape<M, TPL, RK>::B;
+    static constexpr int NSTAGE = Len<L>::value;
+    using In = T[B0][R0];
+    using Out = T[BK][RK];
+
+    __device__ __forceinline__ static void run(T (&v)[B0][R0], T (&u)[BK][RK], T* line, int jt,
+                                               const T* __restrict__ tw) {
+        if constexpr (NSTAGE == 1) {
+#pragma unroll
+            for (int b = 0; b < B0; ++b)
+#pragma unroll
+                for (int r = 0; r < R0; ++r) u[b][r] = v[b][r];
+            bfly<T, M, INV, TPL, 1, R0>(u, jt, tw);
+        } else {
+            bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
+            put<T, M, TPL, 1, R0>(v, line, jt);
+            MidStages<T, M, INV, TPL, R0, typename Mid<L>::L>::run(line, jt, tw);
+            __syncthreads();
+            get<T, M, TPL, RK>(u, line, jt);
+            bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tw);
+        }
+    }
+};
+
+// Forward plan and its reversal for the inverse.
+template <int M> using FwdPlan = typename Radix<M>::L;
+template <int M> using InvPlan = typename Rev<typename Radix<M>::L>::L;
 
 }  // namespace fse

@@ -27,15 +27,21 @@
 
 namespace fse {
 
-constexpr int NT = 256;  // threads of the strided kernels
-
-template <typename R> struct StridedCfg {
-    static constexpr int W = (sizeof(R) == 8) ? 8 : 16;  // columns per tile: 128 B rows
-    static constexpr int TPL = NT / W;                    // threads per line
+// ---------------------------------------------------------------------------
+// Tile configurations.
+//   Column tiles (axes 0 and 1 of the strided passes): W adjacent columns
+//   (128 B of every row), lanes ordered column-fastest so that each load and
+//   store instruction touches whole 128 B row segments; TPL threads per
+//   column.
+//   Line tiles (contiguous axis): LPB whole lines, lanes ordered
+//   position-fastest.
+// ---------------------------------------------------------------------------
+template <typename R, int N> struct ColCfg {
+    static constexpr int W = (sizeof(R) == 8) ? 8 : 16;
+    static constexpr int TPL0 = N / Head<FwdPlan<N>>::value;
+    static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 * W > 512 ? 512 / W : TPL0);
+    static constexpr int NTH = W * TPL;
 };
-
-template <typename L> struct Head;
-template <int R0, int... Rs> struct Head<RList<R0, Rs...>> { static constexpr int value = R0; };
 
 constexpr int floor_pow2(int x) {
     int p = 1;
@@ -43,257 +49,307 @@ constexpr int floor_pow2(int x) {
     return p;
 }
 
-template <typename R, int M> struct LineCfg {
+template <typename R, int N, bool CONV> struct LineCfg {
     using T = typename CT<R>::T;
-    static constexpr int P = line_pitch<R>(M);
-    static constexpr int TPL0 = M / Head<typename Radix<M>::L>::value;
+    static constexpr int P = (sizeof(R) == 8) ? (N + N / 16) : pitch_lines(N);
+    static constexpr int TPL0 = N / Head<FwdPlan<N>>::value;
     static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 > 64 ? 64 : TPL0);
-    static constexpr int LB = 40960 / (P * (int)sizeof(T));
-    static constexpr int LPB0 = floor_pow2(LB < 1 ? 1 : LB);
-    static constexpr int LPB = (LPB0 * TPL > 256) ? (256 / TPL) : LPB0;
-    static constexpr int THREADS = LPB * TPL;
+    static constexpr int SUB = CONV ? 2 : 1;  // LDS sub-lines (and thread groups) per data line
+    static constexpr int BUDGET = 40960 / (P * (int)sizeof(T) * SUB);
+    static constexpr int LPB0 = floor_pow2(BUDGET < 1 ? 1 : BUDGET);
+    static constexpr int LPB1 = (LPB0 * TPL * SUB > 256) ? 256 / (TPL * SUB) : LPB0;
+    static constexpr int LPB = LPB1 < 1 ? 1 : LPB1;
+    static constexpr int NTH = LPB * TPL * SUB;
 };
 
-// ---------------------------------------------------------------------------
-// Tile movement helpers (strided tiles, column-fastest thread order so that
-// each wavefront reads whole 128 B row segments).
-// ---------------------------------------------------------------------------
-template <typename R, int ROWS, int W, int P>
-__device__ __forceinline__ void load_cols(typename CT<R>::T* lds, const typename CT<R>::T* g, long rstride, int cv) {
-    using T = typename CT<R>::T;
-    constexpr int TOT = ROWS * W;
-    constexpr int NQ = (TOT + NT - 1) / NT;
-    T v[NQ];
+// Calls f(b, r, e) for every position e = j + r*N/RAD the thread owns.
+template <int N, int TPL, int RAD, typename F> __device__ __forceinline__ void for_pos(int jt, F f) {
+    using S = Shape<N, TPL, RAD>;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = threadIdx.x + q * NT;
-        if ((TOT % NT) == 0 || i < TOT) {
-            const int e = i / W, l = i % W;
-            v[q] = (l < cv) ? g[(long)e * rstride + l] : T{0, 0};
-        }
-    }
+    for (int b = 0; b < S::B; ++b) {
+        const int j = jt + b * TPL;
+        if (S::active(j)) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = threadIdx.x + q * NT;
-        if ((TOT % NT) == 0 || i < TOT) {
-            const int e = i / W, l = i % W;
-            lds[l * P + padx<R>(e)] = v[q];
+            for (int r = 0; r < RAD; ++r) f(b, r, j + r * S::NB);
         }
     }
 }
 
-template <typename R, int ROWS, int W, int P>
-__device__ __forceinline__ void store_cols(typename CT<R>::T* g, long rstride, const typename CT<R>::T* lds, int cv) {
-    constexpr int TOT = ROWS * W;
-    constexpr int NQ = (TOT + NT - 1) / NT;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = threadIdx.x + q * NT;
-        if ((TOT % NT) == 0 || i < TOT) {
-            const int e = i / W, l = i % W;
-            if (l < cv) g[(long)e * rstride + l] = lds[l * P + padx<R>(e)];
-        }
-    }
-}
-
-template <typename R, int E0, int E1, int W, int P>
-__device__ __forceinline__ void zero_rows(typename CT<R>::T* lds) {
-    using T = typename CT<R>::T;
-    constexpr int TOT = (E1 - E0) * W;
-    for (int i = threadIdx.x; i < TOT; i += NT) {
-        const int e = E0 + i / W, l = i % W;
-        lds[l * P + padx<R>(e)] = T{0, 0};
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Strided complex FFT of one axis.  Array viewed as [B0][rows][B2]; tile =
-// W columns of B2 at one b0 (blockIdx.y).  MODE 0: M rows in, M rows out.
-// MODE 1: M/2 rows in (zero padded to M), M rows out (padded forward).
-// MODE 2: M rows in, first M/2 rows out (cropped inverse).
+// Column-tile complex FFT of one strided axis, array [B0][N][B2], tile = W
+// columns of B2 at b0 = blockIdx.y, forward or inverse, in place allowed.
+// twN: exp(-2 pi i m/N), m < N.
 // ---------------------------------------------------------------------------
-template <typename R, int M, bool INV, int MODE>
-__global__ __launch_bounds__(NT) void k_strided(const typename CT<R>::T* in, typename CT<R>::T* out, int B2,
-                                                const typename CT<R>::T* __restrict__ tw) {
+template <typename R, int N, bool INV>
+__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
+                                                            int B2, const typename CT<R>::T* __restrict__ twN) {
     using T = typename CT<R>::T;
-    constexpr int W = StridedCfg<R>::W, TPL = StridedCfg<R>::TPL;
-    constexpr int RIN = (MODE == 1) ? M / 2 : M;
-    constexpr int ROUT = (MODE == 2) ? M / 2 : M;
-    constexpr int P = line_pitch<R>(M);
+    using C = ColCfg<R, N>;
+    constexpr int W = C::W, TPL = C::TPL;
+    constexpr int P = pitch_cols(N);
+    using F = Fft<T, N, INV, TPL, FwdPlan<N>>;
     __shared__ T lds[W * P];
+    const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = blockIdx.x * W;
-    const int cv = min(W, B2 - col0);
-    const T* gin = in + (long)blockIdx.y * RIN * B2 + col0;
-    T* gout = out + (long)blockIdx.y * ROUT * B2 + col0;
-    load_cols<R, RIN, W, P>(lds, gin, B2, cv);
-    if (MODE == 1) zero_rows<R, RIN, M, W, P>(lds);
-    const int line = threadIdx.x / TPL, jt = threadIdx.x % TPL;
-    fft_line<R, M, INV, TPL>(lds + line * P, jt, tw);
-    __syncthreads();
-    store_cols<R, ROUT, W, P>(gout, B2, lds, cv);
+    const bool lv = (col0 + l) < B2;
+    T* line = lds + l * P;
+    const T* g = in + (long)blockIdx.y * N * B2 + col0 + l;
+    T* o = out + (long)blockIdx.y * N * B2 + col0 + l;
+    {
+        typename F::In v;
+        typename F::Out u;
+        for_pos<N, TPL, F::R0>(jt, [&](int b, int r, int e) { v[b][r] = lv ? g[(long)e * B2] : T{0, 0}; });
+        F::run(v, u, line, jt, twN);
+        for_pos<N, TPL, F::RK>(jt, [&](int b, int r, int e) {
+            if (lv) o[(long)e * B2] = u[b][r];
+        });
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Contiguous-axis line kernel.
-//   MODE 0 (conv): lines of N = M/2 points, zero padded to M, forward FFT,
-//                  times the real multiplier K[row(line)][min(p, M-p)],
-//                  inverse FFT, first N points stored.
-//   MODE 1 (kin):  lines of N = M points, forward FFT, times the complex
-//                  table Q[row(line)][min(p, M-p)], inverse FFT.
-//   MODE 2 / 3:    plain forward / inverse FFT.
+// Zero-padded transforms of a strided axis as one length-M = 2N transform
+// per column: PAD = 1, forward, N rows in (the first stage skips the zero
+// half) and 2N rows out; PAD = 2, inverse, 2N rows in and only the first N
+// rows stored.
+// ---------------------------------------------------------------------------
+template <typename R, int M, int PAD>
+__global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typename CT<R>::T* in,
+                                                                   typename CT<R>::T* out, int B2,
+                                                                   const typename CT<R>::T* __restrict__ twM) {
+    using T = typename CT<R>::T;
+    using C = ColCfg<R, M>;
+    constexpr int W = C::W, TPL = C::TPL;
+    constexpr int P = pitch_cols(M);
+    constexpr bool INV = (PAD == 2);
+    using F = Fft<T, M, INV, TPL, FwdPlan<M>>;
+    __shared__ T lds[W * P];
+    const int l = threadIdx.x % W, jt = threadIdx.x / W;
+    const int col0 = blockIdx.x * W;
+    const bool lv = (col0 + l) < B2;
+    T* line = lds + l * P;
+    constexpr int RIN = (PAD == 1) ? M / 2 : M;
+    constexpr int ROUT = (PAD == 2) ? M / 2 : M;
+    const T* g = in + (long)blockIdx.y * RIN * B2 + col0 + l;
+    T* o = out + (long)blockIdx.y * ROUT * B2 + col0 + l;
+    typename F::In v;
+    typename F::Out u;
+    for_pos<M, TPL, F::R0>(jt, [&](int b, int r, int e) { v[b][r] = (lv && e < RIN) ? g[(long)e * B2] : T{0, 0}; });
+    F::run(v, u, line, jt, twM);
+    for_pos<M, TPL, F::RK>(jt, [&](int b, int r, int e) {
+        if (lv && e < ROUT) o[(long)e * B2] = u[b][r];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Contiguous-axis line kernel, lines of N points.
+//   MODE 0 (conv, used where 2N exceeds the longest compiled transform):
+//          zero-padded length-2N convolution by a real multiplier, computed
+//          as two length-N halves: sub-line h = 0 transforms x,
+//          h = 1 transforms x_n w^n (w = exp(-i pi/N)); their spectra are the
+//          even (p = 2k) and odd (p = 2k+1) frequencies of the padded line,
+//          multiplied by K[row(line)][min(p, 2N-p)]; after the inverse
+//          halves the line is y_n = ya_n + w^{-n} yb_n.
+//   MODE 1 (kin): forward FFT, times Q[row(line)][min(p, N-p)] (complex),
+//          inverse FFT.
+//   MODE 2 / 3: plain forward / inverse FFT.
 // row(line): i0 = line / D1, i1 = line % D1, folded by F0/F1 (0: no fold),
 // row = (k0*T1 + k1)*T2.
 // ---------------------------------------------------------------------------
-
 __device__ __forceinline__ int fold(int i, int F) { return (F == 0) ? i : min(i, F - i); }
 
-template <typename R, int M, int MODE>
-__global__ __launch_bounds__(256) void k_line(typename CT<R>::T* data, int nlines, const void* __restrict__ mult,
-                                              LineIdx li, const typename CT<R>::T* __restrict__ tw) {
+__device__ __forceinline__ long mult_row(int gl, const LineIdx& li) {
+    const int k0 = fold(gl / li.D1, li.F0), k1 = fold(gl % li.D1, li.F1);
+    return (long)(k0 * li.T1 + k1) * li.T2;
+}
+
+template <typename R, int N, int MODE>
+__global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
+    typename CT<R>::T* data, int nlines, const void* __restrict__ mult, LineIdx li,
+    const typename CT<R>::T* __restrict__ twN, const typename CT<R>::T* __restrict__ tw2) {
     using T = typename CT<R>::T;
-    using Cfg = LineCfg<R, M>;
-    constexpr int P = Cfg::P, TPL = Cfg::TPL, LPB = Cfg::LPB, NTH = Cfg::THREADS;
-    constexpr int N = (MODE == 0) ? M / 2 : M;
-    __shared__ T lds[LPB * P];
-    const int line0 = blockIdx.x * LPB;
-    const int lv = min(LPB, nlines - line0);
-    T* g = data + (long)line0 * N;
-    {
-        constexpr int TOT = LPB * N;
-        constexpr int NQ = (TOT + NTH - 1) / NTH;
-        T v[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NTH;
-            if ((TOT % NTH) == 0 || i < TOT) {
-                const int l = i / N;
-                v[q] = (l < lv) ? g[i] : T{0, 0};
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NTH;
-            if ((TOT % NTH) == 0 || i < TOT) {
-                const int l = i / N, e = i % N;
-                lds[l * P + padx<R>(e)] = v[q];
-            }
-        }
-        if (MODE == 0) {
-            for (int i = threadIdx.x; i < LPB * (M - N); i += NTH) {
-                const int l = i / (M - N), e = N + i % (M - N);
-                lds[l * P + padx<R>(e)] = T{0, 0};
-            }
-        }
-    }
-    const int line = threadIdx.x / TPL, jt = threadIdx.x % TPL;
-    if (MODE != 3) fft_line<R, M, false, TPL>(lds + line * P, jt, tw);
-    if (MODE == 0 || MODE == 1) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < LPB * M; i += NTH) {
-            const int l = i / M, p = i % M;
-            if (l < lv) {
-                const int gl = line0 + l;
-                const int k0 = fold(gl / li.D1, li.F0), k1 = fold(gl % li.D1, li.F1);
-                const long idx = (long)(k0 * li.T1 + k1) * li.T2 + min(p, M - p);
-                T x = lds[l * P + padx<R>(p)];
+    using C = LineCfg<R, N, MODE == 0>;
+    constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB, SUB = C::SUB;
+    using FF = Fft<T, N, false, TPL, FwdPlan<N>>;
+    using FI = Fft<T, N, true, TPL, InvPlan<N>>;
+    __shared__ T lds[LPB * SUB * P];
+    const int jt = threadIdx.x % TPL;
+    const int sl = threadIdx.x / TPL;  // sub-line
+    const int dl = sl / SUB, h = sl % SUB;
+    const int gl = blockIdx.x * LPB + dl;
+    const bool valid = gl < nlines;
+    T* line = lds + sl * P;
+    T* g = data + (long)gl * N;
+    if constexpr (MODE == 3) {
+        using FP = Fft<T, N, true, TPL, FwdPlan<N>>;
+        typename FP::In v;
+        typename FP::Out u;
+        for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = valid ? g[e] : T{0, 0}; });
+        FP::run(v, u, line, jt, twN);
+        for_pos<N, TPL, FP::RK>(jt, [&](int b, int r, int e) {
+            if (valid) g[e] = u[b][r];
+        });
+    } else {
+        typename FF::In v;
+        typename FF::Out u;
+        for_pos<N, TPL, FF::R0>(jt, [&](int b, int r, int e) {
+            T x = valid ? g[e] : T{0, 0};
+            if (MODE == 0 && h == 1) x = cmul(x, tw2[e]);
+            v[b][r] = x;
+        });
+        FF::run(v, u, line, jt, twN);
+        if constexpr (MODE == 2) {
+            for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
+                if (valid) g[e] = u[b][r];
+            });
+        } else {
+            const long row = valid ? mult_row(gl, li) : 0;
+            for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
                 if (MODE == 0) {
-                    const R k = static_cast<const R*>(mult)[idx];
-                    x = T{x.x * k, x.y * k};
+                    const int p = 2 * e + h;
+                    const R k = valid ? static_cast<const R*>(mult)[row + min(p, 2 * N - p)] : R(0);
+                    u[b][r] = T{u[b][r].x * k, u[b][r].y * k};
                 } else {
-                    x = cmul(x, static_cast<const T*>(mult)[idx]);
+                    const T q = valid ? static_cast<const T*>(mult)[row + min(e, N - e)] : T{0, 0};
+                    u[b][r] = cmul(u[b][r], q);
                 }
-                lds[l * P + padx<R>(p)] = x;
+            });
+            typename FI::Out w;
+            __syncthreads();
+            FI::run(u, w, line, jt, twN);
+            if constexpr (MODE == 1) {
+                for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+                    if (valid) g[e] = w[b][r];
+                });
+            } else {
+                // combine the halves: y = ya + w^{-n} yb (the odd half goes through LDS)
+                __syncthreads();
+                if (h == 1) {
+                    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) { line[padx(e)] = cmulc(w[b][r], tw2[e]); });
+                }
+                __syncthreads();
+                if (h == 0) {
+                    const T* other = line + P;
+                    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+                        if (valid) g[e] = cadd(w[b][r], other[padx(e)]);
+                    });
+                }
             }
-        }
-    }
-    if (MODE != 2) fft_line<R, M, true, TPL>(lds + line * P, jt, tw);
-    __syncthreads();
-    {
-        constexpr int TOT = LPB * N;
-        for (int i = threadIdx.x; i < TOT; i += NTH) {
-            const int l = i / N, e = i % N;
-            if (l < lv) g[i] = lds[l * P + padx<R>(e)];
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Axis-0 density + padded real-to-complex FFT.
+// The padded convolution along the contiguous axis as one length-M = 2N
+// transform per line (2N <= 512): the first stage skips the zero half, the multiplier is applied in
+// registers between the forward and the inverse, and only the first N points
+// are stored.
+// ---------------------------------------------------------------------------
+template <typename R, int M>
+__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
+    typename CT<R>::T* data, int nlines, const R* __restrict__ mult, LineIdx li,
+    const typename CT<R>::T* __restrict__ twM) {
+    using T = typename CT<R>::T;
+    using C = LineCfg<R, M, false>;
+    constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
+    constexpr int N = M / 2;
+    using FF = Fft<T, M, false, TPL, FwdPlan<M>>;
+    using FI = Fft<T, M, true, TPL, InvPlan<M>>;
+    __shared__ T lds[LPB * P];
+    const int jt = threadIdx.x % TPL;
+    const int dl = threadIdx.x / TPL;
+    const int gl = blockIdx.x * LPB + dl;
+    const bool valid = gl < nlines;
+    T* line = lds + dl * P;
+    T* g = data + (long)gl * N;
+    typename FF::In v;
+    typename FF::Out u;
+    for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (valid && e < N) ? g[e] : T{0, 0}; });
+    FF::run(v, u, line, jt, twM);
+    const long row = valid ? mult_row(gl, li) : 0;
+    for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) {
+        const R k = valid ? mult[row + min(p, M - p)] : R(0);
+        u[b][r] = T{u[b][r].x * k, u[b][r].y * k};
+    });
+    typename FI::Out w;
+    __syncthreads();
+    FI::run(u, w, line, jt, twM);
+    for_pos<M, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+        if (valid && e < N) g[e] = w[b][r];
+    });
+}
+
+// ---------------------------------------------------------------------------
+// Axis-0 density + padded real-to-complex FFT (column tiles over the C =
+// n/N0 columns).
 //   SRC 0: input is the state with the axis-0 inverse FFT pending;
 //   SRC 1: input is psi in physical space;
 //   SRC 2: input is a real density array.
 // Output X1[k][c], k = 0..N0: the length-2N0 DFT of (rho_0..rho_{N0-1}, 0..0)
-// at non-negative frequencies, from Z = FFT_N0(rho_2m + i rho_2m+1):
+// at non-negative frequencies, from Z = FFT_N0(rho_2m + i rho_2m+1) (zero for
+// m >= N0/2):
 //   X_k = (Z_k + conj Z_{N0-k})/2 + exp(-i pi k/N0) (Z_k - conj Z_{N0-k})/(2i).
 // ---------------------------------------------------------------------------
 template <typename R, int N0, int SRC>
-__global__ __launch_bounds__(NT) void k_r2c(const void* src, typename CT<R>::T* __restrict__ X1, int C,
-                                            const typename CT<R>::T* __restrict__ twN,
-                                            const typename CT<R>::T* __restrict__ tw2N) {
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* __restrict__ X1,
+                                                            int C, const typename CT<R>::T* __restrict__ twN,
+                                                            const typename CT<R>::T* __restrict__ tw2N) {
     using T = typename CT<R>::T;
-    constexpr int W = StridedCfg<R>::W, TPL = StridedCfg<R>::TPL;
-    constexpr int P = line_pitch<R>(N0 + 1);
+    using Cf = ColCfg<R, N0>;
+    constexpr int W = Cf::W, TPL = Cf::TPL;
+    constexpr int P = pitch_cols(N0 + 1);
+    using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;
+    using FF = Fft<T, N0, false, TPL, FwdPlan<N0>>;
     __shared__ T lds[W * P];
+    const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = blockIdx.x * W;
-    const int cv = min(W, C - col0);
-    const int line = threadIdx.x / TPL, jt = threadIdx.x % TPL;
-    if (SRC == 2) {
-        const R* g = static_cast<const R*>(src) + col0;
-        for (int i = threadIdx.x; i < N0 * W; i += NT) {
-            const int e = i / W, l = i % W;
-            const R r = (l < cv) ? g[(long)e * C + l] : R(0);
-            lds[l * P + padx<R>(e)] = T{r, R(0)};
-        }
-    } else {
-        load_cols<R, N0, W, P>(lds, static_cast<const T*>(src) + col0, C, cv);
-        if (SRC == 0) fft_line<R, N0, true, TPL>(lds + line * P, jt, twN);
-    }
-    __syncthreads();
-    // z_m = rho_{2m} + i rho_{2m+1} for m < N0/2, zero above.
-    {
-        constexpr int TOT = (N0 / 2) * W;
-        constexpr int NQ = (TOT + NT - 1) / NT;
-        T z[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int m = i / W, l = i % W;
-                const T a = lds[l * P + padx<R>(2 * m)];
-                const T b = lds[l * P + padx<R>(2 * m + 1)];
-                z[q] = (SRC == 2) ? T{a.x, b.x} : T{a.x * a.x + a.y * a.y, b.x * b.x + b.y * b.y};
-            }
-        }
+    const bool lv = (col0 + l) < C;
+    T* line = lds + l * P;
+    // density at the thread's positions, then into LDS (real part)
+    if constexpr (SRC == 0) {
+        const T* g = static_cast<const T*>(src) + col0 + l;
+        typename FI::In v;
+        typename FI::Out u;
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { v[b][r] = lv ? g[(long)e * C] : T{0, 0}; });
+        FI::run(v, u, line, jt, twN);
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int m = i / W, l = i % W;
-                lds[l * P + padx<R>(m)] = z[q];
-            }
-        }
-        zero_rows<R, N0 / 2, N0, W, P>(lds);
+        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+            line[padx(e)].x = u[b][r].x * u[b][r].x + u[b][r].y * u[b][r].y;
+        });
+    } else if constexpr (SRC == 1) {
+        const T* g = static_cast<const T*>(src) + col0 + l;
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) {
+            const T x = lv ? g[(long)e * C] : T{0, 0};
+            line[padx(e)].x = x.x * x.x + x.y * x.y;
+        });
+    } else {
+        const R* g = static_cast<const R*>(src) + col0 + l;
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { line[padx(e)].x = lv ? g[(long)e * C] : R(0); });
     }
-    fft_line<R, N0, false, TPL>(lds + line * P, jt, twN);
     __syncthreads();
-    T* g = X1 + col0;
-    for (int i = threadIdx.x; i < (N0 + 1) * W; i += NT) {
-        const int k = i / W, l = i % W;
-        if (l < cv) {
-            const T zk = lds[l * P + padx<R>(k == N0 ? 0 : k)];
-            const T zc = cconj(lds[l * P + padx<R>(k == 0 ? 0 : N0 - k)]);
-            const T ev = T{R(0.5) * (zk.x + zc.x), R(0.5) * (zk.y + zc.y)};
-            const T dv = csub(zk, zc);
-            const T ov = T{R(0.5) * dv.y, -R(0.5) * dv.x};  // (zk - zc)/(2i)
-            g[(long)k * C + l] = cadd(ev, cmul(tw2N[k], ov));
-        }
+    typename FF::In z;
+    typename FF::Out Z;
+    for_pos<N0, TPL, FF::R0>(jt, [&](int b, int r, int m) {
+        z[b][r] = (m < N0 / 2) ? T{line[padx(2 * m)].x, line[padx(2 * m + 1)].x} : T{0, 0};
+    });
+    __syncthreads();
+    FF::run(z, Z, line, jt, twN);
+    __syncthreads();
+    for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int k) { line[padx(k)] = Z[b][r]; });
+    __syncthreads();
+    T* gout = X1 + col0 + l;
+    for (int k = jt; k <= N0; k += TPL) {
+        const T zk = line[padx(k == N0 ? 0 : k)];
+        const T zc = cconj(line[padx(k == 0 ? 0 : N0 - k)]);
+        const T ev = T{R(0.5) * (zk.x + zc.x), R(0.5) * (zk.y + zc.y)};
+        const T dv = csub(zk, zc);
+        const T ov = T{R(0.5) * dv.y, -R(0.5) * dv.x};  // (zk - zc)/(2i)
+        if (lv) gout[(long)k * C] = cadd(ev, cmul(tw2N[k], ov));
     }
 }
 
 // ---------------------------------------------------------------------------
 // Axis-0 complex-to-real inverse (nonlocal potential) fused with the
-// nonlinear sub-step.
+// nonlinear sub-step (column tiles).
 //   MODE 0: Phi from X1; state S (axis-0 inverse pending) -> psi -> phase
 //           -> forward FFT of axis 0 -> S.
 //   MODE 1: no nonlocal term: psi -> phase -> forward FFT of axis 0.
@@ -303,129 +359,103 @@ __global__ __launch_bounds__(NT) void k_r2c(const void* src, typename CT<R>::T* 
 //   y = IFFT_N0(Z') unnormalised, Phi_{2m} = Re y_m, Phi_{2m+1} = Im y_m.
 // The GauSum multiplier already carries 1/prod(2 N_j).
 // ---------------------------------------------------------------------------
-
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__(NT) void k_c2r_phase(const typename CT<R>::T* __restrict__ X1, typename CT<R>::T* S,
-                                                  R* __restrict__ Phi_out, int C, PhaseArgs pa,
-                                                  const typename CT<R>::T* __restrict__ twN,
-                                                  const typename CT<R>::T* __restrict__ tw2N) {
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* __restrict__ X1,
+                                                                  typename CT<R>::T* S, R* __restrict__ Phi_out,
+                                                                  int C, PhaseArgs pa,
+                                                                  const typename CT<R>::T* __restrict__ twN,
+                                                                  const typename CT<R>::T* __restrict__ tw2N) {
     using T = typename CT<R>::T;
-    constexpr int W = StridedCfg<R>::W, TPL = StridedCfg<R>::TPL;
-    constexpr int P = line_pitch<R>(N0 + 1);
-    constexpr int TOT = N0 * W;
-    constexpr int NQ = (TOT + NT - 1) / NT;
+    using Cf = ColCfg<R, N0>;
+    constexpr int W = Cf::W, TPL = Cf::TPL;
+    constexpr int P = pitch_cols(N0 + 1);
+    using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;   // inverse transforms, outputs at radix-RK positions
+    using FF = Fft<T, N0, false, TPL, InvPlan<N0>>;  // forward after the phase, inputs at radix-RK positions
     __shared__ T lds[W * P];
+    const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = blockIdx.x * W;
-    const int cv = min(W, C - col0);
-    const int line = threadIdx.x / TPL, jt = threadIdx.x % TPL;
-    T sv[NQ];
-    R phi[NQ];
-    if (MODE != 2) {
-        const T* g = S + col0;
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int e = i / W, l = i % W;
-                sv[q] = (l < cv) ? g[(long)e * C + l] : T{0, 0};
-            }
-        }
-    }
-    if (MODE != 1) {
-        load_cols<R, N0 + 1, W, P>(lds, X1 + col0, C, cv);
+    const bool lv = (col0 + l) < C;
+    T* line = lds + l * P;
+    R phi[FI::BK][FI::RK];
+    if constexpr (MODE != 1) {
+        const T* gx = X1 + col0 + l;
+        for (int k = jt; k <= N0; k += TPL) line[padx(k)] = lv ? gx[(long)k * C] : T{0, 0};
         __syncthreads();
-        T zr[NQ];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int k = i / W, l = i % W;
-                const T xk = lds[l * P + padx<R>(k)];
-                const T xc = cconj(lds[l * P + padx<R>(N0 - k)]);
-                const T a = cadd(xk, xc);
-                const T b = cmulc(csub(xk, xc), tw2N[k]);  // exp(+i pi k/N0) (xk - xc)
-                zr[q] = T{a.x - b.y, a.y + b.x};           // a + i b
-            }
-        }
+        typename FI::In zc;
+        typename FI::Out y;
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int k) {
+            const T xk = line[padx(k)];
+            const T xc = cconj(line[padx(N0 - k)]);
+            const T a = cadd(xk, xc);
+            const T bb = cmulc(csub(xk, xc), tw2N[k]);  // exp(+i pi k/N0) (xk - xc)
+            zc[b][r] = T{a.x - bb.y, a.y + bb.x};       // a + i bb
+        });
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int k = i / W, l = i % W;
-                lds[l * P + padx<R>(k)] = zr[q];
-            }
-        }
-        fft_line<R, N0, true, TPL>(lds + line * P, jt, twN);
+        FI::run(zc, y, line, jt, twN);
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int i = threadIdx.x + q * NT;
-            if ((TOT % NT) == 0 || i < TOT) {
-                const int e = i / W, l = i % W;
-                const T y = lds[l * P + padx<R>(e >> 1)];
-                phi[q] = (e & 1) ? y.y : y.x;
+        // only y_m with m < N0/2 carry the physical samples Phi_0..Phi_{N0-1}
+        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int m) {
+            if (m < N0 / 2) {
+                line[padx(2 * m)].x = y[b][r].x;
+                line[padx(2 * m + 1)].x = y[b][r].y;
             }
-        }
-        if (MODE == 2) {
-            R* g = Phi_out + col0;
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const int i = threadIdx.x + q * NT;
-                if ((TOT % NT) == 0 || i < TOT) {
-                    const int e = i / W, l = i % W;
-                    if (l < cv) g[(long)e * C + l] = phi[q];
-                }
-            }
+        });
+        __syncthreads();
+        if constexpr (MODE == 2) {
+            R* go = Phi_out + col0 + l;
+            for (int e = jt; e < N0; e += TPL)
+                if (lv) go[(long)e * C] = line[padx(e)].x;
             return;
         }
+        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) { phi[b][r] = line[padx(e)].x; });
         __syncthreads();
     } else {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) phi[q] = R(0);
-    }
+        for (int b = 0; b < FI::BK; ++b)
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = threadIdx.x + q * NT;
-        if ((TOT % NT) == 0 || i < TOT) {
-            const int e = i / W, l = i % W;
-            lds[l * P + padx<R>(e)] = sv[q];
+            for (int r = 0; r < FI::RK; ++r) phi[b][r] = R(0);
+    }
+    if constexpr (MODE != 2) {
+        typename FI::In vs;
+        typename FI::Out psi;
+        {
+            const T* g = S + col0 + l;
+            for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { vs[b][r] = lv ? g[(long)e * C] : T{0, 0}; });
         }
-    }
-    fft_line<R, N0, true, TPL>(lds + line * P, jt, twN);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int i = threadIdx.x + q * NT;
-        if ((TOT % NT) == 0 || i < TOT) {
-            const int e = i / W, l = i % W;
-            const int c = col0 + l;
+        FI::run(vs, psi, line, jt, twN);
+        const int c = col0 + l;
+        R yv, zv;
+        if (pa.N2 > 0) {
+            yv = R(pa.y0 + (c / pa.N2) * pa.hy);
+            zv = R(pa.z0 + (c % pa.N2) * pa.hz);
+        } else {
+            yv = R(pa.y0 + c * pa.hy);
+            zv = R(0);
+        }
+        const R y2 = yv * yv;
+        const R base = R(pa.cz) * (zv * zv) + R(pa.ca - pa.cc) * y2;
+        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
             const R x = R(pa.x0 + e * pa.hx);
-            R y, z;
-            if (pa.N2 > 0) {
-                y = R(pa.y0 + (c / pa.N2) * pa.hy);
-                z = R(pa.z0 + (c % pa.N2) * pa.hz);
-            } else {
-                y = R(pa.y0 + c * pa.hy);
-                z = R(0);
-            }
-            const R x2 = x * x, y2 = y * y;
-            const R Pv = R(pa.ca) * (x2 + y2) + R(pa.cz) * (z * z) + R(pa.cc) * (x2 - y2) + R(pa.cs) * (R(2) * x * y);
-            T v = lds[l * P + padx<R>(e)];
+            const R Pv = base + R(pa.ca + pa.cc) * (x * x) + R(pa.cs) * (R(2) * x * yv);
+            const T v = psi[b][r];
             const R rho = v.x * v.x + v.y * v.y;
-            const R th = R(pa.bdt) * rho + R(pa.ldt) * phi[q] + Pv;
+            const R th = R(pa.bdt) * rho + R(pa.ldt) * phi[b][r] + Pv;
             R sn, cs;
             if constexpr (sizeof(R) == 4) {
                 sincosf(th, &sn, &cs);
             } else {
                 sincos(th, &sn, &cs);
             }
-            lds[l * P + padx<R>(e)] = T{v.x * cs + v.y * sn, v.y * cs - v.x * sn};  // v * exp(-i th)
-        }
+            psi[b][r] = T{v.x * cs + v.y * sn, v.y * cs - v.x * sn};  // v * exp(-i th)
+        });
+        typename FF::Out out;
+        __syncthreads();
+        FF::run(psi, out, line, jt, twN);
+        T* go = S + col0 + l;
+        for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int e) {
+            if (lv) go[(long)e * C] = out[b][r];
+        });
     }
-    fft_line<R, N0, false, TPL>(lds + line * P, jt, twN);
-    __syncthreads();
-    store_cols<R, N0, W, P>(S + col0, C, lds, cv);
 }
 
 // ---------------------------------------------------------------------------
@@ -656,6 +686,13 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
         }
         H[i] = h;
     }
+}
+
+// Plain streaming copy (HBM bandwidth calibration): 16-byte vectors,
+// grid-stride loop.
+static __global__ __launch_bounds__(256) void k_copy16(double2* __restrict__ dst, const double2* __restrict__ src,
+                                                       long n) {
+    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) dst[i] = src[i];
 }
 
 }  // namespace fse

@@ -15,12 +15,14 @@ bool strided_size_ok(int M);
 bool line_size_ok(int M);
 
 template <typename R> struct Launch {
-    // Strided FFT over [B0][rows][B2]; mode 0 plain, 1 padded forward (M/2 rows in), 2 cropped inverse.
-    static hipError_t strided(int M, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* tw,
-                              hipStream_t st);
-    // Contiguous line pass; mode 0 conv (lines of M/2, real multiplier), 1 kinetic (complex table), 2 fwd, 3 inv.
-    static hipError_t line(int M, int mode, void* data, int nlines, const void* mult, LineIdx li, const void* tw,
-                           hipStream_t st);
+    // Strided length-N FFT over [B0][rows][B2]; mode 0 plain (N -> N rows), 1 zero-padded forward
+    // (N -> 2N rows), 2 cropped inverse (2N -> N rows).  twN: length-N twiddles, tw2N: length 2N.
+    static hipError_t strided(int N, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* twN,
+                              const void* tw2N, hipStream_t st);
+    // Contiguous line pass on lines of N points; mode 0 padded conv (real multiplier over 2N frequencies),
+    // 1 kinetic (complex table), 2 fwd, 3 inv.
+    static hipError_t line(int N, int mode, void* data, int nlines, const void* mult, LineIdx li, const void* twN,
+                           const void* tw2N, hipStream_t st);
     // Axis-0 density + padded real-to-complex FFT; src 0 pending state, 1 physical psi, 2 real density.
     static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
                           hipStream_t st);
@@ -42,6 +44,8 @@ template <typename R> struct Launch {
                               const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
                               double g1, double g2, hipStream_t st);
 };
+
+hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);

@@ -15,9 +15,13 @@ bool strided_size_ok(int M) {
     return in_list(M, l, sizeof(l) / sizeof(l[0]));
 }
 
-bool line_size_ok(int M) {
-    static const int l[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024};
-    return in_list(M, l, sizeof(l) / sizeof(l[0]));
+bool line_size_ok(int M) { return strided_size_ok(M); }
+
+hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
+    long g = (n16 + 255) / 256;
+    if (g > 256L * 64L) g = 256L * 64L;  // 64 workgroups per CU, grid-stride beyond
+    k_copy16<<<(unsigned)g, 256, 0, st>>>(static_cast<double2*>(dst), static_cast<const double2*>(src), n16);
+    return hipGetLastError();
 }
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,

@@ -15,7 +15,7 @@ from typing import Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfse.so")
+LIB_PATH = os.environ.get("FSE_LIB", os.path.join(_PKG, "libfse.so"))
 
 FSE_OK = 0
 STATUS = {0: "FSE_OK", -1: "FSE_ERR_ARG", -2: "FSE_ERR_UNSUPPORTED", -3: "FSE_ERR_NOMEM",
@@ -29,6 +29,7 @@ EXPORTS = [
     "fse_set_time", "fse_get_time", "fse_step", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
+    "fse_device_copy",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -77,6 +78,7 @@ def lib():
         "fse_version": (ctypes.c_char_p, []),
         "fse_set_profiling": (st, [vp, i]),
         "fse_get_profile": (st, [vp, dp, ip, i]),
+        "fse_device_copy": (st, [vp, vp, ctypes.c_size_t, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -124,6 +126,11 @@ def gausum_symbol_host(d, N, L, kernel: Kernel) -> np.ndarray:
     _check(lib().fse_gausum_symbol_host(d, _iarr(N), _darr(L), ctypes.byref(kernel),
                                         out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.reshape(shape)
+
+
+def device_copy(dst, src, nbytes: int, stream=None):
+    """Streaming copy kernel (HBM calibration); dst/src are device tensors."""
+    _check(lib().fse_device_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
 
 
 def version() -> str:

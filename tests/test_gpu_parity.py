@@ -71,6 +71,15 @@ def P(name, **kw):
                          kernel="none", dt=1e-3, name="local2d"),
         local3d=W.Params(d=3, N=(24, 32, 48), L=(5.0, 6.0, 7.0), s=1.5, Omega=0.3, gamma=(1.1, 1.0, 1.5),
                          beta=20.0, lam=0.0, kernel="none", dt=1e-3, name="local3d"),
+        # 2D sizes whose padded contiguous length (768, 1024) exceeds the
+        # longest single transform: the convolution runs as two halves
+        big2d=W.Params(d=2, N=(384, 512), L=(8.0, 8.0), s=0.5, Omega=0.4, gamma=(1.0, 1.0), beta=500.0, lam=1.0,
+                       kernel="coulomb", dt=1e-3, name="big2d"),
+        big2d_t=W.Params(d=2, N=(512, 384), L=(8.0, 8.0), s=0.9, Omega=0.8, gamma=(1.0, 1.0), beta=500.0,
+                         lam=1.0, kernel="coulomb", dt=1e-3, name="big2d_t"),
+        # radix-3 lengths in every pass
+        rad3_3d=W.Params(d=3, N=(48, 96, 24), L=(6.0, 8.0, 4.0), s=0.6, Omega=0.4, gamma=(1.0, 0.9, 1.3),
+                         beta=100.0, lam=2.0, kernel="coulomb", dt=1e-3, name="rad3_3d"),
     )[name]
     return base.replace(**kw) if kw else base
 
@@ -81,7 +90,7 @@ def _psi0(p, seed=0):
     return W.anisotropic_gaussian(p.N, p.L, p.gamma, seed=seed)
 
 
-CASES = ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d"]
+CASES = ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -144,7 +153,7 @@ def test_split_calls_continue_the_trajectory():
     assert _rel(_host(a), ref) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d"])
+@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "big2d", "big2d_t", "rad3_3d"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_nonlocal_potential(name, prec):
     p = P(name)
