@@ -128,6 +128,60 @@ def run_precision(p, prec, steps, warmup, prof_steps):
     }
 
 
+def run_batch(steps, warmup=5):
+    """The batched sweep (64 2D instances, complex64, one graph) vs the same
+    instances one by one through the FP64 single-instance step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    params = W.batch_sweep(steps=steps)
+    states = [W.vortex_lattice_2d(p.N, p.L, seed=k) for k, p in enumerate(params)]
+    npts = sum(p.npts for p in params)
+    b = fse.Batch(params, fse.C64)
+    x = b.pack(states)
+    b.step(x, warmup)
+    b.step(x, steps)  # captures the graph for this step count
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(x, steps)  # replay
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    red = b.reduce(x).cpu().numpy()
+    del b, x
+    # the same instances through the FP64 single-instance path, one at a time
+    plans = [fse.Plan.from_params(p, fse.C128) for p in params]
+    ys = [torch.from_numpy(s).cuda() for s in states]
+    for pl, y, p in zip(plans, ys, params):
+        pl.step(y, warmup, p.dt)
+    torch.cuda.synchronize()
+    e0.record()
+    for pl, y, p in zip(plans, ys, params):
+        pl.step(y, steps, p.dt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms64 = e0.elapsed_time(e1)
+    del plans, ys
+    torch.cuda.empty_cache()
+    sizes = sorted({p.N[0] for p in params})
+    return {
+        "workload": (f"{len(params)} 2D instances, 16 each of " + ", ".join(f"{n}^2" for n in sizes)
+                     + ", s~U[0.3,1], Omega~U[0,0.9], beta=500, Coulomb GauSum, vortex-lattice psi0"),
+        "steps": steps,
+        "value": npts * steps / (ms * 1e-3),
+        "unit": "grid-point-steps/s",
+        "dtype": "c64 (FP64 reductions)",
+        "ms_per_step": ms / steps,
+        "fp64_single_one_by_one_value": npts * steps / (ms64 * 1e-3),
+        "speedup_vs_fp64_single": ms64 / ms,
+        "max_mass_drift": float(np.max(np.abs(red[:, 0] - 1.0))),
+    }
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=10):
     """Achieved bandwidth of the library's plain copy kernel (read + write bytes / time)."""
     import torch
@@ -187,6 +241,7 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched sweep (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the split step of one grid is not sharded here "
@@ -215,6 +270,11 @@ def main():
             "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
             "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"],
         }
+    if args.batch_steps > 0:
+        print(f"[bench] batched sweep, {args.batch_steps} steps", file=sys.stderr, flush=True)
+        variants["batch_c64"] = run_batch(args.batch_steps)
+        print(f"[bench] batch {variants['batch_c64']['ms_per_step']:.3f} ms/step, speedup "
+              f"{variants['batch_c64']['speedup_vs_fp64_single']:.2f}x", file=sys.stderr, flush=True)
     dom = max((k for k in r64["passes"] if k != "edge"),
               key=lambda k: r64["passes"][k]["avg_ms"] * r64["passes"][k]["launches"])
     dp = r64["passes"][dom]

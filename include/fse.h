@@ -142,6 +142,50 @@ fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fs
  * host memory.  FSE_ERR_STATE if the plan has no kernel. */
 fse_status fse_get_symbol(fse_plan plan, double* host_out);
 
+/* ---------------------------------------------------------------------------
+ * Batched sweep: many independent 2D instances (each its own grid, s, Omega,
+ * trap, interactions and time step), stepped together.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int N[2];          /* grid of this instance (same rules as fse_plan_create, d = 2) */
+    double L[2];       /* half-widths */
+    double s, Omega;   /* fractional order, rotation speed */
+    double gamma[2];   /* trap frequencies */
+    double beta, lambda;
+    double dt;         /* time step of this instance (finite, non-zero) */
+    double m;          /* mass term */
+    fse_kernel kernel; /* nonlocal kernel (kind FSE_K_NONE for none) */
+} fse_instance;
+
+typedef struct fse_batch_s* fse_batch; /* opaque; owned by the library */
+
+/* Build a batch of `count` 2D instances (count >= 1) in one precision.  The
+ * states live in one packed device buffer supplied by the caller: instance i
+ * occupies elements [offsets[i], offsets[i+1]) (fse_batch_offsets), laid out
+ * as [N0][N1].  Instances of equal grid size share their GauSum multiplier.
+ * Every instance's time starts at 0.  Synchronises `stream`. */
+fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst, int precision, void* stream);
+fse_status fse_batch_destroy(fse_batch batch);
+
+/* Element offsets of the instances in the packed buffer (count + 1 values,
+ * host memory owned by the caller). */
+fse_status fse_batch_offsets(fse_batch batch, size_t* offsets);
+
+/* nsteps TS2-GauSum steps of every instance (each with its own dt), in place
+ * on the packed buffer.  The pass sequence for a given (nsteps, buffer) is
+ * captured once into a HIP graph, one parallel branch per group of equal
+ * grid size, and replayed on `stream`; instance times live in device memory
+ * and advance by nsteps*dt_i per call. */
+fse_status fse_batch_step(fse_batch batch, void* psi_packed, int nsteps, void* stream);
+
+/* Per-instance diagnostics, out_dev[7*i + k] (device memory, count x 7):
+ * k = 0 mass, 1..6 = E_kin, E_pot, E_int, E_non, E_rot, E_total (as
+ * fse_energy, at the instance's current time). */
+fse_status fse_batch_reduce(fse_batch batch, const void* psi_packed, double* out_dev, void* stream);
+
+/* Current time of every instance (host memory, count values). */
+fse_status fse_batch_times(fse_batch batch, double* t);
+
 /* Per-pass timing for benchmarking.  While enabled, fse_step records a HIP
  * event pair on its stream around every kernel launch.  fse_get_profile
  * synchronises those events, adds the elapsed milliseconds per pass kind

@@ -515,35 +515,9 @@ void destroy(fse_plan p) {
 
 }  // namespace
 
-extern "C" {
-
-const char* fse_last_error(void) { return g_err.c_str(); }
-
-const char* fse_version(void) { return "fse-mi355x 0.1 (gfx950)"; }
-
-fse_status fse_plan_check(int d, const int* N, const double* L, double s, double Omega, const double* gamma,
-                          double beta, double lambda, const fse_kernel* kernel, int precision) {
-    g_err.clear();
-    return check_args(d, N, L, s, Omega, gamma, beta, lambda, kernel, precision);
-}
-
-fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fse_kernel* kernel, double* out) {
-    g_err.clear();
-    if (!kernel || !out) return fail(FSE_ERR_ARG, "kernel and out must not be NULL");
-    if (kernel->kind == FSE_K_NONE) return fail(FSE_ERR_ARG, "no kernel");
-    const double gam[3] = {0, 0, 0};
-    fse_status st = check_args(d, N, L, 1.0, 0.0, gam, 0.0, 1.0, kernel, FSE_C128);
-    if (st != FSE_OK) return st;
-    std::vector<double> k = fse::gausum_symbol(d, N, L, kernel->kind, kernel->mu, kernel->prefactor, kernel->delta,
-                                               kernel->ht);
-    std::memcpy(out, k.data(), k.size() * sizeof(double));
-    return FSE_OK;
-}
-
-fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, double s, double Omega,
-                           const double* gamma, double beta, double lambda, const fse_kernel* kernel, int precision,
-                           double m, void* stream) {
-    g_err.clear();
+static fse_status create_plan(fse_plan* out, int d, const int* N, const double* L, double s, double Omega,
+                              const double* gamma, double beta, double lambda, const fse_kernel* kernel, int precision,
+                              double m, void* stream, fse_plan donor) {
     if (!out) return fail(FSE_ERR_ARG, "out must not be NULL");
     *out = nullptr;
     fse_status st = check_args(d, N, L, s, Omega, gamma, beta, lambda, kernel, precision);
@@ -588,13 +562,22 @@ fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, 
             if ((st = upload_twiddles(p, 2 * N[j])) != FSE_OK) return bail(st);
         for (int j = 0; j < d; ++j)
             if ((st = upload_twiddles(p, N[j])) != FSE_OK) return bail(st);
-        p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor, p->kernel.delta,
-                                          p->kernel.ht);
+        if (donor && donor->khat) {
+            // same grid and kernel: share the donor's multiplier (not owned here)
+            p->khat_host = donor->khat_host;
+            p->khat = donor->khat;
+        } else {
+            p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor,
+                                              p->kernel.delta, p->kernel.ht);
+        }
         double scale = 1.0;
         for (int j = 0; j < d; ++j) scale /= (2.0 * N[j]);
         const size_t nk = p->khat_host.size();
-        if ((st = dev_alloc(p, &p->khat, nk * p->rsize)) != FSE_OK) return bail(st);
-        if (precision == FSE_C128) {
+        if (p->khat) {
+            // shared multiplier: nothing to upload
+        } else if ((st = dev_alloc(p, &p->khat, nk * p->rsize)) != FSE_OK) {
+            return bail(st);
+        } else if (precision == FSE_C128) {
             std::vector<double> v(nk);
             for (size_t i = 0; i < nk; ++i) v[i] = p->khat_host[i] * scale;
             if (hipMemcpy(p->khat, v.data(), nk * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -616,6 +599,154 @@ fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, 
     if (hipStreamSynchronize(hs) != hipSuccess) return bail(fail(FSE_ERR_HIP, "stream synchronisation failed"));
     *out = p;
     return FSE_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batched 2D sweep.
+// ---------------------------------------------------------------------------
+struct fse_batch_s {
+    int count = 0;
+    int prec = FSE_C128;
+    size_t csize = 16;
+    std::vector<fse_plan> plans;  // one per instance (workspace, kinetic tables, diagnostics)
+    std::vector<fse_instance> inst;
+    std::vector<size_t> off;      // count + 1 element offsets
+    std::vector<double> t_host;
+    double* t_dev = nullptr;
+    fse::BInst* d_all = nullptr;  // descriptors, grouped
+    struct Group {
+        int N0 = 0, N1 = 0;
+        bool nl = false;
+        std::vector<int> idx;
+        size_t first = 0;  // index of the group's first descriptor in d_all
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+    };
+    std::vector<Group> groups;
+    hipStream_t cap = nullptr;
+    hipEvent_t fork = nullptr;
+    std::map<std::pair<int, void*>, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+void batch_destroy(fse_batch b) {
+    if (!b) return;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& g : b->groups) {
+        if (g.s) (void)hipStreamDestroy(g.s);
+        if (g.done) (void)hipEventDestroy(g.done);
+    }
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->d_all) (void)hipFree(b->d_all);
+    if (b->t_dev) (void)hipFree(b->t_dev);
+    // plans sharing a multiplier do not own it; destroy them after its owner's users
+    for (auto it = b->plans.rbegin(); it != b->plans.rend(); ++it) destroy(*it);
+    delete b;
+}
+
+template <typename R> fse_status batch_record_group(fse_batch b, const fse_batch_s::Group& g, void* psi, int nsteps) {
+    using L = fse::Launch<R>;
+    const fse_plan rep = b->plans[g.idx[0]];
+    const int N0 = g.N0, N1 = g.N1, cnt = (int)g.idx.size();
+    const fse::BInst* d = b->d_all + g.first;
+    const fse::LineIdx lk{1, N0, 0, 1, N1 / 2 + 1};
+    const fse::LineIdx lc{1, 0, 0, 1, N1 + 1};
+    void* a0 = rep->tw[N0];
+    void* b0 = rep->tw[2 * N0];
+    void* a1 = rep->tw[N1];
+    void* b1 = g.nl ? rep->tw[2 * N1] : nullptr;
+    hipStream_t st = g.s;
+    HIPCHK(L::batch(0, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
+    HIPCHK(L::batch(2, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
+    for (int k = 0; k < nsteps; ++k) {
+        if (g.nl) {
+            HIPCHK(L::batch(3, N0, N1, psi, d, cnt, 0, lc, a0, b0, a1, b1, st));
+            HIPCHK(L::batch(4, N0, N1, psi, d, cnt, 0, lc, a0, b0, a1, b1, st));
+            HIPCHK(L::batch(5, N0, N1, psi, d, cnt, k, lc, a0, b0, a1, b1, st));
+        } else {
+            HIPCHK(L::batch(6, N0, N1, psi, d, cnt, k, lc, a0, b0, a1, b1, st));
+        }
+        HIPCHK(L::batch(2, N0, N1, psi, d, cnt, (k == nsteps - 1) ? 0 : 1, lk, a0, b0, a1, b1, st));
+    }
+    HIPCHK(L::batch(1, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
+    return FSE_OK;
+}
+
+fse_status batch_capture(fse_batch b, void* psi, int nsteps, hipGraphExec_t* exec) {
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    fse_status s = FSE_OK;
+    auto end_capture = [&]() {
+        hipGraph_t gr = nullptr;
+        (void)hipStreamEndCapture(b->cap, &gr);
+        if (gr) (void)hipGraphDestroy(gr);
+    };
+    if (hipEventRecord(b->fork, b->cap) != hipSuccess) {
+        end_capture();
+        return fail(FSE_ERR_HIP, "event record during capture failed");
+    }
+    for (auto& g : b->groups) {
+        if (hipStreamWaitEvent(g.s, b->fork, 0) != hipSuccess) {
+            end_capture();
+            return fail(FSE_ERR_HIP, "stream fork during capture failed");
+        }
+        s = (b->prec == FSE_C128) ? batch_record_group<double>(b, g, psi, nsteps)
+                                  : batch_record_group<float>(b, g, psi, nsteps);
+        if (s != FSE_OK) {
+            end_capture();
+            return s;
+        }
+        if (hipEventRecord(g.done, g.s) != hipSuccess || hipStreamWaitEvent(b->cap, g.done, 0) != hipSuccess) {
+            end_capture();
+            return fail(FSE_ERR_HIP, "stream join during capture failed");
+        }
+    }
+    if (fse::launch_batch_time(b->d_all, b->count, nsteps, b->cap) != hipSuccess) {
+        end_capture();
+        return fail(FSE_ERR_HIP, "time update launch failed");
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamEndCapture(b->cap, &graph));
+    hipError_t e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(FSE_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    return FSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fse_last_error(void) { return g_err.c_str(); }
+
+const char* fse_version(void) { return "fse-mi355x 0.1 (gfx950)"; }
+
+fse_status fse_plan_check(int d, const int* N, const double* L, double s, double Omega, const double* gamma,
+                          double beta, double lambda, const fse_kernel* kernel, int precision) {
+    g_err.clear();
+    return check_args(d, N, L, s, Omega, gamma, beta, lambda, kernel, precision);
+}
+
+fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fse_kernel* kernel, double* out) {
+    g_err.clear();
+    if (!kernel || !out) return fail(FSE_ERR_ARG, "kernel and out must not be NULL");
+    if (kernel->kind == FSE_K_NONE) return fail(FSE_ERR_ARG, "no kernel");
+    const double gam[3] = {0, 0, 0};
+    fse_status st = check_args(d, N, L, 1.0, 0.0, gam, 0.0, 1.0, kernel, FSE_C128);
+    if (st != FSE_OK) return st;
+    std::vector<double> k = fse::gausum_symbol(d, N, L, kernel->kind, kernel->mu, kernel->prefactor, kernel->delta,
+                                               kernel->ht);
+    std::memcpy(out, k.data(), k.size() * sizeof(double));
+    return FSE_OK;
+}
+
+fse_status fse_plan_create(fse_plan* out, int d, const int* N, const double* L, double s, double Omega,
+                           const double* gamma, double beta, double lambda, const fse_kernel* kernel, int precision,
+                           double m, void* stream) {
+    g_err.clear();
+    return create_plan(out, d, N, L, s, Omega, gamma, beta, lambda, kernel, precision, m, stream, nullptr);
 }
 
 fse_status fse_plan_destroy(fse_plan plan) {
@@ -695,6 +826,194 @@ fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev,
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 2, out_dev, st)
                                   : reduce_impl<float>(plan, psi, 2, out_dev, st);
+}
+
+
+fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst, int precision, void* stream) {
+    g_err.clear();
+    if (!out || !inst || count < 1) return fail(FSE_ERR_ARG, "out, inst must not be NULL and count >= 1");
+    *out = nullptr;
+    if (precision != FSE_C128 && precision != FSE_C64) return fail(FSE_ERR_ARG, "unknown precision %d", precision);
+    for (int i = 0; i < count; ++i) {
+        const fse_instance& q = inst[i];
+        fse_status st = check_args(2, q.N, q.L, q.s, q.Omega, q.gamma, q.beta, q.lambda, &q.kernel, precision);
+        if (st != FSE_OK) {
+            const std::string m = g_err;
+            return fail(st, "instance %d: %s", i, m.c_str());
+        }
+        if (!std::isfinite(q.dt) || q.dt == 0.0) return fail(FSE_ERR_ARG, "instance %d: dt must be finite, non-zero", i);
+        if (!(q.m >= 0.0) || !std::isfinite(q.m)) return fail(FSE_ERR_ARG, "instance %d: m must be finite, >= 0", i);
+    }
+    fse_batch b = new fse_batch_s();
+    b->count = count;
+    b->prec = precision;
+    b->csize = (precision == FSE_C128) ? 16 : 8;
+    b->inst.assign(inst, inst + count);
+    b->off.assign(count + 1, 0);
+    b->t_host.assign(count, 0.0);
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    auto bail = [&](fse_status e) {
+        const std::string m = g_err;
+        batch_destroy(b);
+        g_err = m;
+        return e;
+    };
+    for (int i = 0; i < count; ++i) {
+        const fse_instance& q = inst[i];
+        b->off[i + 1] = b->off[i] + (size_t)q.N[0] * q.N[1];
+        fse_plan donor = nullptr;
+        for (int j = 0; j < i; ++j) {
+            const fse_instance& r = inst[j];
+            if (r.N[0] == q.N[0] && r.N[1] == q.N[1] && r.L[0] == q.L[0] && r.L[1] == q.L[1] &&
+                r.kernel.kind == q.kernel.kind && r.kernel.mu == q.kernel.mu &&
+                r.kernel.prefactor == q.kernel.prefactor && r.kernel.delta == q.kernel.delta &&
+                r.kernel.ht == q.kernel.ht && b->plans[j]->khat) {
+                donor = b->plans[j];
+                break;
+            }
+        }
+        fse_plan p = nullptr;
+        fse_status st = create_plan(&p, 2, q.N, q.L, q.s, q.Omega, q.gamma, q.beta, q.lambda, &q.kernel, precision,
+                                    q.m, stream, donor);
+        if (st != FSE_OK) return bail(st);
+        b->plans.push_back(p);
+        void* tab = nullptr;
+        st = (precision == FSE_C128) ? kin_table<double>(p, 0.5 * q.dt, 0, &tab, hs)
+                                     : kin_table<float>(p, 0.5 * q.dt, 0, &tab, hs);
+        if (st != FSE_OK) return bail(st);
+        st = (precision == FSE_C128) ? kin_table<double>(p, q.dt, 1, &tab, hs) : kin_table<float>(p, q.dt, 1, &tab, hs);
+        if (st != FSE_OK) return bail(st);
+    }
+    // groups of equal size (and presence of the nonlocal term)
+    for (int i = 0; i < count; ++i) {
+        const fse_plan p = b->plans[i];
+        bool placed = false;
+        for (auto& g : b->groups)
+            if (g.N0 == p->N[0] && g.N1 == p->N[1] && g.nl == p->nl) {
+                g.idx.push_back(i);
+                placed = true;
+                break;
+            }
+        if (!placed) {
+            fse_batch_s::Group g;
+            g.N0 = p->N[0];
+            g.N1 = p->N[1];
+            g.nl = p->nl;
+            g.idx.push_back(i);
+            b->groups.push_back(g);
+        }
+    }
+    if (hipMalloc((void**)&b->t_dev, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_NOMEM, "hipMalloc"));
+    if (hipMemset(b->t_dev, 0, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_HIP, "hipMemset"));
+    std::vector<fse::BInst> desc;
+    for (auto& g : b->groups) {
+        g.first = desc.size();
+        for (int i : g.idx) {
+            const fse_plan p = b->plans[i];
+            const fse_instance& q = inst[i];
+            fse::BInst d{};
+            d.psi_off = (long)b->off[i];
+            d.X1 = p->X1;
+            d.khat = p->khat;
+            d.kin0 = p->kin[0];
+            d.kin1 = p->kin[1];
+            d.t = b->t_dev + i;
+            d.dt = q.dt;
+            d.Omega = q.Omega;
+            const double gx2 = q.gamma[0] * q.gamma[0], gy2 = q.gamma[1] * q.gamma[1];
+            d.ca = q.dt * (gx2 + gy2) / 4.0;
+            d.gdiff = (gx2 - gy2) / 4.0;
+            d.bdt = q.beta * q.dt;
+            d.ldt = q.lambda * q.dt;
+            d.x0 = -q.L[0];
+            d.hx = p->h[0];
+            d.y0 = -q.L[1];
+            d.hy = p->h[1];
+            desc.push_back(d);
+        }
+        if (hipStreamCreateWithFlags(&g.s, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(FSE_ERR_HIP, "stream/event creation failed"));
+    }
+    if (hipMalloc((void**)&b->d_all, sizeof(fse::BInst) * desc.size()) != hipSuccess)
+        return bail(fail(FSE_ERR_NOMEM, "hipMalloc"));
+    if (hipMemcpy(b->d_all, desc.data(), sizeof(fse::BInst) * desc.size(), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(FSE_ERR_HIP, "descriptor upload failed"));
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+        return bail(fail(FSE_ERR_HIP, "stream/event creation failed"));
+    if (hipStreamSynchronize(hs) != hipSuccess) return bail(fail(FSE_ERR_HIP, "stream synchronisation failed"));
+    *out = b;
+    return FSE_OK;
+}
+
+fse_status fse_batch_destroy(fse_batch batch) {
+    g_err.clear();
+    if (!batch) return FSE_OK;
+    (void)hipDeviceSynchronize();
+    batch_destroy(batch);
+    return FSE_OK;
+}
+
+fse_status fse_batch_offsets(fse_batch batch, size_t* offsets) {
+    g_err.clear();
+    if (!batch || !offsets) return fail(FSE_ERR_ARG, "batch and offsets must not be NULL");
+    for (int i = 0; i <= batch->count; ++i) offsets[i] = batch->off[i];
+    return FSE_OK;
+}
+
+fse_status fse_batch_times(fse_batch batch, double* t) {
+    g_err.clear();
+    if (!batch || !t) return fail(FSE_ERR_ARG, "batch and t must not be NULL");
+    for (int i = 0; i < batch->count; ++i) t[i] = batch->t_host[i];
+    return FSE_OK;
+}
+
+fse_status fse_batch_step(fse_batch batch, void* psi_packed, int nsteps, void* stream) {
+    g_err.clear();
+    if (!batch || !psi_packed) return fail(FSE_ERR_ARG, "batch and psi_packed must not be NULL");
+    if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
+    if (nsteps == 0) return FSE_OK;
+    const auto key = std::make_pair(nsteps, psi_packed);
+    auto it = batch->graphs.find(key);
+    hipGraphExec_t exec = nullptr;
+    if (it == batch->graphs.end()) {
+        if (batch->graphs.size() >= 8) {
+            HIPCHK(hipDeviceSynchronize());
+            for (auto& kv : batch->graphs) (void)hipGraphExecDestroy(kv.second);
+            batch->graphs.clear();
+        }
+        fse_status s = batch_capture(batch, psi_packed, nsteps, &exec);
+        if (s != FSE_OK) return s;
+        batch->graphs[key] = exec;
+    } else {
+        exec = it->second;
+    }
+    HIPCHK(hipGraphLaunch(exec, static_cast<hipStream_t>(stream)));
+    for (int i = 0; i < batch->count; ++i) {
+        batch->t_host[i] += nsteps * batch->inst[i].dt;
+        batch->plans[i]->t = batch->t_host[i];
+    }
+    return FSE_OK;
+}
+
+fse_status fse_batch_reduce(fse_batch batch, const void* psi_packed, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!batch || !psi_packed || !out_dev) return fail(FSE_ERR_ARG, "batch, psi_packed and out_dev must not be NULL");
+    const char* base = static_cast<const char*>(psi_packed);
+    for (int i = 0; i < batch->count; ++i) {
+        fse_plan p = batch->plans[i];
+        p->t = batch->t_host[i];
+        const void* psi = base + batch->off[i] * batch->csize;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        fse_status s = (p->prec == FSE_C128) ? reduce_impl<double>(p, psi, 0, out_dev + 7 * i, st)
+                                             : reduce_impl<float>(p, psi, 0, out_dev + 7 * i, st);
+        if (s != FSE_OK) return s;
+        s = (p->prec == FSE_C128) ? reduce_impl<double>(p, psi, 1, out_dev + 7 * i + 1, st)
+                                  : reduce_impl<float>(p, psi, 1, out_dev + 7 * i + 1, st);
+        if (s != FSE_OK) return s;
+    }
+    return FSE_OK;
 }
 
 fse_status fse_set_profiling(fse_plan plan, int enable) {

@@ -81,20 +81,19 @@ template <int N, int TPL, int RAD, typename F> __device__ __forceinline__ void f
 // twN: exp(-2 pi i m/N), m < N.
 // ---------------------------------------------------------------------------
 template <typename R, int N, bool INV>
-__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
-                                                            int B2, const typename CT<R>::T* __restrict__ twN) {
+__device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename CT<R>::T* out,
+                                                            int B2, const typename CT<R>::T* twN, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using C = ColCfg<R, N>;
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols(N);
     using F = Fft<T, N, INV, TPL, FwdPlan<N>>;
-    __shared__ T lds[W * P];
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
-    const int col0 = blockIdx.x * W;
+    const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
     T* line = lds + l * P;
-    const T* g = in + (long)blockIdx.y * N * B2 + col0 + l;
-    T* o = out + (long)blockIdx.y * N * B2 + col0 + l;
+    const T* g = in + (long)by * N * B2 + col0 + l;
+    T* o = out + (long)by * N * B2 + col0 + l;
     {
         typename F::In v;
         typename F::Out u;
@@ -106,6 +105,13 @@ __global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<
     }
 }
 
+template <typename R, int N, bool INV>
+__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
+                                                            int B2, const typename CT<R>::T* twN) {
+    __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols(N)];
+    cols_body<R, N, INV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Zero-padded transforms of a strided axis as one length-M = 2N transform
 // per column: PAD = 1, forward, N rows in (the first stage skips the zero
@@ -113,24 +119,23 @@ __global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<
 // rows stored.
 // ---------------------------------------------------------------------------
 template <typename R, int M, int PAD>
-__global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typename CT<R>::T* in,
+__device__ __forceinline__ void cols_full_body(const typename CT<R>::T* in,
                                                                    typename CT<R>::T* out, int B2,
-                                                                   const typename CT<R>::T* __restrict__ twM) {
+                                                                   const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using C = ColCfg<R, M>;
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols(M);
     constexpr bool INV = (PAD == 2);
     using F = Fft<T, M, INV, TPL, FwdPlan<M>>;
-    __shared__ T lds[W * P];
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
-    const int col0 = blockIdx.x * W;
+    const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
     T* line = lds + l * P;
     constexpr int RIN = (PAD == 1) ? M / 2 : M;
     constexpr int ROUT = (PAD == 2) ? M / 2 : M;
-    const T* g = in + (long)blockIdx.y * RIN * B2 + col0 + l;
-    T* o = out + (long)blockIdx.y * ROUT * B2 + col0 + l;
+    const T* g = in + (long)by * RIN * B2 + col0 + l;
+    T* o = out + (long)by * ROUT * B2 + col0 + l;
     typename F::In v;
     typename F::Out u;
     for_pos<M, TPL, F::R0>(jt, [&](int b, int r, int e) { v[b][r] = (lv && e < RIN) ? g[(long)e * B2] : T{0, 0}; });
@@ -138,6 +143,14 @@ __global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typenam
     for_pos<M, TPL, F::RK>(jt, [&](int b, int r, int e) {
         if (lv && e < ROUT) o[(long)e * B2] = u[b][r];
     });
+}
+
+template <typename R, int M, int PAD>
+__global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typename CT<R>::T* in,
+                                                                   typename CT<R>::T* out, int B2,
+                                                                   const typename CT<R>::T* twM) {
+    __shared__ typename CT<R>::T lds[ColCfg<R, M>::W * pitch_cols(M)];
+    cols_full_body<R, M, PAD>(in, out, B2, twM, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -163,19 +176,18 @@ __device__ __forceinline__ long mult_row(int gl, const LineIdx& li) {
 }
 
 template <typename R, int N, int MODE>
-__global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
-    typename CT<R>::T* data, int nlines, const void* __restrict__ mult, LineIdx li,
-    const typename CT<R>::T* __restrict__ twN, const typename CT<R>::T* __restrict__ tw2) {
+__device__ __forceinline__ void lines_body(
+    typename CT<R>::T* data, int nlines, const void* mult, LineIdx li,
+    const typename CT<R>::T* twN, const typename CT<R>::T* tw2, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using C = LineCfg<R, N, MODE == 0>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB, SUB = C::SUB;
     using FF = Fft<T, N, false, TPL, FwdPlan<N>>;
     using FI = Fft<T, N, true, TPL, InvPlan<N>>;
-    __shared__ T lds[LPB * SUB * P];
     const int jt = threadIdx.x % TPL;
     const int sl = threadIdx.x / TPL;  // sub-line
     const int dl = sl / SUB, h = sl % SUB;
-    const int gl = blockIdx.x * LPB + dl;
+    const int gl = bx * LPB + dl;
     const bool valid = gl < nlines;
     T* line = lds + sl * P;
     T* g = data + (long)gl * N;
@@ -238,6 +250,14 @@ __global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
     }
 }
 
+template <typename R, int N, int MODE>
+__global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
+    typename CT<R>::T* data, int nlines, const void* mult, LineIdx li,
+    const typename CT<R>::T* twN, const typename CT<R>::T* tw2) {
+    __shared__ typename CT<R>::T lds[LineCfg<R, N, (MODE) == 0>::LPB * LineCfg<R, N, (MODE) == 0>::SUB * LineCfg<R, N, (MODE) == 0>::P];
+    lines_body<R, N, MODE>(data, nlines, mult, li, twN, tw2, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // The padded convolution along the contiguous axis as one length-M = 2N
 // transform per line (2N <= 512): the first stage skips the zero half, the multiplier is applied in
@@ -245,19 +265,18 @@ __global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
 // are stored.
 // ---------------------------------------------------------------------------
 template <typename R, int M>
-__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
-    typename CT<R>::T* data, int nlines, const R* __restrict__ mult, LineIdx li,
-    const typename CT<R>::T* __restrict__ twM) {
+__device__ __forceinline__ void conv_full_body(
+    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
+    const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using C = LineCfg<R, M, false>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
     constexpr int N = M / 2;
     using FF = Fft<T, M, false, TPL, FwdPlan<M>>;
     using FI = Fft<T, M, true, TPL, InvPlan<M>>;
-    __shared__ T lds[LPB * P];
     const int jt = threadIdx.x % TPL;
     const int dl = threadIdx.x / TPL;
-    const int gl = blockIdx.x * LPB + dl;
+    const int gl = bx * LPB + dl;
     const bool valid = gl < nlines;
     T* line = lds + dl * P;
     T* g = data + (long)gl * N;
@@ -278,6 +297,14 @@ __global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
     });
 }
 
+template <typename R, int M>
+__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
+    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
+    const typename CT<R>::T* twM) {
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LPB * LineCfg<R, M, false>::P];
+    conv_full_body<R, M>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Axis-0 density + padded real-to-complex FFT (column tiles over the C =
 // n/N0 columns).
@@ -290,18 +317,17 @@ __global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
 //   X_k = (Z_k + conj Z_{N0-k})/2 + exp(-i pi k/N0) (Z_k - conj Z_{N0-k})/(2i).
 // ---------------------------------------------------------------------------
 template <typename R, int N0, int SRC>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* __restrict__ X1,
-                                                            int C, const typename CT<R>::T* __restrict__ twN,
-                                                            const typename CT<R>::T* __restrict__ tw2N) {
+__device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
+                                                            int C, const typename CT<R>::T* twN,
+                                                            const typename CT<R>::T* tw2N, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using Cf = ColCfg<R, N0>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols(N0 + 1);
     using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;
     using FF = Fft<T, N0, false, TPL, FwdPlan<N0>>;
-    __shared__ T lds[W * P];
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
-    const int col0 = blockIdx.x * W;
+    const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
     T* line = lds + l * P;
     // density at the thread's positions, then into LDS (real part)
@@ -347,6 +373,14 @@ __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, t
     }
 }
 
+template <typename R, int N0, int SRC>
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* X1,
+                                                            int C, const typename CT<R>::T* twN,
+                                                            const typename CT<R>::T* tw2N) {
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    r2c_body<R, N0, SRC>(src, X1, C, twN, tw2N, blockIdx.x, blockIdx.y, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Axis-0 complex-to-real inverse (nonlocal potential) fused with the
 // nonlinear sub-step (column tiles).
@@ -360,20 +394,19 @@ __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, t
 // The GauSum multiplier already carries 1/prod(2 N_j).
 // ---------------------------------------------------------------------------
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* __restrict__ X1,
-                                                                  typename CT<R>::T* S, R* __restrict__ Phi_out,
+__device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
+                                                                  typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
-                                                                  const typename CT<R>::T* __restrict__ twN,
-                                                                  const typename CT<R>::T* __restrict__ tw2N) {
+                                                                  const typename CT<R>::T* twN,
+                                                                  const typename CT<R>::T* tw2N, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
     using Cf = ColCfg<R, N0>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols(N0 + 1);
     using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;   // inverse transforms, outputs at radix-RK positions
     using FF = Fft<T, N0, false, TPL, InvPlan<N0>>;  // forward after the phase, inputs at radix-RK positions
-    __shared__ T lds[W * P];
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
-    const int col0 = blockIdx.x * W;
+    const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
     T* line = lds + l * P;
     R phi[FI::BK][FI::RK];
@@ -456,6 +489,115 @@ __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_c2r_phase(const typena
             if (lv) go[(long)e * C] = out[b][r];
         });
     }
+}
+
+template <typename R, int N0, int MODE>
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* X1,
+                                                                  typename CT<R>::T* S, R* Phi_out,
+                                                                  int C, PhaseArgs pa,
+                                                                  const typename CT<R>::T* twN,
+                                                                  const typename CT<R>::T* tw2N) {
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    c2r_phase_body<R, N0, MODE>(X1, S, Phi_out, C, pa, twN, tw2N, blockIdx.x, blockIdx.y, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2D passes: blockIdx.y selects the instance of a group of equal-size
+// instances; the tile index is blockIdx.x as in the single-instance kernels.
+//   KIND 0 / 1: forward / inverse FFT of axis 0 (column tiles over N1)
+//   KIND 2:     kinetic line pass (which = 0: dt/2 table, 1: dt table)
+//   KIND 3:     density + padded real-to-complex FFT of axis 0
+//   KIND 4:     padded convolution along axis 1
+//   KIND 5 / 6: complex-to-real + nonlinear phase (with / without nonlocal
+//               term) at t_n = *t + which * dt
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
+    const double tn = *b.t + kstep * b.dt;
+    const double f = (b.Omega == 0.0) ? b.dt : sin(b.Omega * b.dt) / b.Omega;
+    PhaseArgs pa;
+    pa.x0 = b.x0;
+    pa.hx = b.hx;
+    pa.y0 = b.y0;
+    pa.hy = b.hy;
+    pa.z0 = 0.0;
+    pa.hz = 0.0;
+    pa.N2 = 0;
+    pa.ca = b.ca;
+    pa.cz = 0.0;
+    pa.cc = (b.Omega == 0.0) ? b.gdiff * b.dt : b.gdiff * cos(b.Omega * (2.0 * tn + b.dt)) * f;
+    pa.cs = (b.Omega == 0.0) ? 0.0 : b.gdiff * sin(b.Omega * (2.0 * tn + b.dt)) * f;
+    pa.bdt = b.bdt;
+    pa.ldt = b.ldt;
+    return pa;
+}
+
+template <typename R, int N0, bool INV>
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_cols(void* psi, const BInst* bi, int N1,
+                                                                const typename CT<R>::T* twN0) {
+    using T = typename CT<R>::T;
+    T* x = static_cast<T*>(psi) + bi[blockIdx.y].psi_off;
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0)];
+    cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds);
+}
+
+template <typename R, int N1>
+__global__ __launch_bounds__((LineCfg<R, N1, false>::NTH)) void k_b_kin(void* psi, const BInst* bi,
+                                                                       int N0, int which, LineIdx li,
+                                                                       const typename CT<R>::T* twN1) {
+    using T = typename CT<R>::T;
+    const BInst& b = bi[blockIdx.y];
+    __shared__ typename CT<R>::T lds[LineCfg<R, N1, (1) == 0>::LPB * LineCfg<R, N1, (1) == 0>::SUB * LineCfg<R, N1, (1) == 0>::P];
+    lines_body<R, N1, 1>(static_cast<T*>(psi) + b.psi_off, N0, which ? b.kin1 : b.kin0, li, twN1, nullptr, blockIdx.x,
+                         0, lds);
+}
+
+template <typename R, int N0>
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_r2c(void* psi, const BInst* bi, int N1,
+                                                               const typename CT<R>::T* twN0,
+                                                               const typename CT<R>::T* tw2N0) {
+    using T = typename CT<R>::T;
+    const BInst& b = bi[blockIdx.y];
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    r2c_body<R, N0, 0>(static_cast<const T*>(psi) + b.psi_off, static_cast<T*>(b.X1), N1, twN0, tw2N0, blockIdx.x, 0, lds);
+}
+
+template <typename R, int M>
+__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_b_conv_full(const BInst* bi, int nlines,
+                                                                            LineIdx li,
+                                                                            const typename CT<R>::T* twM) {
+    using T = typename CT<R>::T;
+    const BInst& b = bi[blockIdx.y];
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LPB * LineCfg<R, M, false>::P];
+    conv_full_body<R, M>(static_cast<T*>(b.X1), nlines, static_cast<const R*>(b.khat), li, twM, blockIdx.x, 0, lds);
+}
+
+template <typename R, int N1>
+__global__ __launch_bounds__((LineCfg<R, N1, true>::NTH)) void k_b_conv_halves(
+    const BInst* bi, int nlines, LineIdx li, const typename CT<R>::T* twN1,
+    const typename CT<R>::T* tw2N1) {
+    using T = typename CT<R>::T;
+    const BInst& b = bi[blockIdx.y];
+    __shared__ typename CT<R>::T lds[LineCfg<R, N1, (0) == 0>::LPB * LineCfg<R, N1, (0) == 0>::SUB * LineCfg<R, N1, (0) == 0>::P];
+    lines_body<R, N1, 0>(static_cast<T*>(b.X1), nlines, b.khat, li, twN1, tw2N1, blockIdx.x, 0, lds);
+}
+
+template <typename R, int N0, int MODE>
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_c2r_phase(void* psi, const BInst* bi,
+                                                                     int N1, int kstep,
+                                                                     const typename CT<R>::T* twN0,
+                                                                     const typename CT<R>::T* tw2N0) {
+    using T = typename CT<R>::T;
+    const BInst& b = bi[blockIdx.y];
+    const PhaseArgs pa = batch_phase(b, kstep);
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    c2r_phase_body<R, N0, MODE>(static_cast<const T*>(b.X1), static_cast<T*>(psi) + b.psi_off, nullptr, N1, pa, twN0,
+                                tw2N0, blockIdx.x, 0, lds);
+}
+
+// Advances every instance's time by nsteps * dt (one thread per instance).
+static __global__ void k_b_time(const BInst* __restrict__ bi, int count, int nsteps) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) *bi[i].t += nsteps * bi[i].dt;
 }
 
 // ---------------------------------------------------------------------------

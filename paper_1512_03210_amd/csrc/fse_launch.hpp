@@ -29,6 +29,10 @@ template <typename R> struct Launch {
     // Axis-0 complex-to-real + nonlinear phase; mode 0 full, 1 phase only, 2 potential output only.
     static hipError_t c2r_phase(int N0, int mode, const void* X1, void* S, void* Phi, int C, const PhaseArgs& pa,
                                 const void* twN, const void* tw2N, hipStream_t st);
+    // Batched 2D pass over `count` equal-size instances (kinds in fse_kernels.hpp).
+    static hipError_t batch(int kind, int N0, int N1, void* psi, const BInst* bi, int count, int which, LineIdx li,
+                            const void* twN0, const void* tw2N0, const void* twN1, const void* tw2N1,
+                            hipStream_t st);
     static hipError_t build_kin(void* Q, int T0, int T1, int T2, double dmu0, double dmu1, double dmu2, double s,
                                 double m2, double tau, double scale, hipStream_t st);
     static hipError_t red_local(const void* psi, const void* Phi, long n, const GridGeom& g, double wa, double wz,
@@ -44,6 +48,8 @@ template <typename R> struct Launch {
                               const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
                               double g1, double g2, hipStream_t st);
 };
+
+hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st);
 
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 

@@ -17,6 +17,11 @@ bool strided_size_ok(int M) {
 
 bool line_size_ok(int M) { return strided_size_ok(M); }
 
+hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st) {
+    k_b_time<<<(count + 63) / 64, 64, 0, st>>>(bi, count, nsteps);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
     long g = (n16 + 255) / 256;
     if (g > 256L * 64L) g = 256L * 64L;  // 64 workgroups per CU, grid-stride beyond

@@ -28,4 +28,21 @@ struct GridGeom {
     double x0, hx, y0, hy, z0, hz;
 };
 
+// One instance of a batched 2D sweep (device memory).  The state lives at
+// psi_base + psi_off (elements) of the packed buffer passed to each launch;
+// *t is the instance's time at the start of the call.
+struct BInst {
+    long psi_off;
+    void* X1;            // axis-0 real-to-complex workspace, (N0+1) x N1
+    const void* khat;    // GauSum multiplier (carries 1/(4 N0 N1)), or null
+    const void* kin0;    // kinetic table for dt/2 (carries 1/(N0 N1))
+    const void* kin1;    // kinetic table for dt
+    double* t;
+    double dt, Omega;
+    double ca;           // dt (gx^2 + gy^2)/4
+    double gdiff;        // (gx^2 - gy^2)/4
+    double bdt, ldt;     // beta dt, lambda dt
+    double x0, hx, y0, hy;
+};
+
 }  // namespace fse

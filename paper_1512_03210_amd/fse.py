@@ -29,7 +29,8 @@ EXPORTS = [
     "fse_set_time", "fse_get_time", "fse_step", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
-    "fse_device_copy",
+    "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
+    "fse_batch_reduce", "fse_batch_times",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -43,6 +44,12 @@ class FseError(RuntimeError):
 class Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("mu", ctypes.c_double), ("prefactor", ctypes.c_double),
                 ("n", ctypes.c_double * 3), ("delta", ctypes.c_double), ("ht", ctypes.c_double)]
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int * 2), ("L", ctypes.c_double * 2), ("s", ctypes.c_double),
+                ("Omega", ctypes.c_double), ("gamma", ctypes.c_double * 2), ("beta", ctypes.c_double),
+                ("lam", ctypes.c_double), ("dt", ctypes.c_double), ("m", ctypes.c_double), ("kernel", Kernel)]
 
 
 _lib = None
@@ -79,6 +86,12 @@ def lib():
         "fse_set_profiling": (st, [vp, i]),
         "fse_get_profile": (st, [vp, dp, ip, i]),
         "fse_device_copy": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "fse_batch_create": (st, [ctypes.POINTER(vp), i, ctypes.POINTER(Instance), i, vp]),
+        "fse_batch_destroy": (st, [vp]),
+        "fse_batch_offsets": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "fse_batch_step": (st, [vp, vp, i, vp]),
+        "fse_batch_reduce": (st, [vp, vp, vp, vp]),
+        "fse_batch_times": (st, [vp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -261,3 +274,75 @@ class Plan:
         out = np.zeros(int(np.prod(shape)), dtype=np.float64)
         _check(lib().fse_get_symbol(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out.reshape(shape)
+
+
+class Batch:
+    """Batched sweep over 2D instances (wraps fse_batch); states in one packed tensor."""
+
+    def __init__(self, params, precision: int = C64, stream=None):
+        import torch
+        self.params = list(params)
+        self.count = len(self.params)
+        self.precision = precision
+        self.cdtype = torch.complex128 if precision == C128 else torch.complex64
+        arr = (Instance * self.count)()
+        for k, p in enumerate(self.params):
+            if p.d != 2:
+                raise ValueError("batched instances are 2D")
+            q = arr[k]
+            q.N = (ctypes.c_int * 2)(*p.N)
+            q.L = (ctypes.c_double * 2)(*p.L)
+            q.s, q.Omega, q.beta, q.lam, q.dt, q.m = p.s, p.Omega, p.beta, p.lam, p.dt, p.m
+            q.gamma = (ctypes.c_double * 2)(*p.gamma)
+            q.kernel = make_kernel(p.kernel, mu=p.mu, prefactor=p.c) if p.kernel != "none" else make_kernel("none")
+        self._h = ctypes.c_void_p()
+        _check(lib().fse_batch_create(ctypes.byref(self._h), self.count, arr, precision, _stream(stream)))
+        off = (ctypes.c_size_t * (self.count + 1))()
+        _check(lib().fse_batch_offsets(self._h, off))
+        self.offsets = [int(x) for x in off]
+
+    def close(self):
+        if self._h:
+            _check(lib().fse_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, states):
+        """Packed device tensor from a list of numpy arrays (one per instance)."""
+        import torch
+        flat = np.concatenate([np.asarray(s).ravel() for s in states])
+        if flat.size != self.offsets[-1]:
+            raise ValueError("state sizes do not match the batch")
+        np_dtype = np.complex128 if self.precision == C128 else np.complex64
+        return torch.from_numpy(flat.astype(np_dtype)).to("cuda")
+
+    def unpack(self, packed):
+        h = packed.detach().cpu().numpy()
+        return [h[self.offsets[k]:self.offsets[k + 1]].reshape(self.params[k].N) for k in range(self.count)]
+
+    def _check_packed(self, packed):
+        if packed.dtype != self.cdtype or packed.numel() != self.offsets[-1] or not packed.is_contiguous():
+            raise ValueError("packed state has the wrong dtype or size")
+
+    def step(self, packed, nsteps: int, stream=None):
+        self._check_packed(packed)
+        _check(lib().fse_batch_step(self._h, _ptr(packed), int(nsteps), _stream(stream)))
+        return packed
+
+    def reduce(self, packed, stream=None):
+        """Device tensor (count, 7): mass, E_kin, E_pot, E_int, E_non, E_rot, E_total."""
+        import torch
+        self._check_packed(packed)
+        out = torch.empty(self.count * 7, dtype=torch.float64, device=packed.device)
+        _check(lib().fse_batch_reduce(self._h, _ptr(packed), _ptr(out), _stream(stream)))
+        return out.view(self.count, 7)
+
+    def times(self):
+        t = (ctypes.c_double * self.count)()
+        _check(lib().fse_batch_times(self._h, t))
+        return list(t)

@@ -1,0 +1,141 @@
+"""GPU parity of the batched 2D sweep (graph-captured, one branch per grid size)."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import diagnostics as dg
+from oracle import scheme
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1512_03210_amd import fse  # noqa: E402
+
+
+def _note(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fse.lib()
+
+
+def _instances():
+    base = dict(L=(8.0, 8.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0)
+    return [
+        W.Params(d=2, N=(64, 64), s=0.75, Omega=0.5, gamma=(1.0, 1.0), dt=1e-3, name="a", **base),
+        W.Params(d=2, N=(64, 64), s=0.4, Omega=0.9, gamma=(1.0, 1.3), dt=2e-3, name="b", **base),
+        W.Params(d=2, N=(96, 96), s=1.1, Omega=0.2, gamma=(1.2, 1.0), dt=1e-3, name="c", **base),
+        W.Params(d=2, N=(64, 48), s=0.9, Omega=0.0, gamma=(1.0, 1.0), dt=5e-4, name="d", **base),
+        W.Params(d=2, N=(128, 128), s=0.6, Omega=0.7, gamma=(1.0, 1.0), dt=1e-3, name="e",
+                 **dict(base, beta=500.0)),
+        W.Params(d=2, N=(64, 64), s=0.8, Omega=0.3, gamma=(1.0, 1.1), dt=1e-3, name="f",
+                 **dict(base, lam=0.0, kernel="none")),
+    ]
+
+
+def _states(params, seed0=10):
+    return [W.harmonic_vortex_2d(p.N, p.L, seed=seed0 + k) for k, p in enumerate(params)]
+
+
+def _oracle(params, states, nsteps):
+    out = []
+    for p, s in zip(params, states):
+        pr = scheme.Problem.from_params(p)
+        out.append(pr.run(s, nsteps, p.dt)[0])
+    return out
+
+
+@pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-11), (fse.C64, 1e-5)])
+def test_batch_matches_oracle_per_instance(prec, tol):
+    params = _instances()
+    states = _states(params)
+    ref = _oracle(params, states, 4)
+    b = fse.Batch(params, prec)
+    x = b.pack(states)
+    b.step(x, 4)
+    torch.cuda.synchronize()
+    for k, (got, r) in enumerate(zip(b.unpack(x), ref)):
+        err = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+        _note(f"[batch] prec={prec} instance {params[k].name} N={params[k].N}: {err:.3e}")
+        assert err < tol
+    assert np.allclose(b.times(), [4 * p.dt for p in params], rtol=0, atol=1e-15)
+
+
+def test_batch_graph_replays_with_eager_work_between():
+    params = _instances()
+    states = _states(params, seed0=20)
+    b = fse.Batch(params, fse.C128)
+    x = b.pack(states)
+    other = fse.Plan.from_params(W.preset("cfg1"), fse.C128)
+    y = torch.from_numpy(W.harmonic_vortex_2d((64, 64), (8.0, 8.0), seed=1)).cuda()
+    for rep in range(1, 4):
+        b.step(x, 2)          # first call captures, the others replay the same graph
+        other.step(y, 3, 1e-3)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        ref = _oracle(params, states, 2 * rep)
+        for k, (got, r) in enumerate(zip(b.unpack(x), ref)):
+            err = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+            assert err < 1e-11, (rep, k, err)
+
+
+def test_batch_equals_single_instance_plans():
+    params = _instances()
+    states = _states(params, seed0=30)
+    b = fse.Batch(params, fse.C64)
+    x = b.pack(states)
+    b.step(x, 3)
+    got = b.unpack(x)
+    for k, p in enumerate(params):
+        plan = fse.Plan.from_params(p, fse.C64)
+        y = torch.from_numpy(states[k].astype(np.complex64)).cuda()
+        plan.step(y, 3, p.dt)
+        err = float(np.linalg.norm(got[k] - y.cpu().numpy()) / np.linalg.norm(got[k]))
+        assert err < 1e-6, (k, err)
+
+
+def test_batch_reduce():
+    params = _instances()
+    states = _states(params, seed0=40)
+    b = fse.Batch(params, fse.C128)
+    x = b.pack(states)
+    b.step(x, 3)
+    red = b.reduce(x).cpu().numpy()
+    for k, (p, s) in enumerate(zip(params, b.unpack(x))):
+        pr = scheme.Problem.from_params(p)
+        eo = np.array(dg.energy_parts(pr, s, t=3 * p.dt))
+        assert abs(red[k, 0] - dg.mass(s, p.N, p.L)) < 1e-12
+        assert np.all(np.abs(red[k, 1:] - eo) <= 1e-11 * np.maximum(1.0, np.abs(eo)))
+
+
+def test_batch_invalid():
+    bad = _instances()[:1] + [W.Params(d=2, N=(62, 64), L=(8.0, 8.0), s=0.5, Omega=0.1, gamma=(1.0, 1.0),
+                                       beta=1.0, lam=1.0, dt=1e-3)]
+    with pytest.raises(fse.FseError):
+        fse.Batch(bad, fse.C64)
+
+
+def test_full_sweep_sampled_against_fp64_single_plans():
+    # The benchmarked sweep: 64 instances, 16 each of 128^2, 256^2, 384^2, 512^2.
+    params = W.batch_sweep()
+    states = [W.vortex_lattice_2d(p.N, p.L, seed=k) for k, p in enumerate(params)]
+    b = fse.Batch(params, fse.C64)
+    x = b.pack(states)
+    b.step(x, 5)
+    red = b.reduce(x).cpu().numpy()
+    got = b.unpack(x)
+    for k in (0, 17, 38, 63):  # one instance of every size
+        p = params[k]
+        plan = fse.Plan.from_params(p, fse.C128)
+        y = torch.from_numpy(states[k]).cuda()
+        plan.step(y, 5, p.dt)
+        ref = y.cpu().numpy()
+        err = float(np.linalg.norm(got[k] - ref) / np.linalg.norm(ref))
+        _note(f"[sweep] instance {k} N={p.N} s={p.s:.3f} Omega={p.Omega:.3f}: c64 vs c128 {err:.3e}")
+        assert err < 1e-5
+    assert np.max(np.abs(red[:, 0] - 1.0)) < 1e-5
