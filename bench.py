@@ -27,6 +27,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "grid-point-steps/s and % HBM roofline, 3D 256³ split step, FP32-batched vs FP64"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_m0_256cube.json")
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: measured traffic is only reported for the kernels it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1512_03210_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hpp", ".inc", ".hip")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(pass_name, precision):
+    """HBM bytes per launch from the rocprofv3 counter runs, if taken on the current kernels."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    entry = rec.get("passes", {}).get(precision, {}).get(pass_name)
+    return None if entry is None else entry["read_bytes"] + entry["write_bytes"]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -285,7 +311,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dp["gbs"] / HBM_PEAK_GBS, 4),
-        "traffic": None,
+        "traffic": measured_traffic(dom, "c128"),
         "bytes_per_launch": dp["bytes_per_launch"],
         "avg_ms": dp["avg_ms"],
     }
@@ -324,6 +350,7 @@ def main():
         "variants": variants,
         "passes": r64["passes"],
         "mass_after": r64["mass_after"],
+        "kernel_source_hash": kernel_source_hash(),
     }
     print(json.dumps(out), flush=True)
 

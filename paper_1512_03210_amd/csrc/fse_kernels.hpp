@@ -830,11 +830,19 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
     }
 }
 
-// Plain streaming copy (HBM bandwidth calibration): 16-byte vectors,
-// grid-stride loop.
-static __global__ __launch_bounds__(256) void k_copy16(double2* __restrict__ dst, const double2* __restrict__ src,
-                                                       long n) {
-    for (long i = blockIdx.x * 256L + threadIdx.x; i < n; i += (long)gridDim.x * 256L) dst[i] = src[i];
+// Plain streaming copy (HBM bandwidth calibration): 16-byte vectors, four
+// independent loads in flight per thread, grid-stride loop.
+static __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src, long n) {
+    const long stride = (long)gridDim.x * 256L;
+    long i = blockIdx.x * 256L + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+        dst[i] = a;
+        dst[i + stride] = b;
+        dst[i + 2 * stride] = c;
+        dst[i + 3 * stride] = d;
+    }
+    for (; i < n; i += stride) dst[i] = src[i];
 }
 
 }  // namespace fse
