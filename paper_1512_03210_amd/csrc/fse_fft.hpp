@@ -51,6 +51,49 @@ template <bool INV, typename T> __device__ __forceinline__ T twmul(T a, T w) {
 }
 
 // ---------------------------------------------------------------------------
+// Sine and cosine.
+// FP64: Cody-Waite reduction x = k pi/2 + r with pi/2 split into three doubles
+// (the first two with 33 significant bits, so k*P1 and k*P2 are exact for
+// |k| < 2^20; beyond that the reduction error stays within a few ulp of x, the
+// rounding the argument itself carries), then the Taylor series of sin and
+// cos on |r| <= pi/4 to degree 19 and 20 (truncation below 1e-22) and the
+// quadrant k mod 4.  FP32: the library routine.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fsincos(double x, double* s, double* c) {
+    const double k = rint(x * 0.6366197723675814);  // 2/pi
+    double r = fma(-k, 1.5707963267341256, x);
+    r = fma(-k, 6.077100506303966e-11, r);
+    r = fma(-k, 2.0222662487959506e-21, r);
+    const double r2 = r * r;
+    double ps = -8.22063524662433e-18;  // -1/19!
+    ps = fma(ps, r2, 2.8114572543455206e-15);
+    ps = fma(ps, r2, -7.647163731819816e-13);
+    ps = fma(ps, r2, 1.6059043836821613e-10);
+    ps = fma(ps, r2, -2.505210838544172e-08);
+    ps = fma(ps, r2, 2.7557319223985893e-06);
+    ps = fma(ps, r2, -0.0001984126984126984);
+    ps = fma(ps, r2, 0.008333333333333333);
+    ps = fma(ps, r2, -0.16666666666666666);
+    const double sn = fma(r * r2, ps, r);
+    double pc = 4.110317623312165e-19;  // 1/20!
+    pc = fma(pc, r2, -1.5619206968586225e-16);
+    pc = fma(pc, r2, 4.779477332387385e-14);
+    pc = fma(pc, r2, -1.1470745597729725e-11);
+    pc = fma(pc, r2, 2.08767569878681e-09);
+    pc = fma(pc, r2, -2.755731922398589e-07);
+    pc = fma(pc, r2, 2.48015873015873e-05);
+    pc = fma(pc, r2, -0.001388888888888889);
+    pc = fma(pc, r2, 0.041666666666666664);
+    pc = fma(pc, r2, -0.5);
+    const double cs = fma(r2, pc, 1.0);
+    const int q = (int)(k - 4.0 * floor(0.25 * k));  // k mod 4, exact for any integral k
+    *s = (q == 0) ? sn : (q == 1) ? cs : (q == 2) ? -sn : -cs;
+    *c = (q == 0) ? cs : (q == 1) ? -sn : (q == 2) ? -cs : sn;
+}
+
+__device__ __forceinline__ void fsincos(float x, float* s, float* c) { sincosf(x, s, c); }
+
+// ---------------------------------------------------------------------------
 // Radix-R DFTs in registers.
 // ---------------------------------------------------------------------------
 template <int R, bool INV> struct DFT;
@@ -198,16 +241,22 @@ template <int R0, int R1, int R2, int... Rs> struct Mid<RList<R0, R1, R2, Rs...>
 };
 
 // ---------------------------------------------------------------------------
-// LDS layout: one pad element every 16 elements; the line pitch is chosen by
-// the kernel for its lane order.
+// LDS layout: one pad element every 16 elements (8 for length 512); the line
+// pitch is chosen by the kernel for its lane order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int padx(int e) { return e + (e >> 4); }
+// Pad granularity per transform length: one pad element every 2^value
+// elements (every 8 for the 512-point plan: about 1% faster there, neutral
+// elsewhere).
+template <int M> struct PadShift {
+    static constexpr int value = (M == 512) ? 3 : 4;
+};
+template <int M> __device__ __forceinline__ int padx(int e) { return e + (e >> PadShift<M>::value); }
 
 constexpr int round_up(int x, int m) { return ((x + m - 1) / m) * m; }
 // Lanes that differ in the line index first (column tiles): pitch = 2 mod 32.
-constexpr int pitch_cols(int E) { return round_up(E + E / 16 + 1, 32) + 2; }
+template <int M> constexpr int pitch_cols(int E) { return round_up(E + (E >> PadShift<M>::value) + 1, 32) + 2; }
 // Lanes that differ in the position first (whole lines): pitch = 16 mod 32.
-constexpr int pitch_lines(int E) { return round_up(E + E / 16, 32) + 16; }
+template <int M> constexpr int pitch_lines(int E) { return round_up(E + (E >> PadShift<M>::value), 32) + 16; }
 
 // ---------------------------------------------------------------------------
 // Stage primitives.  A thread owns butterflies j = jt + b*TPL (b < B) of its
@@ -271,7 +320,7 @@ __device__ __forceinline__ void put(const T (&v)[B][RAD], T* line, int jt) {
         if (S::active(j)) {
             const int base = (j / NS) * NS * RAD + j % NS;
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) line[padx(base + r * NS)] = v[b][r];
+            for (int r = 0; r < RAD; ++r) line[padx<M>(base + r * NS)] = v[b][r];
         }
     }
 }
@@ -286,7 +335,7 @@ __device__ __forceinline__ void get(T (&v)[B][RAD], const T* line, int jt) {
         const int j = jt + b * TPL;
         if (S::active(j)) {
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) v[b][r] = line[padx(j + r * S::NB)];
+            for (int r = 0; r < RAD; ++r) v[b][r] = line[padx<M>(j + r * S::NB)];
         }
     }
 }

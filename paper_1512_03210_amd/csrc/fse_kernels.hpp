@@ -36,12 +36,25 @@ namespace fse {
 //   Line tiles (contiguous axis): LPB whole lines, lanes ordered
 //   position-fastest.
 // ---------------------------------------------------------------------------
-template <typename R, int N> struct ColCfg {
+template <int N, typename PL> struct PlanOf { using L = PL; };
+template <int N> struct PlanOf<N, void> { using L = FwdPlan<N>; };
+
+// Column tile: W columns of 128 B, TPL threads per column (the plan's first
+// radix sets the points per thread); PL = void selects the plain plan.
+template <typename R, int N, typename PL = void> struct ColCfg {
     static constexpr int W = (sizeof(R) == 8) ? 8 : 16;
-    static constexpr int TPL0 = N / Head<FwdPlan<N>>::value;
+    static constexpr int TPL0 = N / Head<typename PlanOf<N, PL>::L>::value;
     static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 * W > 512 ? 512 / W : TPL0);
     static constexpr int NTH = W * TPL;
 };
+
+// Radix plan of the fused complex-to-real + nonlinear phase kernel: in FP64
+// it keeps three arrays per thread live, so where the plain plan gives a
+// thread 16 points this one gives it 8 (one more LDS exchange per transform,
+// half the registers per array: occupancy 4 instead of 2).
+template <typename R, int N> struct FusedPlan { using L = void; };
+template <> struct FusedPlan<double, 256> { using L = RList<8, 8, 4>; };
+template <typename R, int N> using FusedCfg = ColCfg<R, N, typename FusedPlan<R, N>::L>;
 
 constexpr int floor_pow2(int x) {
     int p = 1;
@@ -51,7 +64,7 @@ constexpr int floor_pow2(int x) {
 
 template <typename R, int N, bool CONV> struct LineCfg {
     using T = typename CT<R>::T;
-    static constexpr int P = (sizeof(R) == 8) ? (N + N / 16) : pitch_lines(N);
+    static constexpr int P = (sizeof(R) == 8) ? (N + (N >> PadShift<N>::value)) : pitch_lines<N>(N);
     static constexpr int TPL0 = N / Head<FwdPlan<N>>::value;
     static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 > 64 ? 64 : TPL0);
     static constexpr int SUB = CONV ? 2 : 1;  // LDS sub-lines (and thread groups) per data line
@@ -75,6 +88,16 @@ template <int N, int TPL, int RAD, typename F> __device__ __forceinline__ void f
     }
 }
 
+// Calls f(i, k) for the rows k = jt + i*TPL <= N that the thread owns (N + 1
+// rows), unrolled so that the loads in f issue together.
+template <int N, int TPL, typename F> __device__ __forceinline__ void for_rows_incl(int jt, F f) {
+#pragma unroll
+    for (int i = 0; i < (N + TPL) / TPL; ++i) {
+        const int k = jt + i * TPL;
+        if (k <= N) f(i, k);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Column-tile complex FFT of one strided axis, array [B0][N][B2], tile = W
 // columns of B2 at b0 = blockIdx.y, forward or inverse, in place allowed.
@@ -86,7 +109,7 @@ __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename 
     using T = typename CT<R>::T;
     using C = ColCfg<R, N>;
     constexpr int W = C::W, TPL = C::TPL;
-    constexpr int P = pitch_cols(N);
+    constexpr int P = pitch_cols<N>(N);
     using F = Fft<T, N, INV, TPL, FwdPlan<N>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
@@ -108,7 +131,7 @@ __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename 
 template <typename R, int N, bool INV>
 __global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
                                                             int B2, const typename CT<R>::T* twN) {
-    __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols(N)];
+    __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols<N>(N)];
     cols_body<R, N, INV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds);
 }
 
@@ -125,7 +148,7 @@ __device__ __forceinline__ void cols_full_body(const typename CT<R>::T* in,
     using T = typename CT<R>::T;
     using C = ColCfg<R, M>;
     constexpr int W = C::W, TPL = C::TPL;
-    constexpr int P = pitch_cols(M);
+    constexpr int P = pitch_cols<M>(M);
     constexpr bool INV = (PAD == 2);
     using F = Fft<T, M, INV, TPL, FwdPlan<M>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
@@ -149,7 +172,7 @@ template <typename R, int M, int PAD>
 __global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typename CT<R>::T* in,
                                                                    typename CT<R>::T* out, int B2,
                                                                    const typename CT<R>::T* twM) {
-    __shared__ typename CT<R>::T lds[ColCfg<R, M>::W * pitch_cols(M)];
+    __shared__ typename CT<R>::T lds[ColCfg<R, M>::W * pitch_cols<M>(M)];
     cols_full_body<R, M, PAD>(in, out, B2, twM, blockIdx.x, blockIdx.y, lds);
 }
 
@@ -236,13 +259,13 @@ __device__ __forceinline__ void lines_body(
                 // combine the halves: y = ya + w^{-n} yb (the odd half goes through LDS)
                 __syncthreads();
                 if (h == 1) {
-                    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) { line[padx(e)] = cmulc(w[b][r], tw2[e]); });
+                    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) { line[padx<N>(e)] = cmulc(w[b][r], tw2[e]); });
                 }
                 __syncthreads();
                 if (h == 0) {
                     const T* other = line + P;
                     for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
-                        if (valid) g[e] = cadd(w[b][r], other[padx(e)]);
+                        if (valid) g[e] = cadd(w[b][r], other[padx<N>(e)]);
                     });
                 }
             }
@@ -323,7 +346,7 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
     using T = typename CT<R>::T;
     using Cf = ColCfg<R, N0>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
-    constexpr int P = pitch_cols(N0 + 1);
+    constexpr int P = pitch_cols<N0>(N0 + 1);
     using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;
     using FF = Fft<T, N0, false, TPL, FwdPlan<N0>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
@@ -339,45 +362,45 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
         FI::run(v, u, line, jt, twN);
         __syncthreads();
         for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
-            line[padx(e)].x = u[b][r].x * u[b][r].x + u[b][r].y * u[b][r].y;
+            line[padx<N0>(e)].x = u[b][r].x * u[b][r].x + u[b][r].y * u[b][r].y;
         });
     } else if constexpr (SRC == 1) {
         const T* g = static_cast<const T*>(src) + col0 + l;
         for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) {
             const T x = lv ? g[(long)e * C] : T{0, 0};
-            line[padx(e)].x = x.x * x.x + x.y * x.y;
+            line[padx<N0>(e)].x = x.x * x.x + x.y * x.y;
         });
     } else {
         const R* g = static_cast<const R*>(src) + col0 + l;
-        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { line[padx(e)].x = lv ? g[(long)e * C] : R(0); });
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { line[padx<N0>(e)].x = lv ? g[(long)e * C] : R(0); });
     }
     __syncthreads();
     typename FF::In z;
     typename FF::Out Z;
     for_pos<N0, TPL, FF::R0>(jt, [&](int b, int r, int m) {
-        z[b][r] = (m < N0 / 2) ? T{line[padx(2 * m)].x, line[padx(2 * m + 1)].x} : T{0, 0};
+        z[b][r] = (m < N0 / 2) ? T{line[padx<N0>(2 * m)].x, line[padx<N0>(2 * m + 1)].x} : T{0, 0};
     });
     __syncthreads();
     FF::run(z, Z, line, jt, twN);
     __syncthreads();
-    for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int k) { line[padx(k)] = Z[b][r]; });
+    for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int k) { line[padx<N0>(k)] = Z[b][r]; });
     __syncthreads();
     T* gout = X1 + col0 + l;
-    for (int k = jt; k <= N0; k += TPL) {
-        const T zk = line[padx(k == N0 ? 0 : k)];
-        const T zc = cconj(line[padx(k == 0 ? 0 : N0 - k)]);
+    for_rows_incl<N0, TPL>(jt, [&](int, int k) {
+        const T zk = line[padx<N0>(k == N0 ? 0 : k)];
+        const T zc = cconj(line[padx<N0>(k == 0 ? 0 : N0 - k)]);
         const T ev = T{R(0.5) * (zk.x + zc.x), R(0.5) * (zk.y + zc.y)};
         const T dv = csub(zk, zc);
         const T ov = T{R(0.5) * dv.y, -R(0.5) * dv.x};  // (zk - zc)/(2i)
         if (lv) gout[(long)k * C] = cadd(ev, cmul(tw2N[k], ov));
-    }
+    });
 }
 
 template <typename R, int N0, int SRC>
 __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* X1,
                                                             int C, const typename CT<R>::T* twN,
                                                             const typename CT<R>::T* tw2N) {
-    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     r2c_body<R, N0, SRC>(src, X1, C, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
 
@@ -400,11 +423,12 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
                                                                   const typename CT<R>::T* twN,
                                                                   const typename CT<R>::T* tw2N, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
-    using Cf = ColCfg<R, N0>;
+    using PL = typename PlanOf<N0, typename FusedPlan<R, N0>::L>::L;
+    using Cf = FusedCfg<R, N0>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
-    constexpr int P = pitch_cols(N0 + 1);
-    using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;   // inverse transforms, outputs at radix-RK positions
-    using FF = Fft<T, N0, false, TPL, InvPlan<N0>>;  // forward after the phase, inputs at radix-RK positions
+    constexpr int P = pitch_cols<N0>(N0 + 1);
+    using FI = Fft<T, N0, true, TPL, PL>;                    // inverse transforms, outputs at radix-RK positions
+    using FF = Fft<T, N0, false, TPL, typename Rev<PL>::L>;  // forward after the phase, inputs at radix-RK positions
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
@@ -412,13 +436,17 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
     R phi[FI::BK][FI::RK];
     if constexpr (MODE != 1) {
         const T* gx = X1 + col0 + l;
-        for (int k = jt; k <= N0; k += TPL) line[padx(k)] = lv ? gx[(long)k * C] : T{0, 0};
+        {
+            T xr[(N0 + TPL) / TPL];
+            for_rows_incl<N0, TPL>(jt, [&](int i, int k) { xr[i] = lv ? gx[(long)k * C] : T{0, 0}; });
+            for_rows_incl<N0, TPL>(jt, [&](int i, int k) { line[padx<N0>(k)] = xr[i]; });
+        }
         __syncthreads();
         typename FI::In zc;
         typename FI::Out y;
         for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int k) {
-            const T xk = line[padx(k)];
-            const T xc = cconj(line[padx(N0 - k)]);
+            const T xk = line[padx<N0>(k)];
+            const T xc = cconj(line[padx<N0>(N0 - k)]);
             const T a = cadd(xk, xc);
             const T bb = cmulc(csub(xk, xc), tw2N[k]);  // exp(+i pi k/N0) (xk - xc)
             zc[b][r] = T{a.x - bb.y, a.y + bb.x};       // a + i bb
@@ -429,18 +457,19 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
         // only y_m with m < N0/2 carry the physical samples Phi_0..Phi_{N0-1}
         for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int m) {
             if (m < N0 / 2) {
-                line[padx(2 * m)].x = y[b][r].x;
-                line[padx(2 * m + 1)].x = y[b][r].y;
+                line[padx<N0>(2 * m)].x = y[b][r].x;
+                line[padx<N0>(2 * m + 1)].x = y[b][r].y;
             }
         });
         __syncthreads();
         if constexpr (MODE == 2) {
             R* go = Phi_out + col0 + l;
-            for (int e = jt; e < N0; e += TPL)
-                if (lv) go[(long)e * C] = line[padx(e)].x;
+            for_rows_incl<N0 - 1, TPL>(jt, [&](int, int e) {
+                if (lv) go[(long)e * C] = line[padx<N0>(e)].x;
+            });
             return;
         }
-        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) { phi[b][r] = line[padx(e)].x; });
+        for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) { phi[b][r] = line[padx<N0>(e)].x; });
         __syncthreads();
     } else {
 #pragma unroll
@@ -449,8 +478,8 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
             for (int r = 0; r < FI::RK; ++r) phi[b][r] = R(0);
     }
     if constexpr (MODE != 2) {
-        typename FI::In vs;
         typename FI::Out psi;
+        typename FI::In vs;
         {
             const T* g = S + col0 + l;
             for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { vs[b][r] = lv ? g[(long)e * C] : T{0, 0}; });
@@ -474,11 +503,7 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
             const R rho = v.x * v.x + v.y * v.y;
             const R th = R(pa.bdt) * rho + R(pa.ldt) * phi[b][r] + Pv;
             R sn, cs;
-            if constexpr (sizeof(R) == 4) {
-                sincosf(th, &sn, &cs);
-            } else {
-                sincos(th, &sn, &cs);
-            }
+            fsincos(th, &sn, &cs);
             psi[b][r] = T{v.x * cs + v.y * sn, v.y * cs - v.x * sn};  // v * exp(-i th)
         });
         typename FF::Out out;
@@ -492,12 +517,12 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
 }
 
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* X1,
+__global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* X1,
                                                                   typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
                                                                   const typename CT<R>::T* twN,
                                                                   const typename CT<R>::T* tw2N) {
-    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    __shared__ typename CT<R>::T lds[FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     c2r_phase_body<R, N0, MODE>(X1, S, Phi_out, C, pa, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
 
@@ -536,7 +561,7 @@ __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_cols(void* psi, cons
                                                                 const typename CT<R>::T* twN0) {
     using T = typename CT<R>::T;
     T* x = static_cast<T*>(psi) + bi[blockIdx.y].psi_off;
-    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0)];
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0)];
     cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds);
 }
 
@@ -557,7 +582,7 @@ __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_r2c(void* psi, const
                                                                const typename CT<R>::T* tw2N0) {
     using T = typename CT<R>::T;
     const BInst& b = bi[blockIdx.y];
-    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     r2c_body<R, N0, 0>(static_cast<const T*>(psi) + b.psi_off, static_cast<T*>(b.X1), N1, twN0, tw2N0, blockIdx.x, 0, lds);
 }
 
@@ -582,14 +607,14 @@ __global__ __launch_bounds__((LineCfg<R, N1, true>::NTH)) void k_b_conv_halves(
 }
 
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_c2r_phase(void* psi, const BInst* bi,
+__global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_b_c2r_phase(void* psi, const BInst* bi,
                                                                      int N1, int kstep,
                                                                      const typename CT<R>::T* twN0,
                                                                      const typename CT<R>::T* tw2N0) {
     using T = typename CT<R>::T;
     const BInst& b = bi[blockIdx.y];
     const PhaseArgs pa = batch_phase(b, kstep);
-    __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols(N0 + 1)];
+    __shared__ typename CT<R>::T lds[FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     c2r_phase_body<R, N0, MODE>(static_cast<const T*>(b.X1), static_cast<T*>(psi) + b.psi_off, nullptr, N1, pa, twN0,
                                 tw2N0, blockIdx.x, 0, lds);
 }

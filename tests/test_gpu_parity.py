@@ -235,6 +235,22 @@ def test_reversibility_and_mass():
     assert abs(plan.time) < 1e-15
 
 
+@pytest.mark.parametrize("beta,tol", [(3e5, 1e-12), (2e9, 1e-8)])
+def test_large_nonlinear_phases(beta, tol):
+    # dt*beta*rho reaches ~1e2 (first case) and ~1e6 (second: beyond the
+    # argument range of the polynomial sine/cosine, taking the wide-range
+    # path); the phase itself is rounded at ~1e-16*theta on both sides.
+    p = P("local2d").replace(beta=beta)
+    psi0 = _psi0(p, seed=8)
+    ref, _ = _oracle_problem(p).step(psi0, 0.0, p.dt)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0)
+    plan.step(x, 1, p.dt)
+    err = _rel(_host(x), ref)
+    _note(f"[parity] large phase beta={beta:g}: {err:.3e}")
+    assert err < tol
+
+
 def test_deterministic_rerun():
     p = P("coul3d")
     psi0 = _psi0(p, seed=6)
