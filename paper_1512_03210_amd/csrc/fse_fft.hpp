@@ -340,21 +340,35 @@ __device__ __forceinline__ void get(T (&v)[B][RAD], const T* line, int jt) {
     }
 }
 
+// Ordering point between the LDS writes and reads of an exchange.  WS: every
+// thread that touches the LDS region is a lane of one wavefront, whose LDS
+// accesses execute in program order, so only the compiler has to be kept
+// from moving accesses across it; otherwise a workgroup barrier.
+template <bool WS> __device__ __forceinline__ void lds_sync() {
+    if constexpr (WS) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Middle stages entirely in LDS (each: barrier, read, barrier, compute, write).
-template <typename T, int M, bool INV, int TPL, int NS, typename L> struct MidStages;
-template <typename T, int M, bool INV, int TPL, int NS> struct MidStages<T, M, INV, TPL, NS, RList<>> {
+template <typename T, int M, bool INV, int TPL, int NS, typename L, bool WS> struct MidStages;
+template <typename T, int M, bool INV, int TPL, int NS, bool WS> struct MidStages<T, M, INV, TPL, NS, RList<>, WS> {
     __device__ __forceinline__ static void run(T*, int, const T*) {}
 };
-template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs>
-struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>> {
+template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs, bool WS>
+struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS> {
     __device__ __forceinline__ static void run(T* line, int jt, const T* __restrict__ tw) {
         T v[Shape<M, TPL, R0>::B][R0];
-        __syncthreads();
+        lds_sync<WS>();
         get<T, M, TPL, R0>(v, line, jt);
-        __syncthreads();
+        lds_sync<WS>();
         bfly<T, M, INV, TPL, NS, R0>(v, jt, tw);
         put<T, M, TPL, NS, R0>(v, line, jt);
-        MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>>::run(line, jt, tw);
+        MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>, WS>::run(line, jt, tw);
     }
 };
 
@@ -363,8 +377,9 @@ struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>> {
 //   out: u = outputs at positions j + r*M/Rk (last radix Rk)
 // The caller guarantees that no thread still reads the line's LDS when this
 // starts; on return other threads may still be reading it (barrier before
-// reuse).  Single-stage plans use no LDS.
-template <typename T, int M, bool INV, int TPL, typename L> struct Fft {
+// reuse).  Single-stage plans use no LDS.  WS: the threads of a line are
+// lanes of one wavefront (see lds_sync).
+template <typename T, int M, bool INV, int TPL, typename L, bool WS = false> struct Fft {
     static constexpr int R0 = Head<L>::value;
     static constexpr int RK = Last<L>::value;
     static constexpr int B0 = Shape<M, TPL, R0>::B;
@@ -384,8 +399,8 @@ template <typename T, int M, bool INV, int TPL, typename L> struct Fft {
         } else {
             bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
             put<T, M, TPL, 1, R0>(v, line, jt);
-            MidStages<T, M, INV, TPL, R0, typename Mid<L>::L>::run(line, jt, tw);
-            __syncthreads();
+            MidStages<T, M, INV, TPL, R0, typename Mid<L>::L, WS>::run(line, jt, tw);
+            lds_sync<WS>();
             get<T, M, TPL, RK>(u, line, jt);
             bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tw);
         }

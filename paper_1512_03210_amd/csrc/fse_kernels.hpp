@@ -193,6 +193,25 @@ __global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typenam
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int fold(int i, int F) { return (F == 0) ? i : min(i, F - i); }
 
+// Position q of the mirror order over [0, F) -> index: q = 2m -> m,
+// q = 2m + 1 -> F - m (m >= 1) or F/2 (m = 0).
+__device__ __forceinline__ int mirror_order(int q, int F) {
+    const int m = q >> 1;
+    return (q & 1) == 0 ? m : (m == 0 ? F / 2 : F - m);
+}
+
+// Line handled at visit position gl (identity unless X0 or X1 is set).
+__device__ __forceinline__ int line_at(int gl, const LineIdx& li) {
+    if (li.X0 && li.X1) {
+        const int G = gl >> 2, h1 = li.F1 >> 1;
+        const int q0 = 2 * (G / h1) + ((gl >> 1) & 1), q1 = 2 * (G % h1) + (gl & 1);
+        return mirror_order(q0, li.F0) * li.D1 + mirror_order(q1, li.F1);
+    }
+    if (li.X1) return (gl / li.D1) * li.D1 + mirror_order(gl % li.D1, li.F1);
+    if (li.X0) return mirror_order(gl, li.F0);
+    return gl;
+}
+
 __device__ __forceinline__ long mult_row(int gl, const LineIdx& li) {
     const int k0 = fold(gl / li.D1, li.F0), k1 = fold(gl % li.D1, li.F1);
     return (long)(k0 * li.T1 + k1) * li.T2;
@@ -205,17 +224,19 @@ __device__ __forceinline__ void lines_body(
     using T = typename CT<R>::T;
     using C = LineCfg<R, N, MODE == 0>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB, SUB = C::SUB;
-    using FF = Fft<T, N, false, TPL, FwdPlan<N>>;
-    using FI = Fft<T, N, true, TPL, InvPlan<N>>;
+    constexpr bool WS = (64 % (TPL * SUB)) == 0;  // a data line's threads share one wavefront
+    using FF = Fft<T, N, false, TPL, FwdPlan<N>, WS>;
+    using FI = Fft<T, N, true, TPL, InvPlan<N>, WS>;
     const int jt = threadIdx.x % TPL;
     const int sl = threadIdx.x / TPL;  // sub-line
     const int dl = sl / SUB, h = sl % SUB;
-    const int gl = bx * LPB + dl;
-    const bool valid = gl < nlines;
+    const int gv = bx * LPB + dl;
+    const bool valid = gv < nlines;
+    const int gl = valid ? line_at(gv, li) : 0;
     T* line = lds + sl * P;
     T* g = data + (long)gl * N;
     if constexpr (MODE == 3) {
-        using FP = Fft<T, N, true, TPL, FwdPlan<N>>;
+        using FP = Fft<T, N, true, TPL, FwdPlan<N>, WS>;
         typename FP::In v;
         typename FP::Out u;
         for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = valid ? g[e] : T{0, 0}; });
@@ -249,7 +270,7 @@ __device__ __forceinline__ void lines_body(
                 }
             });
             typename FI::Out w;
-            __syncthreads();
+            lds_sync<WS>();
             FI::run(u, w, line, jt, twN);
             if constexpr (MODE == 1) {
                 for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
@@ -257,11 +278,11 @@ __device__ __forceinline__ void lines_body(
                 });
             } else {
                 // combine the halves: y = ya + w^{-n} yb (the odd half goes through LDS)
-                __syncthreads();
+                lds_sync<WS>();
                 if (h == 1) {
                     for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) { line[padx<N>(e)] = cmulc(w[b][r], tw2[e]); });
                 }
-                __syncthreads();
+                lds_sync<WS>();
                 if (h == 0) {
                     const T* other = line + P;
                     for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
@@ -295,12 +316,14 @@ __device__ __forceinline__ void conv_full_body(
     using C = LineCfg<R, M, false>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
     constexpr int N = M / 2;
-    using FF = Fft<T, M, false, TPL, FwdPlan<M>>;
-    using FI = Fft<T, M, true, TPL, InvPlan<M>>;
+    constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
+    using FF = Fft<T, M, false, TPL, FwdPlan<M>, WS>;
+    using FI = Fft<T, M, true, TPL, InvPlan<M>, WS>;
     const int jt = threadIdx.x % TPL;
     const int dl = threadIdx.x / TPL;
-    const int gl = bx * LPB + dl;
-    const bool valid = gl < nlines;
+    const int gv = bx * LPB + dl;
+    const bool valid = gv < nlines;
+    const int gl = valid ? line_at(gv, li) : 0;
     T* line = lds + dl * P;
     T* g = data + (long)gl * N;
     typename FF::In v;
@@ -313,7 +336,7 @@ __device__ __forceinline__ void conv_full_body(
         u[b][r] = T{u[b][r].x * k, u[b][r].y * k};
     });
     typename FI::Out w;
-    __syncthreads();
+    lds_sync<WS>();
     FI::run(u, w, line, jt, twM);
     for_pos<M, TPL, FI::RK>(jt, [&](int b, int r, int e) {
         if (valid && e < N) g[e] = w[b][r];

@@ -6,8 +6,13 @@ namespace fse {
 // Row of the multiplier table for a contiguous line: i0 = line / D1,
 // i1 = line % D1, each folded to min(i, F - i) when F > 0,
 // row = (k0 * T1 + k1) * T2.
+// X0, X1 (0 or 1): visit the lines in mirror order along axis 0 / 1 (F0 / F1
+// even and > 0), so that the lines i and F - i that share a row are handled
+// by the same block and the row is read once.  With both set, D1 == F1 and
+// consecutive groups of four lines are {i0, F0 - i0} x {i1, F1 - i1}.
 struct LineIdx {
     int D1, F0, F1, T1, T2;
+    int X0 = 0, X1 = 0;
 };
 
 // Grid and coefficients of the fused nonlinear sub-step.
