@@ -285,28 +285,57 @@ __device__ __forceinline__ T twpow(const T (&p)[4], int r) {
     return w;
 }
 
-// Twiddles (stage with Ns > 1) and the radix-RAD DFT, in registers.
+// Twiddle powers W^(k 2^bit), 2^bit < RAD, k = j mod NS, of the thread's
+// butterflies in a stage with NS > 1.  Loaded ahead of the stage's LDS
+// exchange so that their latency overlaps it.
+template <typename T, int M, int TPL, int NS, int RAD> struct TwP {
+    static constexpr int B = Shape<M, TPL, RAD>::B;
+    static constexpr int NP = 1 + (RAD > 2) + (RAD > 4) + (RAD > 8);
+    T p[B][NP];
+    __device__ __forceinline__ void load(int jt, const T* __restrict__ tw) {
+        if constexpr (NS > 1) {
+            constexpr int TWS = M / (NS * RAD);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const int j = jt + b * TPL;
+                if (Shape<M, TPL, RAD>::active(j)) {
+                    const int k = j % NS;
+#pragma unroll
+                    for (int bit = 0; bit < NP; ++bit) p[b][bit] = tw[(k << bit) * TWS];
+                }
+            }
+        }
+    }
+};
+
+// Twiddles (stage with NS > 1, from preloaded powers) and the radix-RAD DFT,
+// in registers.
 template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
-__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const T* __restrict__ tw) {
+__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL, NS, RAD>& tp) {
     using S = Shape<M, TPL, RAD>;
     static_assert(B == S::B, "register array shape");
-    constexpr int TWS = M / (NS * RAD);
 #pragma unroll
     for (int b = 0; b < S::B; ++b) {
         const int j = jt + b * TPL;
         if (S::active(j)) {
-            if (NS > 1) {
-                const int k = j % NS;
+            if constexpr (NS > 1) {
                 T p[4];
 #pragma unroll
                 for (int bit = 0; bit < 4; ++bit)
-                    if ((1 << bit) < RAD) p[bit] = tw[(k << bit) * TWS];
+                    if (bit < TwP<T, M, TPL, NS, RAD>::NP) p[bit] = tp.p[b][bit];
 #pragma unroll
                 for (int r = 1; r < RAD; ++r) v[b][r] = twmul<INV>(v[b][r], twpow<INV, T, RAD>(p, r));
             }
             DFT<RAD, INV>::run(v[b]);
         }
     }
+}
+
+template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
+__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const T* __restrict__ tw) {
+    TwP<T, M, TPL, NS, RAD> tp;
+    tp.load(jt, tw);
+    bfly<T, M, INV, TPL, NS, RAD>(v, jt, tp);
 }
 
 // Write the stage outputs to their Stockham positions in LDS.
@@ -363,10 +392,12 @@ template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs, bool 
 struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS> {
     __device__ __forceinline__ static void run(T* line, int jt, const T* __restrict__ tw) {
         T v[Shape<M, TPL, R0>::B][R0];
+        TwP<T, M, TPL, NS, R0> tp;
+        tp.load(jt, tw);
         lds_sync<WS>();
         get<T, M, TPL, R0>(v, line, jt);
         lds_sync<WS>();
-        bfly<T, M, INV, TPL, NS, R0>(v, jt, tw);
+        bfly<T, M, INV, TPL, NS, R0>(v, jt, tp);
         put<T, M, TPL, NS, R0>(v, line, jt);
         MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>, WS>::run(line, jt, tw);
     }
@@ -400,9 +431,11 @@ template <typename T, int M, bool INV, int TPL, typename L, bool WS = false> str
             bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
             put<T, M, TPL, 1, R0>(v, line, jt);
             MidStages<T, M, INV, TPL, R0, typename Mid<L>::L, WS>::run(line, jt, tw);
+            TwP<T, M, TPL, M / RK, RK> tp;
+            tp.load(jt, tw);
             lds_sync<WS>();
             get<T, M, TPL, RK>(u, line, jt);
-            bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tw);
+            bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tp);
         }
     }
 };

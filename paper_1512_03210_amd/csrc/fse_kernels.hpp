@@ -239,7 +239,7 @@ __device__ __forceinline__ void lines_body(
         using FP = Fft<T, N, true, TPL, FwdPlan<N>, WS>;
         typename FP::In v;
         typename FP::Out u;
-        for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = valid ? g[e] : T{0, 0}; });
+        for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = g[e]; });
         FP::run(v, u, line, jt, twN);
         for_pos<N, TPL, FP::RK>(jt, [&](int b, int r, int e) {
             if (valid) g[e] = u[b][r];
@@ -247,8 +247,9 @@ __device__ __forceinline__ void lines_body(
     } else {
         typename FF::In v;
         typename FF::Out u;
+        // (a line past the end reads line 0 and stores nothing)
         for_pos<N, TPL, FF::R0>(jt, [&](int b, int r, int e) {
-            T x = valid ? g[e] : T{0, 0};
+            T x = g[e];
             if (MODE == 0 && h == 1) x = cmul(x, tw2[e]);
             v[b][r] = x;
         });
@@ -258,14 +259,14 @@ __device__ __forceinline__ void lines_body(
                 if (valid) g[e] = u[b][r];
             });
         } else {
-            const long row = valid ? mult_row(gl, li) : 0;
+            const long row = mult_row(gl, li);
             for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
                 if (MODE == 0) {
                     const int p = 2 * e + h;
-                    const R k = valid ? static_cast<const R*>(mult)[row + min(p, 2 * N - p)] : R(0);
+                    const R k = static_cast<const R*>(mult)[row + min(p, 2 * N - p)];
                     u[b][r] = T{u[b][r].x * k, u[b][r].y * k};
                 } else {
-                    const T q = valid ? static_cast<const T*>(mult)[row + min(e, N - e)] : T{0, 0};
+                    const T q = static_cast<const T*>(mult)[row + min(e, N - e)];
                     u[b][r] = cmul(u[b][r], q);
                 }
             });
@@ -328,12 +329,14 @@ __device__ __forceinline__ void conv_full_body(
     T* g = data + (long)gl * N;
     typename FF::In v;
     typename FF::Out u;
-    for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (valid && e < N) ? g[e] : T{0, 0}; });
+    // (a line past the end reads line 0 and stores nothing)
+    for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (e < N) ? g[e] : T{0, 0}; });
+    const long row = mult_row(gl, li);
+    R kq[FF::BK][FF::RK];
+    for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
     FF::run(v, u, line, jt, twM);
-    const long row = valid ? mult_row(gl, li) : 0;
-    for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) {
-        const R k = valid ? mult[row + min(p, M - p)] : R(0);
-        u[b][r] = T{u[b][r].x * k, u[b][r].y * k};
+    for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int) {
+        u[b][r] = T{u[b][r].x * kq[b][r], u[b][r].y * kq[b][r]};
     });
     typename FI::Out w;
     lds_sync<WS>();
