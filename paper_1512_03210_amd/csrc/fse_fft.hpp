@@ -287,8 +287,12 @@ __device__ __forceinline__ T twpow(const T (&p)[4], int r) {
 
 // Twiddle powers W^(k 2^bit), 2^bit < RAD, k = j mod NS, of the thread's
 // butterflies in a stage with NS > 1.  Loaded ahead of the stage's LDS
-// exchange so that their latency overlaps it.
-template <typename T, int M, int TPL, int NS, int RAD> struct TwP {
+// exchange so that their latency overlaps it.  The first TWL powers are read
+// from the table and the rest are squares of the previous one: line kernels,
+// whose lanes all need different twiddles, trade table reads (which bound
+// them) for a few multiplies; column kernels, whose lanes share them, read
+// all.
+template <typename T, int M, int TPL, int NS, int RAD, int TWL> struct TwP {
     static constexpr int B = Shape<M, TPL, RAD>::B;
     static constexpr int NP = 1 + (RAD > 2) + (RAD > 4) + (RAD > 8);
     T p[B][NP];
@@ -301,7 +305,14 @@ template <typename T, int M, int TPL, int NS, int RAD> struct TwP {
                 if (Shape<M, TPL, RAD>::active(j)) {
                     const int k = j % NS;
 #pragma unroll
-                    for (int bit = 0; bit < NP; ++bit) p[b][bit] = tw[(k << bit) * TWS];
+                    for (int bit = 0; bit < NP; ++bit) {
+                        if (bit < TWL) {
+                            p[b][bit] = tw[(k << bit) * TWS];
+                        } else {
+                            const T q = p[b][bit - 1];
+                            p[b][bit] = T{(q.x - q.y) * (q.x + q.y), 2 * q.x * q.y};
+                        }
+                    }
                 }
             }
         }
@@ -310,8 +321,8 @@ template <typename T, int M, int TPL, int NS, int RAD> struct TwP {
 
 // Twiddles (stage with NS > 1, from preloaded powers) and the radix-RAD DFT,
 // in registers.
-template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
-__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL, NS, RAD>& tp) {
+template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B, int TWL>
+__device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL, NS, RAD, TWL>& tp) {
     using S = Shape<M, TPL, RAD>;
     static_assert(B == S::B, "register array shape");
 #pragma unroll
@@ -322,7 +333,7 @@ __device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL
                 T p[4];
 #pragma unroll
                 for (int bit = 0; bit < 4; ++bit)
-                    if (bit < TwP<T, M, TPL, NS, RAD>::NP) p[bit] = tp.p[b][bit];
+                    if (bit < TwP<T, M, TPL, NS, RAD, TWL>::NP) p[bit] = tp.p[b][bit];
 #pragma unroll
                 for (int r = 1; r < RAD; ++r) v[b][r] = twmul<INV>(v[b][r], twpow<INV, T, RAD>(p, r));
             }
@@ -333,7 +344,7 @@ __device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL
 
 template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
 __device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const T* __restrict__ tw) {
-    TwP<T, M, TPL, NS, RAD> tp;
+    TwP<T, M, TPL, NS, RAD, 4> tp;
     tp.load(jt, tw);
     bfly<T, M, INV, TPL, NS, RAD>(v, jt, tp);
 }
@@ -384,22 +395,23 @@ template <bool WS> __device__ __forceinline__ void lds_sync() {
 }
 
 // Middle stages entirely in LDS (each: barrier, read, barrier, compute, write).
-template <typename T, int M, bool INV, int TPL, int NS, typename L, bool WS> struct MidStages;
-template <typename T, int M, bool INV, int TPL, int NS, bool WS> struct MidStages<T, M, INV, TPL, NS, RList<>, WS> {
+template <typename T, int M, bool INV, int TPL, int NS, typename L, bool WS, int TWL> struct MidStages;
+template <typename T, int M, bool INV, int TPL, int NS, bool WS, int TWL>
+struct MidStages<T, M, INV, TPL, NS, RList<>, WS, TWL> {
     __device__ __forceinline__ static void run(T*, int, const T*) {}
 };
-template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs, bool WS>
-struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS> {
+template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs, bool WS, int TWL>
+struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS, TWL> {
     __device__ __forceinline__ static void run(T* line, int jt, const T* __restrict__ tw) {
         T v[Shape<M, TPL, R0>::B][R0];
-        TwP<T, M, TPL, NS, R0> tp;
+        TwP<T, M, TPL, NS, R0, TWL> tp;
         tp.load(jt, tw);
         lds_sync<WS>();
         get<T, M, TPL, R0>(v, line, jt);
         lds_sync<WS>();
         bfly<T, M, INV, TPL, NS, R0>(v, jt, tp);
         put<T, M, TPL, NS, R0>(v, line, jt);
-        MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>, WS>::run(line, jt, tw);
+        MidStages<T, M, INV, TPL, NS * R0, RList<Rs...>, WS, TWL>::run(line, jt, tw);
     }
 };
 
@@ -409,8 +421,9 @@ struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS> {
 // The caller guarantees that no thread still reads the line's LDS when this
 // starts; on return other threads may still be reading it (barrier before
 // reuse).  Single-stage plans use no LDS.  WS: the threads of a line are
-// lanes of one wavefront (see lds_sync).
-template <typename T, int M, bool INV, int TPL, typename L, bool WS = false> struct Fft {
+// lanes of one wavefront (see lds_sync).  TWL: twiddle powers read per
+// butterfly (see TwP).
+template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int TWL = 4> struct Fft {
     static constexpr int R0 = Head<L>::value;
     static constexpr int RK = Last<L>::value;
     static constexpr int B0 = Shape<M, TPL, R0>::B;
@@ -430,8 +443,8 @@ template <typename T, int M, bool INV, int TPL, typename L, bool WS = false> str
         } else {
             bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
             put<T, M, TPL, 1, R0>(v, line, jt);
-            MidStages<T, M, INV, TPL, R0, typename Mid<L>::L, WS>::run(line, jt, tw);
-            TwP<T, M, TPL, M / RK, RK> tp;
+            MidStages<T, M, INV, TPL, R0, typename Mid<L>::L, WS, TWL>::run(line, jt, tw);
+            TwP<T, M, TPL, M / RK, RK, TWL> tp;
             tp.load(jt, tw);
             lds_sync<WS>();
             get<T, M, TPL, RK>(u, line, jt);

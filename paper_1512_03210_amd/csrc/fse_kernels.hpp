@@ -225,8 +225,8 @@ __device__ __forceinline__ void lines_body(
     using C = LineCfg<R, N, MODE == 0>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB, SUB = C::SUB;
     constexpr bool WS = (64 % (TPL * SUB)) == 0;  // a data line's threads share one wavefront
-    using FF = Fft<T, N, false, TPL, FwdPlan<N>, WS>;
-    using FI = Fft<T, N, true, TPL, InvPlan<N>, WS>;
+    using FF = Fft<T, N, false, TPL, FwdPlan<N>, WS, 2>;
+    using FI = Fft<T, N, true, TPL, InvPlan<N>, WS, 2>;
     const int jt = threadIdx.x % TPL;
     const int sl = threadIdx.x / TPL;  // sub-line
     const int dl = sl / SUB, h = sl % SUB;
@@ -236,7 +236,7 @@ __device__ __forceinline__ void lines_body(
     T* line = lds + sl * P;
     T* g = data + (long)gl * N;
     if constexpr (MODE == 3) {
-        using FP = Fft<T, N, true, TPL, FwdPlan<N>, WS>;
+        using FP = Fft<T, N, true, TPL, FwdPlan<N>, WS, 2>;
         typename FP::In v;
         typename FP::Out u;
         for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = g[e]; });
@@ -318,8 +318,8 @@ __device__ __forceinline__ void conv_full_body(
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
     constexpr int N = M / 2;
     constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
-    using FF = Fft<T, M, false, TPL, FwdPlan<M>, WS>;
-    using FI = Fft<T, M, true, TPL, InvPlan<M>, WS>;
+    using FF = Fft<T, M, false, TPL, FwdPlan<M>, WS, 2>;
+    using FI = Fft<T, M, true, TPL, InvPlan<M>, WS, 2>;
     const int jt = threadIdx.x % TPL;
     const int dl = threadIdx.x / TPL;
     const int gv = bx * LPB + dl;
