@@ -412,20 +412,23 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
     for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int k) { line[padx<N0>(k)] = Z[b][r]; });
     __syncthreads();
     T* gout = X1 + col0 + l;
-    for_rows_incl<N0, TPL>(jt, [&](int, int k) {
+    // exp(-i pi k/N0) for k = jt + i*TPL as tw2N[jt] * tw2N[i*TPL]: one table
+    // read per thread, the second factor is the same for every lane
+    const T wj = tw2N[jt];
+    for_rows_incl<N0, TPL>(jt, [&](int i, int k) {
         const T zk = line[padx<N0>(k == N0 ? 0 : k)];
         const T zc = cconj(line[padx<N0>(k == 0 ? 0 : N0 - k)]);
         const T ev = T{R(0.5) * (zk.x + zc.x), R(0.5) * (zk.y + zc.y)};
         const T dv = csub(zk, zc);
         const T ov = T{R(0.5) * dv.y, -R(0.5) * dv.x};  // (zk - zc)/(2i)
-        if (lv) gout[(long)k * C] = cadd(ev, cmul(tw2N[k], ov));
+        if (lv) gout[(long)k * C] = cadd(ev, cmul(cmul(wj, tw2N[i * TPL]), ov));
     });
 }
 
 template <typename R, int N0, int SRC>
 __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* X1,
-                                                            int C, const typename CT<R>::T* twN,
-                                                            const typename CT<R>::T* tw2N) {
+                                                            int C, const typename CT<R>::T* __restrict__ twN,
+                                                            const typename CT<R>::T* __restrict__ tw2N) {
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     r2c_body<R, N0, SRC>(src, X1, C, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
@@ -470,11 +473,18 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
         __syncthreads();
         typename FI::In zc;
         typename FI::Out y;
+        // exp(-i pi k/N0) for k = j + r*N0/R0 as tw2N[j] * tw2N[r*N0/R0] (the
+        // second factor is the same for every lane)
+        T wj[FI::B0];
+        for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int k) {
+            if (r == 0) wj[b] = tw2N[k];
+        });
         for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int k) {
             const T xk = line[padx<N0>(k)];
             const T xc = cconj(line[padx<N0>(N0 - k)]);
             const T a = cadd(xk, xc);
-            const T bb = cmulc(csub(xk, xc), tw2N[k]);  // exp(+i pi k/N0) (xk - xc)
+            const T w = (r == 0) ? wj[b] : cmul(wj[b], tw2N[r * (N0 / FI::R0)]);
+            const T bb = cmulc(csub(xk, xc), w);  // exp(+i pi k/N0) (xk - xc)
             zc[b][r] = T{a.x - bb.y, a.y + bb.x};       // a + i bb
         });
         __syncthreads();
@@ -546,8 +556,8 @@ template <typename R, int N0, int MODE>
 __global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* X1,
                                                                   typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
-                                                                  const typename CT<R>::T* twN,
-                                                                  const typename CT<R>::T* tw2N) {
+                                                                  const typename CT<R>::T* __restrict__ twN,
+                                                                  const typename CT<R>::T* __restrict__ tw2N) {
     __shared__ typename CT<R>::T lds[FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
     c2r_phase_body<R, N0, MODE>(X1, S, Phi_out, C, pa, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
@@ -604,8 +614,8 @@ __global__ __launch_bounds__((LineCfg<R, N1, false>::NTH)) void k_b_kin(void* ps
 
 template <typename R, int N0>
 __global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_r2c(void* psi, const BInst* bi, int N1,
-                                                               const typename CT<R>::T* twN0,
-                                                               const typename CT<R>::T* tw2N0) {
+                                                               const typename CT<R>::T* __restrict__ twN0,
+                                                               const typename CT<R>::T* __restrict__ tw2N0) {
     using T = typename CT<R>::T;
     const BInst& b = bi[blockIdx.y];
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
@@ -635,8 +645,8 @@ __global__ __launch_bounds__((LineCfg<R, N1, true>::NTH)) void k_b_conv_halves(
 template <typename R, int N0, int MODE>
 __global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_b_c2r_phase(void* psi, const BInst* bi,
                                                                      int N1, int kstep,
-                                                                     const typename CT<R>::T* twN0,
-                                                                     const typename CT<R>::T* tw2N0) {
+                                                                     const typename CT<R>::T* __restrict__ twN0,
+                                                                     const typename CT<R>::T* __restrict__ tw2N0) {
     using T = typename CT<R>::T;
     const BInst& b = bi[blockIdx.y];
     const PhaseArgs pa = batch_phase(b, kstep);
