@@ -891,19 +891,21 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
     }
 }
 
-// Plain streaming copy (HBM bandwidth calibration): 16-byte vectors, four
-// independent loads in flight per thread, grid-stride loop.
+// Plain streaming copy (HBM bandwidth calibration): 16-byte vectors, each
+// thread loads four elements 256 apart, then stores them; one pass, no loop.
 static __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src, long n) {
-    const long stride = (long)gridDim.x * 256L;
-    long i = blockIdx.x * 256L + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {
-        const double2 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        dst[i] = a;
-        dst[i + stride] = b;
-        dst[i + 2 * stride] = c;
-        dst[i + 3 * stride] = d;
+    const long base = (long)blockIdx.x * 1024L + threadIdx.x;
+    double2 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const long i = base + 256L * u;
+        if (i < n) v[u] = src[i];
     }
-    for (; i < n; i += stride) dst[i] = src[i];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const long i = base + 256L * u;
+        if (i < n) dst[i] = v[u];
+    }
 }
 
 }  // namespace fse

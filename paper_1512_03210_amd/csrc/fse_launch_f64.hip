@@ -23,8 +23,8 @@ hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t
 }
 
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
-    long g = (n16 + 4 * 256 - 1) / (4 * 256);
-    if (g > 256L * 32L) g = 256L * 32L;  // 32 workgroups per CU, grid-stride beyond
+    const long g = (n16 + 1023) / 1024;  // 1024 elements per workgroup
+    if (g > 0x7fffffffL) return hipErrorInvalidValue;
     k_copy16<<<(unsigned)g, 256, 0, st>>>(static_cast<double2*>(dst), static_cast<const double2*>(src), n16);
     return hipGetLastError();
 }
