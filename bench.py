@@ -230,7 +230,7 @@ def copy_bandwidth(nbytes=2 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(p, nsteps=1):
+def cpu_baseline(p, nsteps=2):
     """The FP64 oracle on a bounded sample: nsteps steps of the same workload."""
     import numpy as np
 
