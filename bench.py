@@ -208,6 +208,86 @@ def run_batch(steps, warmup=5):
     }
 
 
+def run_case(p, prec, steps, warmup=5):
+    """Throughput of one fse_step call of `steps` steps of a named case, and the
+    drift of its invariants (mass, energy, <Lz>) over those steps."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    psi0 = W.initial_state(p, seed=0)
+    dtype = np.complex128 if prec == fse.C128 else np.complex64
+    plan = fse.Plan.from_params(p, prec)
+    x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
+    if warmup > 0:  # on a copy: the measured run starts from psi0 at t = 0
+        w = x.clone()
+        plan.step(w, warmup, p.dt)
+        del w
+        plan.time = 0.0
+    m0, e0, l0 = plan.mass(x).item(), plan.energy(x)[5].item(), plan.angular_momentum(x).item()
+    torch.cuda.synchronize()
+    e_0, e_1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e_0.record()
+    plan.step(x, steps, p.dt)
+    e_1.record()
+    torch.cuda.synchronize()
+    ms = e_0.elapsed_time(e_1)
+    m1, e1, l1 = plan.mass(x).item(), plan.energy(x)[5].item(), plan.angular_momentum(x).item()
+    del plan, x
+    torch.cuda.empty_cache()
+    return {
+        "steps": steps,
+        "value": p.npts * steps / (ms * 1e-3),
+        "unit": "grid-point-steps/s",
+        "ms_per_step": ms / steps,
+        "drift": {"mass_abs": abs(m1 - m0), "energy_rel": abs(e1 - e0) / abs(e0), "lz_abs": abs(l1 - l0)},
+    }
+
+
+def run_ops(p, prec, reps=10):
+    """Per-call time of the FP64 reductions and of H psi on the headline grid."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    psi0 = W.initial_state(p, seed=0)
+    dtype = np.complex128 if prec == fse.C128 else np.complex64
+    csize = 16 if prec == fse.C128 else 8
+    plan = fse.Plan.from_params(p, prec)
+    x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
+    del psi0
+    rho = (x.real * x.real + x.imag * x.imag).contiguous()
+    out = torch.empty_like(x)
+    calls = {
+        "mass": lambda: plan.mass(x),
+        "energy": lambda: plan.energy(x),
+        "angular_momentum": lambda: plan.angular_momentum(x),
+        "apply_H": lambda: plan.apply_H(x, out),
+        "apply_H_frozen_rho": lambda: plan.apply_H(x, out, rho_frozen=rho),
+    }
+    res = {}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, f in calls.items():
+        f()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[name] = {"ms": round(ms, 4), "grid_points_per_s": p.npts / (ms * 1e-3)}
+    # the mass is one read of psi
+    res["mass"]["gbs"] = round(p.npts * csize / (res["mass"]["ms"] * 1e-3) / 1e9, 1)
+    del plan, x, out, rho
+    torch.cuda.empty_cache()
+    return res
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=10):
     """Achieved bandwidth of the library's plain copy kernel (read + write bytes / time)."""
     import torch
@@ -268,6 +348,8 @@ def main():
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched sweep (0: skip)")
+    ap.add_argument("--no-cases", dest="cases", action="store_false",
+                    help="skip the 128^3 (1000 steps) and 64^2 (100 steps) cases")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: the split step of one grid is not sharded here "
@@ -296,6 +378,18 @@ def main():
             "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
             "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"],
         }
+    print("[bench] reductions and H psi", file=sys.stderr, flush=True)
+    ops = {"c128": run_ops(p, fse.C128)}
+    if not args.no_c64:
+        ops["c64"] = run_ops(p, fse.C64)
+    cases = {}
+    if args.cases:
+        for name, steps in (("cfg2", 1000), ("cfg1", 100)):
+            q = W.preset(name)
+            print(f"[bench] case {q.name}: {steps} steps", file=sys.stderr, flush=True)
+            cases[q.name] = {"c128": run_case(q, fse.C128, steps)}
+            if not args.no_c64:
+                cases[q.name]["c64"] = run_case(q, fse.C64, steps)
     if args.batch_steps > 0:
         print(f"[bench] batched sweep, {args.batch_steps} steps", file=sys.stderr, flush=True)
         variants["batch_c64"] = run_batch(args.batch_steps)
@@ -348,6 +442,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,
+        "reductions_and_H": ops,
+        "cases": cases,
         "passes": r64["passes"],
         "mass_after": r64["mass_after"],
         "kernel_source_hash": kernel_source_hash(),
