@@ -681,7 +681,29 @@ __global__ void k_build_kin(typename CT<R>::T* __restrict__ Q, int T0, int T1, i
         const double om = (q > 0.0) ? pow(q, s) : 0.0;
         double sn, cs;
         sincos(-0.5 * tau * om, &sn, &cs);
-        Q[i] = T{R(scale * cs), R(scale * sn)};
+        if constexpr (sizeof(R) == 4) {
+            // The same entry multiplies the same mode every step, so a bias in
+            // its magnitude accumulates in the mass: of the four FP32 pairs that
+            // bracket (cx, cy), take the one whose squared modulus is closest.
+            const double cx = scale * cs, cy = scale * sn, tgt = cx * cx + cy * cy;
+            const float x0 = (float)cx, y0 = (float)cy;
+            const float xs[2] = {x0, ((double)x0 < cx) ? nextafterf(x0, 2.0f) : nextafterf(x0, -2.0f)};
+            const float ys[2] = {y0, ((double)y0 < cy) ? nextafterf(y0, 2.0f) : nextafterf(y0, -2.0f)};
+            float bx = x0, by = y0;
+            double best = fabs((double)x0 * x0 + (double)y0 * y0 - tgt);
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b) {
+                    const double e = fabs((double)xs[a] * xs[a] + (double)ys[b] * ys[b] - tgt);
+                    if (e < best) {
+                        best = e;
+                        bx = xs[a];
+                        by = ys[b];
+                    }
+                }
+            Q[i] = T{bx, by};
+        } else {
+            Q[i] = T{R(scale * cs), R(scale * sn)};
+        }
     }
 }
 
