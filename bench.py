@@ -288,6 +288,44 @@ def run_ops(p, prec, reps=10):
     return res
 
 
+def run_gs(p, prec, steps, tol, maxit=200):
+    """Ground-state steps (backward-Euler GFDN, preconditioned BiCGStab) from the
+    rotating initial guess; time per step and per Krylov iteration."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    psi0 = W.ground_state_guess(p.N, p.L, p.Omega, p.gamma, seed=0)
+    dtype = np.complex128 if prec == fse.C128 else np.complex64
+    plan = fse.Plan.from_params(p, prec)
+    x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
+    del psi0
+    e0 = plan.energy(x)[5].item()
+    plan.gs_step(x.clone(), p.dt, tol=tol, maxit=2)  # first call allocates the solver vectors
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stats.append(plan.gs_step(x, p.dt, tol=tol, maxit=maxit))
+    sec = time.perf_counter() - t0
+    e1 = plan.energy(x)[5].item()
+    its = sum(st["iterations"] for st in stats)
+    del plan, x
+    torch.cuda.empty_cache()
+    return {
+        "steps": steps,
+        "tol": tol,
+        "ms_per_step": 1e3 * sec / steps,
+        "krylov_iterations": [st["iterations"] for st in stats],
+        "ms_per_krylov_iteration": 1e3 * sec / max(its, 1),
+        "residuals": [st["residual"] for st in stats],
+        "diff_inf": [st["diff_inf"] for st in stats],
+        "energy_before_after": [e0, e1],
+    }
+
+
 def copy_bandwidth(nbytes=2 << 30, reps=10):
     """Achieved bandwidth of the library's plain copy kernel (read + write bytes / time)."""
     import torch
@@ -348,6 +386,7 @@ def main():
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched sweep (0: skip)")
+    ap.add_argument("--gs-steps", type=int, default=2, help="ground-state steps at 256^3 complex64 (0: skip)")
     ap.add_argument("--no-cases", dest="cases", action="store_false",
                     help="skip the 128^3 (1000 steps) and 64^2 (100 steps) cases")
     args = ap.parse_args()
@@ -390,6 +429,14 @@ def main():
             cases[q.name] = {"c128": run_case(q, fse.C128, steps)}
             if not args.no_c64:
                 cases[q.name]["c64"] = run_case(q, fse.C64, steps)
+    gs = None
+    if args.gs_steps > 0:
+        q = W.preset("cfg5")
+        print(f"[bench] ground state {q.name}: {args.gs_steps} steps", file=sys.stderr, flush=True)
+        gs = {"workload": (f"{q.name}: {'x'.join(map(str, q.N))} on [-{q.L[0]:g},{q.L[0]:g}]^3, s={q.s}, "
+                           f"Omega={q.Omega}, beta={q.beta}, lambda={q.lam} z-dipole GauSum, dt={q.dt}, "
+                           "initial guess ((1-Omega) phi_ho + Omega phi_ho^v) x z-Gaussian"),
+              "c64": run_gs(q, fse.C64, args.gs_steps, 1e-6)}
     if args.batch_steps > 0:
         print(f"[bench] batched sweep, {args.batch_steps} steps", file=sys.stderr, flush=True)
         variants["batch_c64"] = run_batch(args.batch_steps)
@@ -444,6 +491,7 @@ def main():
         "variants": variants,
         "reductions_and_H": ops,
         "cases": cases,
+        "ground_state": gs,
         "passes": r64["passes"],
         "mass_after": r64["mass_after"],
         "kernel_source_hash": kernel_source_hash(),

@@ -130,6 +130,37 @@ fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* str
 /* <Lz> = h^d sum psi^* (-i)(x D_y - y D_x) psi (eq. AME) -> out_dev[0]. */
 fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Ground state: one step of the gradient flow with discrete normalisation,
+ * discretised by the semi-implicit backward Euler method (Section 3.2, eqs.
+ * gf-eq2 to gffg33).  With rho^n = |psi|^2 and Phi^n = U * rho^n frozen,
+ *   A^{BE,n} phi1 = psi / dt,
+ *   A^{BE,n} = I/dt + (1/2)(-Lap+m^2)^s + V + beta rho^n + lambda Phi^n - Omega Lz,
+ * is solved in the first preconditioned form of eq. precond_type1,
+ *   (I + P_Delta A_TF) phi1 = P_Delta psi / dt,  P_Delta = [I/dt + (1/2)(-Lap+m^2)^s]^{-1},
+ * by BiCGStab started from psi, until the relative residual of that system is
+ * at most tol or maxit iterations have run; then psi <- phi1 / ||phi1||
+ * (discrete norm h^d sum |.|^2).  V is the unrotated trap (the frame in which
+ * the energy carries -Omega Lz, as fse_apply_H).  Vectors are kept in the
+ * plan's precision; inner products and the Krylov scalars are FP64.
+ *
+ * The call reads the Krylov scalars back to the host every iteration, so it
+ * returns only when the step is complete (it synchronises `stream`).  The
+ * first call allocates the solver's vectors (ten complex and two real arrays
+ * of the grid's size).
+ * dt > 0, tol > 0, maxit >= 1.  Returns FSE_ERR_NUMERIC if the recurrence
+ * breaks down (a zero denominator); psi is then left unchanged.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int iterations;  /* BiCGStab iterations of this step */
+    int converged;   /* 1 if the relative residual reached tol */
+    double residual; /* final relative residual of the preconditioned system */
+    double diff_inf; /* max |psi^{n+1} - psi^n| over the grid (the paper's stopping quantity) */
+} fse_gs_stats;
+
+fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxit, fse_gs_stats* stats,
+                       void* stream);
+
 /* Host-only: the GauSum multiplier Khat (before any FFT normalisation) on the
  * non-negative frequency octant, out[(k0*(N1+1)+k1)*(N2+1)+k2] for d = 3
  * (out[k0*(N1+1)+k1] for d = 2), kappa_j = pi k_j / (2 L_j), k_j = 0..N_j.

@@ -84,6 +84,8 @@ struct fse_plan_s {
     void* kin[2] = {nullptr, nullptr};
     double kin_tau[2] = {NAN, NAN};
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
+    void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
+    double* gs_out = nullptr;
     double* partials = nullptr;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -529,6 +531,192 @@ fse_status apply_H_impl(fse_plan p, const void* psi, void* H, const void* rho, h
     return FSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Ground-state step (Section 3.2): backward-Euler GFDN, first preconditioned
+// system of eq. precond_type1, BiCGStab with FP64 scalars.
+// ---------------------------------------------------------------------------
+struct GsBuf {
+    void *x, *r, *r0, *pv, *v, *sv, *t, *A, *Dx, *Dy;  // complex, n each
+    void *W, *Phi;                                     // real, n each
+};
+
+fse_status ensure_gs(fse_plan p, GsBuf* b) {
+    if (!p->gs) {
+        fse_status st = dev_alloc(p, &p->gs, (size_t)p->n * (10 * p->csize + 2 * p->rsize));
+        if (st != FSE_OK) return st;
+        st = dev_alloc(p, (void**)&p->gs_out, sizeof(double) * 8);
+        if (st != FSE_OK) return st;
+    }
+    char* c = static_cast<char*>(p->gs);
+    void** v[10] = {&b->x, &b->r, &b->r0, &b->pv, &b->v, &b->sv, &b->t, &b->A, &b->Dx, &b->Dy};
+    for (int k = 0; k < 10; ++k) *v[k] = c + (size_t)k * p->n * p->csize;
+    b->W = c + (size_t)10 * p->n * p->csize;
+    b->Phi = c + (size_t)10 * p->n * p->csize + (size_t)p->n * p->rsize;
+    return FSE_OK;
+}
+
+// out = v + P_Delta (W v - Omega Lz v), c0 = 1/dt.
+template <typename R> fse_status gs_apply_M(fse_plan p, const GsBuf& b, const void* v, void* out, double c0,
+                                            hipStream_t st) {
+    using L = fse::Launch<R>;
+    const fse::GridGeom g = geom(p);
+    const double inv_n = 1.0 / (double)p->n;
+    const void *Dx = nullptr, *Dy = nullptr;
+    if (p->Omega != 0.0) {
+        HIPCHK(hipMemcpyAsync(b.A, v, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
+        fse_status s = fft_forward<R>(p, b.A, st);
+        if (s != FSE_OK) return s;
+        HIPCHK(L::gs_grad2(b.A, b.Dx, b.Dy, p->n, g, dmu(p, 0), dmu(p, 1), inv_n, st));
+        if ((s = fft_inverse<R>(p, b.Dx, st)) != FSE_OK) return s;
+        if ((s = fft_inverse<R>(p, b.Dy, st)) != FSE_OK) return s;
+        Dx = b.Dx;
+        Dy = b.Dy;
+    }
+    HIPCHK(L::gs_tf(v, Dx, Dy, b.W, b.A, p->n, g, p->Omega, st));
+    fse_status s = fft_forward<R>(p, b.A, st);
+    if (s != FSE_OK) return s;
+    HIPCHK(L::gs_pdelta(b.A, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, c0, inv_n, st));
+    if ((s = fft_inverse<R>(p, b.A, st)) != FSE_OK) return s;
+    HIPCHK(L::gs_axpy(v, b.A, out, p->n, 1.0, 0.0, st));
+    return FSE_OK;
+}
+
+struct Cplx {
+    double re, im;
+};
+inline Cplx cdiv(Cplx a, Cplx b) {
+    const double d = b.re * b.re + b.im * b.im;
+    return Cplx{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+inline Cplx cmul(Cplx a, Cplx b) { return Cplx{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+
+// Inner products conj(a_k).b_k of npair pairs, read back to the host.
+template <typename R> fse_status gs_dots(fse_plan p, int npair, const void* const* a, const void* const* b, Cplx* out,
+                                         hipStream_t st) {
+    using L = fse::Launch<R>;
+    HIPCHK(L::gs_dots(a[0], b[0], npair > 1 ? a[1] : nullptr, npair > 1 ? b[1] : nullptr, npair > 2 ? a[2] : nullptr,
+                      npair > 2 ? b[2] : nullptr, npair, p->n, p->partials, kRedBlocks, st));
+    HIPCHK(fse::launch_gs_slots(p->partials, kRedBlocks, 2 * npair, 0, p->gs_out, st));
+    double h[6];
+    HIPCHK(hipMemcpyAsync(h, p->gs_out, sizeof(double) * 2 * npair, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < npair; ++k) out[k] = Cplx{h[2 * k], h[2 * k + 1]};
+    return FSE_OK;
+}
+
+template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, double tol, int maxit,
+                                              fse_gs_stats* stats, hipStream_t st) {
+    using L = fse::Launch<R>;
+    GsBuf b;
+    fse_status s = ensure_gs(p, &b);
+    if (s != FSE_OK) return s;
+    const fse::GridGeom g = geom(p);
+    const size_t bytes = (size_t)p->n * p->csize;
+    const double c0 = 1.0 / dt;
+    // frozen W^n = V + beta rho^n + lambda Phi^n
+    if (p->nl) {
+        if ((s = potential_impl<R>(p, psi, 1, b.Phi, st)) != FSE_OK) return s;
+    }
+    HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
+                        (p->d == 3) ? p->gamma[2] : 0.0, st));
+    // right-hand side P_Delta psi/dt, held in sv until r is formed
+    HIPCHK(hipMemcpyAsync(b.sv, psi, bytes, hipMemcpyDeviceToDevice, st));
+    if ((s = fft_forward<R>(p, b.sv, st)) != FSE_OK) return s;
+    HIPCHK(L::gs_pdelta(b.sv, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, c0,
+                        c0 / (double)p->n, st));
+    if ((s = fft_inverse<R>(p, b.sv, st)) != FSE_OK) return s;
+    // x0 = psi, r = rhs - M x0, r0 = p = r
+    HIPCHK(hipMemcpyAsync(b.x, psi, bytes, hipMemcpyDeviceToDevice, st));
+    if ((s = gs_apply_M<R>(p, b, b.x, b.v, c0, st)) != FSE_OK) return s;
+    HIPCHK(L::gs_axpy(b.sv, b.v, b.r, p->n, -1.0, 0.0, st));
+    HIPCHK(hipMemcpyAsync(b.r0, b.r, bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(b.pv, b.r, bytes, hipMemcpyDeviceToDevice, st));
+    Cplx d3[3];
+    {
+        const void* a[3] = {b.r0, b.r, b.sv};
+        const void* c[3] = {b.r, b.r, b.sv};
+        if ((s = gs_dots<R>(p, 3, a, c, d3, st)) != FSE_OK) return s;
+    }
+    Cplx rho = d3[0];
+    const double bnorm = std::sqrt(d3[2].re);
+    if (!(bnorm > 0.0)) return fail(FSE_ERR_NUMERIC, "psi is zero");
+    double res = std::sqrt(d3[1].re) / bnorm;
+    int it = 0;
+    bool conv = res <= tol;
+    while (!conv && it < maxit) {
+        ++it;
+        if ((s = gs_apply_M<R>(p, b, b.pv, b.v, c0, st)) != FSE_OK) return s;
+        Cplx r0v;
+        {
+            const void* a[1] = {b.r0};
+            const void* c[1] = {b.v};
+            if ((s = gs_dots<R>(p, 1, a, c, &r0v, st)) != FSE_OK) return s;
+        }
+        if (r0v.re == 0.0 && r0v.im == 0.0) return fail(FSE_ERR_NUMERIC, "BiCGStab breakdown: (r0, v) = 0");
+        const Cplx alpha = cdiv(rho, r0v);
+        HIPCHK(L::gs_axpy(b.r, b.v, b.sv, p->n, -alpha.re, -alpha.im, st));  // s = r - alpha v
+        Cplx ss;
+        {
+            const void* a[1] = {b.sv};
+            if ((s = gs_dots<R>(p, 1, a, a, &ss, st)) != FSE_OK) return s;
+        }
+        if (std::sqrt(ss.re) / bnorm <= tol) {
+            HIPCHK(L::gs_axpy(b.x, b.pv, b.x, p->n, alpha.re, alpha.im, st));  // x += alpha p
+            res = std::sqrt(ss.re) / bnorm;
+            conv = true;
+            break;
+        }
+        if ((s = gs_apply_M<R>(p, b, b.sv, b.t, c0, st)) != FSE_OK) return s;
+        Cplx ts_tt[2];
+        {
+            const void* a[2] = {b.t, b.t};
+            const void* c[2] = {b.sv, b.t};
+            if ((s = gs_dots<R>(p, 2, a, c, ts_tt, st)) != FSE_OK) return s;
+        }
+        if (ts_tt[1].re == 0.0) return fail(FSE_ERR_NUMERIC, "BiCGStab breakdown: (t, t) = 0");
+        const Cplx omega{ts_tt[0].re / ts_tt[1].re, ts_tt[0].im / ts_tt[1].re};
+        HIPCHK(L::gs_update_xr(b.x, b.r, b.pv, b.sv, b.t, p->n, alpha.re, alpha.im, omega.re, omega.im, st));
+        Cplx rr[2];
+        {
+            const void* a[2] = {b.r0, b.r};
+            const void* c[2] = {b.r, b.r};
+            if ((s = gs_dots<R>(p, 2, a, c, rr, st)) != FSE_OK) return s;
+        }
+        res = std::sqrt(rr[1].re) / bnorm;
+        if (res <= tol) {
+            conv = true;
+            break;
+        }
+        if ((omega.re == 0.0 && omega.im == 0.0) || (rho.re == 0.0 && rho.im == 0.0))
+            return fail(FSE_ERR_NUMERIC, "BiCGStab breakdown: omega = 0 or rho = 0");
+        const Cplx beta = cmul(cdiv(rr[0], rho), cdiv(alpha, omega));
+        HIPCHK(L::gs_update_p(b.pv, b.r, b.v, p->n, beta.re, beta.im, omega.re, omega.im, st));
+        rho = rr[0];
+    }
+    // psi <- x / ||x||, ||.||^2 = h^d sum |.|^2
+    Cplx xx;
+    {
+        const void* a[1] = {b.x};
+        if ((s = gs_dots<R>(p, 1, a, a, &xx, st)) != FSE_OK) return s;
+    }
+    double vol = 1.0;
+    for (int j = 0; j < p->d; ++j) vol *= p->h[j];
+    const double nrm2 = vol * xx.re;
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2)) return fail(FSE_ERR_NUMERIC, "solution has zero or non-finite norm");
+    HIPCHK(L::gs_finish(b.x, psi, p->n, 1.0 / std::sqrt(nrm2), p->partials, kRedBlocks, st));
+    HIPCHK(fse::launch_gs_slots(p->partials, kRedBlocks, 1, 1, p->gs_out, st));
+    double diff = 0.0;
+    HIPCHK(hipMemcpyAsync(&diff, p->gs_out, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+        stats->iterations = it;
+        stats->converged = conv ? 1 : 0;
+        stats->residual = res;
+        stats->diff_inf = diff;
+    }
+    return FSE_OK;
+}
+
 void destroy(fse_plan p) {
     if (!p) return;
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
@@ -817,6 +1005,18 @@ fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* r
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? apply_H_impl<double>(plan, psi, Hpsi, rho_frozen, st)
                                   : apply_H_impl<float>(plan, psi, Hpsi, rho_frozen, st);
+}
+
+fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxit, fse_gs_stats* stats,
+                       void* stream) {
+    g_err.clear();
+    if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FSE_ERR_ARG, "dt must be finite and > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite and > 0");
+    if (maxit < 1) return fail(FSE_ERR_ARG, "maxit must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? gs_step_impl<double>(plan, psi, dt, tol, maxit, stats, st)
+                                  : gs_step_impl<float>(plan, psi, dt, tol, maxit, stats, st);
 }
 
 fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, void* stream) {

@@ -47,7 +47,28 @@ template <typename R> struct Launch {
     static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi, long n,
                               const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
                               double g1, double g2, hipStream_t st);
+    // Ground-state step (kernels in fse_gs.hpp).
+    static hipError_t gs_frozen(const void* psi, const void* Phi, void* W, long n, const GridGeom& g, double beta,
+                                double lam, double g0, double g1, double g2, hipStream_t st);
+    static hipError_t gs_tf(const void* v, const void* Dx, const void* Dy, const void* W, void* u, long n,
+                            const GridGeom& g, double Omega, hipStream_t st);
+    static hipError_t gs_grad2(const void* a, void* ox, void* oy, long n, const GridGeom& g, double dmu0,
+                               double dmu1, double scale, hipStream_t st);
+    static hipError_t gs_pdelta(void* a, long n, const GridGeom& g, double dmu0, double dmu1, double dmu2, double s,
+                                double m2, double c0, double scale, hipStream_t st);
+    static hipError_t gs_axpy(const void* a, const void* b, void* out, long n, double cr, double ci, hipStream_t st);
+    static hipError_t gs_update_xr(void* x, void* r, const void* p, const void* s, const void* t, long n, double ar,
+                                   double ai, double wr, double wi, hipStream_t st);
+    static hipError_t gs_update_p(void* p, const void* r, const void* v, long n, double br, double bi, double wr,
+                                  double wi, hipStream_t st);
+    static hipError_t gs_dots(const void* a0, const void* b0, const void* a1, const void* b1, const void* a2,
+                              const void* b2, int npair, long n, double* partials, int nblk, hipStream_t st);
+    static hipError_t gs_finish(const void* x, void* psi, long n, double scale, double* partials, int nblk,
+                                hipStream_t st);
 };
+
+// out[k] = sum (op 0) or max (op 1) over the nblk partials of slot k, k < nslot.
+hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, double* out, hipStream_t st);
 
 hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st);
 

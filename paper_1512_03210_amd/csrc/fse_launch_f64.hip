@@ -22,6 +22,11 @@ hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t
     return hipGetLastError();
 }
 
+hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, double* out, hipStream_t st) {
+    k_gs_slots<<<(unsigned)nslot, RED_THREADS, 0, st>>>(partials, nblk, op, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
     const long g = (n16 + 1023) / 1024;  // 1024 elements per workgroup
     if (g > 0x7fffffffL) return hipErrorInvalidValue;

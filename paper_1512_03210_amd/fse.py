@@ -30,7 +30,7 @@ EXPORTS = [
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
-    "fse_batch_reduce", "fse_batch_times",
+    "fse_batch_reduce", "fse_batch_times", "fse_gs_step",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -44,6 +44,11 @@ class FseError(RuntimeError):
 class Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("mu", ctypes.c_double), ("prefactor", ctypes.c_double),
                 ("n", ctypes.c_double * 3), ("delta", ctypes.c_double), ("ht", ctypes.c_double)]
+
+
+class GsStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
+                ("diff_inf", ctypes.c_double)]
 
 
 class Instance(ctypes.Structure):
@@ -92,6 +97,7 @@ def lib():
         "fse_batch_step": (st, [vp, vp, i, vp]),
         "fse_batch_reduce": (st, [vp, vp, vp, vp]),
         "fse_batch_times": (st, [vp, dp]),
+        "fse_gs_step": (st, [vp, vp, d, d, i, ctypes.POINTER(GsStats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -257,6 +263,16 @@ class Plan:
 
     def angular_momentum(self, psi, stream=None):
         return self._scalar(lib().fse_angular_momentum, psi, 1, stream)
+
+    def gs_step(self, psi, dt: float, tol: float = 1e-12, maxit: int = 1000, stream=None) -> dict:
+        """One backward-Euler gradient-flow step toward the ground state, in place on psi
+        (fse_gs_step); returns the solver statistics."""
+        self._check_psi(psi)
+        st = GsStats()
+        _check(lib().fse_gs_step(self._h, _ptr(psi), float(dt), float(tol), int(maxit), ctypes.byref(st),
+                                 _stream(stream)))
+        return {"iterations": st.iterations, "converged": bool(st.converged), "residual": st.residual,
+                "diff_inf": st.diff_inf}
 
     def set_profiling(self, enable: bool):
         _check(lib().fse_set_profiling(self._h, 1 if enable else 0))

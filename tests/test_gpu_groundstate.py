@@ -1,0 +1,136 @@
+"""GPU parity of the ground-state step (backward-Euler GFDN, preconditioned BiCGStab)
+against the oracle (oracle/groundstate.py)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import groundstate as ogs
+from oracle.scheme import Problem, axes
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+from paper_1512_03210_amd import fse  # noqa: E402
+
+
+def _note(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _require_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fse.lib()
+
+
+def _params(name):
+    c2 = 1.0 / (2.0 * math.pi)
+    cases = {
+        "rot2d": W.Params(d=2, N=(32, 48), L=(8.0, 9.0), s=0.7, Omega=0.6, gamma=(1.0, 1.2), beta=20.0, lam=3.0,
+                          kernel="coulomb", coef=c2, dt=0.05, name="rot2d"),
+        "ddi3d": W.Params(d=3, N=(24, 24, 16), L=(6.0, 6.0, 5.0), s=0.9, Omega=0.5, gamma=(1.0, 1.0, 2.0),
+                          beta=50.0, lam=-5.0, kernel="ddi3", dt=0.02, name="ddi3d"),
+        "local2d": W.Params(d=2, N=(48, 48), L=(8.0, 8.0), s=0.5, Omega=0.0, gamma=(1.0, 1.0), beta=100.0, lam=0.0,
+                            kernel="none", dt=0.1, name="local2d"),
+    }
+    return cases[name]
+
+
+def _oracle(p):
+    return Problem.from_params(p)
+
+
+def _psi0(p):
+    return ogs.initial_guess(p.N, p.L, p.Omega, p.gamma)
+
+
+def _dev(a, prec):
+    dt = np.complex128 if prec == fse.C128 else np.complex64
+    return torch.from_numpy(np.ascontiguousarray(a.astype(dt))).to("cuda:0")
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("name", ["rot2d", "ddi3d", "local2d"])
+@pytest.mark.parametrize("prec,tol,gate", [(fse.C128, 1e-12, 1e-10), (fse.C64, 1e-6, 1e-5)])
+def test_one_step_against_oracle(name, prec, tol, gate):
+    p = _params(name)
+    psi0 = _psi0(p)
+    g = ogs.GroundState(_oracle(p), p.dt)
+    ref, (oits, ores, odiff) = g.step(psi0, rtol=1e-12)
+    plan = fse.Plan.from_params(p, prec)
+    x = _dev(psi0, prec)
+    st = plan.gs_step(x, p.dt, tol=tol, maxit=500)
+    err = _rel(x.cpu().numpy().astype(np.complex128), ref)
+    _note(f"[gs] {name} prec={prec}: rel L2 {err:.3e}; GPU {st['iterations']} its res {st['residual']:.1e} "
+          f"diff {st['diff_inf']:.3e}; oracle {oits} its diff {odiff:.3e}")
+    assert st["converged"] and st["residual"] <= tol
+    assert err < gate
+    assert abs(st["diff_inf"] - odiff) <= 10 * gate * max(odiff, 1.0)
+    assert abs(plan.mass(x).item() - 1.0) < (1e-13 if prec == fse.C128 else 1e-6)
+
+
+def test_twenty_steps_against_oracle():
+    p = _params("rot2d")
+    psi = _psi0(p)
+    g = ogs.GroundState(_oracle(p), p.dt)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi, fse.C128)
+    for _ in range(20):
+        psi, _ = g.step(psi, rtol=1e-12)
+        plan.gs_step(x, p.dt, tol=1e-12)
+    err = _rel(x.cpu().numpy(), psi)
+    _note(f"[gs] 20 steps rot2d: rel L2 {err:.3e}")
+    assert err < 1e-9
+
+
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_converges_to_linear_harmonic_ground_state(prec):
+    # s = 1, beta = lam = 0, Omega = 0.3 < 1: the Gaussian with energy 1
+    p = W.Params(d=2, N=(32, 32), L=(8.0, 8.0), s=1.0, Omega=0.3, gamma=(1.0, 1.0), beta=0.0, lam=0.0,
+                 kernel="none", dt=1.0, name="ho")
+    plan = fse.Plan.from_params(p, prec)
+    x = _dev(_psi0(p), prec)
+    eps = 1e-10 if prec == fse.C128 else 1e-5
+    tol = 1e-12 if prec == fse.C128 else 1e-6
+    for n in range(400):
+        st = plan.gs_step(x, p.dt, tol=tol)
+        if st["diff_inf"] <= eps * p.dt:
+            break
+    E = plan.energy(x).cpu().numpy()[5]
+    X = np.meshgrid(*axes(p.N, p.L), indexing="ij")
+    ho = np.exp(-(X[0] ** 2 + X[1] ** 2) / 2.0) / math.sqrt(math.pi)
+    y = x.cpu().numpy().astype(np.complex128)
+    ov = abs(0.5 * 0.5 * np.sum(np.conj(ho) * y))  # h = 16/32
+    _note(f"[gs] harmonic prec={prec}: {n + 1} steps, E = {E:.12f}, |<ho, phi>| = {ov:.12f}")
+    assert abs(E - 1.0) < (1e-10 if prec == fse.C128 else 1e-5)
+    assert abs(ov - 1.0) < (1e-10 if prec == fse.C128 else 1e-5)
+
+
+def test_energy_decreases_along_the_flow():
+    p = _params("local2d")
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(_psi0(p), fse.C128)
+    E = [plan.energy(x).cpu().numpy()[5]]
+    for _ in range(30):
+        plan.gs_step(x, p.dt)
+        E.append(plan.energy(x).cpu().numpy()[5])
+    assert np.all(np.diff(E) <= 1e-12)
+
+
+def test_invalid_arguments():
+    p = _params("local2d")
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(_psi0(p), fse.C128)
+    with pytest.raises(fse.FseError):
+        plan.gs_step(x, 0.0)
+    with pytest.raises(fse.FseError):
+        plan.gs_step(x, 0.1, tol=0.0)
+    with pytest.raises(fse.FseError):
+        plan.gs_step(x, 0.1, maxit=0)

@@ -190,6 +190,11 @@ PRESETS = {
     "cfg4": Params(d=3, N=(96, 96, 96), L=(12.0, 12.0, 12.0), s=0.6, Omega=0.4,
                    gamma=(1.0, 1.0, 1.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0,
                    dt=1e-3, steps=200, name="cfg4-3d-96-coulomb"),
+    # ground-state solve at scale: trap and time step not stated; gamma = 1 and
+    # the paper's ground-state time step dt = 1e-3 are taken
+    "cfg5": Params(d=3, N=(256, 256, 256), L=(16.0, 16.0, 16.0), s=0.9, Omega=0.8,
+                   gamma=(1.0, 1.0, 1.0), beta=1000.0, lam=-50.0, kernel="ddi3", mu=1.0,
+                   dt=1e-3, steps=2, name="cfg5-3d-256-gs"),
 }
 
 
