@@ -86,6 +86,9 @@ struct fse_plan_s {
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
     double* gs_out = nullptr;
+    void* pd = nullptr;    // P_Delta table (layout of the kinetic tables) for pd_c0 = 1/dt
+    double pd_c0 = NAN;
+    void* ks = nullptr;    // kinetic symbol omega/2 / n (layout of the kinetic tables), built on first use
     double* partials = nullptr;
     size_t bytes = 0;
     std::vector<void*> allocs;
@@ -261,7 +264,7 @@ template <typename R> fse_status kin_table(fse_plan p, double tau, int slot, voi
         fse_status s = dev_alloc(p, &p->kin[slot], (size_t)T0 * T1 * T2 * p->csize);
         if (s != FSE_OK) return s;
     }
-    HIPCHK(fse::Launch<R>::build_kin(p->kin[slot], T0, T1, T2, dmu(p, 0), dm1, dm2, p->s, p->m * p->m, tau,
+    HIPCHK(fse::Launch<R>::build_kin(p->kin[slot], T0, T1, T2, dmu(p, 0), dm1, dm2, p->s, p->m * p->m, 0, tau, 0.0,
                                      1.0 / (double)p->n, st));
     p->kin_tau[slot] = tau;
     *out = p->kin[slot];
@@ -362,24 +365,6 @@ template <typename R> fse_status potential_impl(fse_plan p, const void* src, int
     return FSE_OK;
 }
 
-template <typename R> fse_status fft_forward(fse_plan p, void* a, hipStream_t st) {
-    using L = fse::Launch<R>;
-    HIPCHK(L::strided(p->N[0], false, 0, a, a, 1, p->C0, p->tw[p->N[0]], nullptr, st));
-    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], nullptr, st));
-    HIPCHK(L::line(p->last(), 2, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()],
-                   nullptr, st));
-    return FSE_OK;
-}
-
-template <typename R> fse_status fft_inverse(fse_plan p, void* a, hipStream_t st) {
-    using L = fse::Launch<R>;
-    HIPCHK(L::line(p->last(), 3, a, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1}, p->tw[p->last()],
-                   nullptr, st));
-    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, p->N[0], p->N[2], p->tw[p->N[1]], nullptr, st));
-    HIPCHK(L::strided(p->N[0], true, 0, a, a, 1, p->C0, p->tw[p->N[0]], nullptr, st));
-    return FSE_OK;
-}
-
 fse_status ensure_diag(fse_plan p) {
     if (p->diag) return FSE_OK;
     return dev_alloc(p, &p->diag, (size_t)p->n * (2 * p->csize + p->rsize));
@@ -442,6 +427,8 @@ template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, do
 }
 
 // Energy / mass / Lz reductions; kind 0 mass, 1 energy, 2 Lz.
+template <typename R> hipError_t deriv_axis(fse_plan p, int axis, const void* v, void* out, hipStream_t st);
+
 template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int kind, double* out, hipStream_t st) {
     using L = fse::Launch<R>;
     const fse::GridGeom g = geom(p);
@@ -475,19 +462,19 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
         // slots 0..4 unused for Lz; keep them defined
         HIPCHK(hipMemsetAsync(p->partials, 0, sizeof(double) * kRedBlocks * 5, st));
     }
-    HIPCHK(hipMemcpyAsync(A, psi, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
-    s = fft_forward<R>(p, A, st);
-    if (s != FSE_OK) return s;
-    if (kind == 1)
+    if (kind == 1) {
+        // kinetic energy by Parseval from the spectrum (first pass out of place)
+        const int N0 = p->N[0];
+        HIPCHK(L::strided(N0, false, 0, psi, A, 1, p->C0, p->tw[N0], nullptr, st));
+        if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, A, A, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+        HIPCHK(L::line(p->last(), 2, A, (int)p->lines_last(), nullptr, fse::LineIdx{1, 0, 0, 1, 1},
+                       p->tw[p->last()], nullptr, st));
         HIPCHK(L::red_kin(A, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, p->partials, 4, kRedBlocks,
                           st));
-    // D_y psi against x, D_x psi against y
+    }
+    // D_y psi against x, D_x psi against y (one derivative pass each)
     for (int pass = 0; pass < 2; ++pass) {
-        const int axis = (pass == 0) ? 1 : 0;
-        HIPCHK(L::fourier_mult(A, B, p->n, g, 0, axis, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
-                               1.0 / (double)p->n, st));
-        s = fft_inverse<R>(p, B, st);
-        if (s != FSE_OK) return s;
+        HIPCHK(deriv_axis<R>(p, pass == 0 ? 1 : 0, psi, B, st));
         HIPCHK(L::red_lz(psi, B, p->n, g, pass == 0 ? 0 : 1, p->partials, 5 + pass, kRedBlocks, st));
     }
     HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, nslot, kind, vol, (double)p->n, p->beta, p->lambda, p->Omega,
@@ -495,36 +482,39 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     return FSE_OK;
 }
 
-template <typename R>
-fse_status apply_H_impl(fse_plan p, const void* psi, void* H, const void* rho, hipStream_t st) {
+template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void* H, const void* rho, hipStream_t st) {
     using L = fse::Launch<R>;
     fse_status s = ensure_diag(p);
     if (s != FSE_OK) return s;
     const fse::GridGeom g = geom(p);
     char* base = static_cast<char*>(p->diag);
-    void* A = base;
     void* B = base + (size_t)p->n * p->csize;
     void* Phi = base + (size_t)p->n * 2 * p->csize;
     if (p->nl) {
         s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, st);
         if (s != FSE_OK) return s;
     }
-    HIPCHK(hipMemcpyAsync(A, psi, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
-    s = fft_forward<R>(p, A, st);
-    if (s != FSE_OK) return s;
-    HIPCHK(L::fourier_mult(A, H, p->n, g, 1, 0, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
-                           1.0 / (double)p->n, st));
-    s = fft_inverse<R>(p, H, st);
-    if (s != FSE_OK) return s;
+    // kinetic part: H = (1/2)(-Lap+m^2)^s psi through the strided forward passes
+    // (the first out of place), one line pass (FFT, times omega/2 / n,
+    // inverse) and the strided inverse passes
+    const int T0 = p->N[0] / 2 + 1, T1 = (p->d == 3) ? p->N[1] / 2 + 1 : 1, T2 = p->last() / 2 + 1;
+    if (!p->ks) {
+        if ((s = dev_alloc(p, &p->ks, (size_t)T0 * T1 * T2 * p->csize)) != FSE_OK) return s;
+        HIPCHK(L::build_kin(p->ks, T0, T1, T2, dmu(p, 0), (p->d == 3) ? dmu(p, 1) : 0.0, dmu(p, p->d - 1), p->s,
+                            p->m * p->m, 2, 0.0, 0.0, 1.0 / (double)p->n, st));
+    }
+    const int N0 = p->N[0], NL = p->last();
+    HIPCHK(L::strided(N0, false, 0, psi, H, 1, p->C0, p->tw[N0], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, H, H, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::line(NL, 1, H, (int)p->lines_last(), p->ks, kin_index(p), p->tw[NL], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, H, H, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::strided(N0, true, 0, H, H, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->Omega != 0.0) {
-        for (int pass = 0; pass < 2; ++pass) {
-            const int axis = (pass == 0) ? 1 : 0;
-            HIPCHK(L::fourier_mult(A, B, p->n, g, 0, axis, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m,
-                                   1.0 / (double)p->n, st));
-            s = fft_inverse<R>(p, B, st);
-            if (s != FSE_OK) return s;
-            HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, pass, p->Omega, 0, 0, 0, 0, 0, st));
-        }
+        // -Omega Lz psi = i Omega (x D_y psi - y D_x psi), one derivative pass per axis
+        HIPCHK(deriv_axis<R>(p, 1, psi, B, st));
+        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, 0, p->Omega, 0, 0, 0, 0, 0, st));
+        HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
+        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, 1, p->Omega, 0, 0, 0, 0, 0, st));
     }
     HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, p->n, g, 2, p->Omega, p->beta, p->lambda,
                       p->gamma[0], p->gamma[1], (p->d == 3) ? p->gamma[2] : 0.0, st));
@@ -555,28 +545,60 @@ fse_status ensure_gs(fse_plan p, GsBuf* b) {
     return FSE_OK;
 }
 
-// out = v + P_Delta (W v - Omega Lz v), c0 = 1/dt.
-template <typename R> fse_status gs_apply_M(fse_plan p, const GsBuf& b, const void* v, void* out, double c0,
-                                            hipStream_t st) {
+// The P_Delta table [c0 + omega/2]^{-1} / n on the kinetic tables' octant,
+// rebuilt when c0 = 1/dt changes.
+template <typename R> fse_status pd_table(fse_plan p, double c0, hipStream_t st) {
+    if (p->pd && p->pd_c0 == c0) return FSE_OK;
+    const int T0 = p->N[0] / 2 + 1, T1 = (p->d == 3) ? p->N[1] / 2 + 1 : 1;
+    const int T2 = p->last() / 2 + 1;
+    if (!p->pd) {
+        fse_status s = dev_alloc(p, &p->pd, (size_t)T0 * T1 * T2 * p->csize);
+        if (s != FSE_OK) return s;
+    }
+    HIPCHK(fse::Launch<R>::build_kin(p->pd, T0, T1, T2, dmu(p, 0), (p->d == 3) ? dmu(p, 1) : 0.0,
+                                     dmu(p, p->d - 1), p->s, p->m * p->m, 1, 0.0, c0, 1.0 / (double)p->n, st));
+    p->pd_c0 = c0;
+    return FSE_OK;
+}
+
+// a <- P_Delta a: the strided forward passes, one line pass (forward FFT of
+// the contiguous axis, times the table, inverse), the strided inverse passes.
+template <typename R> fse_status pd_apply(fse_plan p, void* a, hipStream_t st) {
+    using L = fse::Launch<R>;
+    const int N0 = p->N[0], NL = p->last();
+    HIPCHK(L::strided(N0, false, 0, a, a, 1, p->C0, p->tw[N0], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::line(NL, 1, a, (int)p->lines_last(), p->pd, kin_index(p), p->tw[NL], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::strided(N0, true, 0, a, a, 1, p->C0, p->tw[N0], nullptr, st));
+    return FSE_OK;
+}
+
+// out = D_axis v (axis 0 or 1) in one pass: only the transform along that axis
+// is needed, the multiplier depends on nothing else.
+template <typename R> hipError_t deriv_axis(fse_plan p, int axis, const void* v, void* out, hipStream_t st) {
+    using L = fse::Launch<R>;
+    const int Na = p->N[axis];
+    const double sc = 1.0 / (double)Na;
+    if (axis == 0) return L::deriv(Na, false, v, out, 1, p->C0, p->tw[Na], dmu(p, 0), sc, st);
+    if (p->d == 3) return L::deriv(Na, false, v, out, p->N[0], p->N[2], p->tw[Na], dmu(p, 1), sc, st);
+    return L::deriv(Na, true, v, out, p->N[0], 0, p->tw[Na], dmu(p, 1), sc, st);
+}
+
+// out = v + P_Delta (W v - Omega Lz v) (P_Delta's table is current).
+template <typename R> fse_status gs_apply_M(fse_plan p, const GsBuf& b, const void* v, void* out, hipStream_t st) {
     using L = fse::Launch<R>;
     const fse::GridGeom g = geom(p);
-    const double inv_n = 1.0 / (double)p->n;
     const void *Dx = nullptr, *Dy = nullptr;
     if (p->Omega != 0.0) {
-        HIPCHK(hipMemcpyAsync(b.A, v, (size_t)p->n * p->csize, hipMemcpyDeviceToDevice, st));
-        fse_status s = fft_forward<R>(p, b.A, st);
-        if (s != FSE_OK) return s;
-        HIPCHK(L::gs_grad2(b.A, b.Dx, b.Dy, p->n, g, dmu(p, 0), dmu(p, 1), inv_n, st));
-        if ((s = fft_inverse<R>(p, b.Dx, st)) != FSE_OK) return s;
-        if ((s = fft_inverse<R>(p, b.Dy, st)) != FSE_OK) return s;
+        HIPCHK(deriv_axis<R>(p, 0, v, b.Dx, st));
+        HIPCHK(deriv_axis<R>(p, 1, v, b.Dy, st));
         Dx = b.Dx;
         Dy = b.Dy;
     }
     HIPCHK(L::gs_tf(v, Dx, Dy, b.W, b.A, p->n, g, p->Omega, st));
-    fse_status s = fft_forward<R>(p, b.A, st);
+    fse_status s = pd_apply<R>(p, b.A, st);
     if (s != FSE_OK) return s;
-    HIPCHK(L::gs_pdelta(b.A, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, c0, inv_n, st));
-    if ((s = fft_inverse<R>(p, b.A, st)) != FSE_OK) return s;
     HIPCHK(L::gs_axpy(v, b.A, out, p->n, 1.0, 0.0, st));
     return FSE_OK;
 }
@@ -619,15 +641,13 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     }
     HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
                         (p->d == 3) ? p->gamma[2] : 0.0, st));
+    if ((s = pd_table<R>(p, c0, st)) != FSE_OK) return s;
     // right-hand side P_Delta psi/dt, held in sv until r is formed
-    HIPCHK(hipMemcpyAsync(b.sv, psi, bytes, hipMemcpyDeviceToDevice, st));
-    if ((s = fft_forward<R>(p, b.sv, st)) != FSE_OK) return s;
-    HIPCHK(L::gs_pdelta(b.sv, p->n, g, dmu(p, 0), dmu(p, 1), dmu(p, 2), p->s, p->m * p->m, c0,
-                        c0 / (double)p->n, st));
-    if ((s = fft_inverse<R>(p, b.sv, st)) != FSE_OK) return s;
+    HIPCHK(L::gs_axpy(psi, psi, b.sv, p->n, c0 - 1.0, 0.0, st));  // sv = psi/dt
+    if ((s = pd_apply<R>(p, b.sv, st)) != FSE_OK) return s;
     // x0 = psi, r = rhs - M x0, r0 = p = r
     HIPCHK(hipMemcpyAsync(b.x, psi, bytes, hipMemcpyDeviceToDevice, st));
-    if ((s = gs_apply_M<R>(p, b, b.x, b.v, c0, st)) != FSE_OK) return s;
+    if ((s = gs_apply_M<R>(p, b, b.x, b.v, st)) != FSE_OK) return s;
     HIPCHK(L::gs_axpy(b.sv, b.v, b.r, p->n, -1.0, 0.0, st));
     HIPCHK(hipMemcpyAsync(b.r0, b.r, bytes, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(b.pv, b.r, bytes, hipMemcpyDeviceToDevice, st));
@@ -645,7 +665,7 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     bool conv = res <= tol;
     while (!conv && it < maxit) {
         ++it;
-        if ((s = gs_apply_M<R>(p, b, b.pv, b.v, c0, st)) != FSE_OK) return s;
+        if ((s = gs_apply_M<R>(p, b, b.pv, b.v, st)) != FSE_OK) return s;
         Cplx r0v;
         {
             const void* a[1] = {b.r0};
@@ -666,7 +686,7 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
             conv = true;
             break;
         }
-        if ((s = gs_apply_M<R>(p, b, b.sv, b.t, c0, st)) != FSE_OK) return s;
+        if ((s = gs_apply_M<R>(p, b, b.sv, b.t, st)) != FSE_OK) return s;
         Cplx ts_tt[2];
         {
             const void* a[2] = {b.t, b.t};

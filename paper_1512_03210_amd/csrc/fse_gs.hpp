@@ -60,41 +60,6 @@ __global__ void k_gs_tf(const typename CT<R>::T* __restrict__ v, const typename 
     }
 }
 
-// Derivative spectra of axes 0 and 1 from one spectrum: ox = i mu_0 a * scale,
-// oy = i mu_1 a * scale (Nyquist index kept as -N/2).
-template <typename R>
-__global__ void k_gs_grad2(const typename CT<R>::T* __restrict__ a, typename CT<R>::T* __restrict__ ox,
-                           typename CT<R>::T* __restrict__ oy, long n, GridGeom g, double dmu0, double dmu1,
-                           double scale) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        int i0, i1, i2;
-        decode(i, g, i0, i1, i2);
-        const int p0 = (i0 < g.N0 / 2) ? i0 : i0 - g.N0;
-        const int p1 = (i1 < g.N1 / 2) ? i1 : i1 - g.N1;
-        const double2 v = gsd::up(a[i]);
-        const double fx = p0 * dmu0 * scale, fy = p1 * dmu1 * scale;
-        ox[i] = gsd::down<R>(double2{-v.y * fx, v.x * fx});
-        oy[i] = gsd::down<R>(double2{-v.y * fy, v.x * fy});
-    }
-}
-
-// In place: a *= scale / (c0 + (1/2)(|mu|^2 + m^2)^s)   (P_Delta with c0 = 1/dt).
-template <typename R>
-__global__ void k_gs_pdelta(typename CT<R>::T* __restrict__ a, long n, GridGeom g, double dmu0, double dmu1,
-                            double dmu2, double s, double m2, double c0, double scale) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        int i0, i1, i2;
-        decode(i, g, i0, i1, i2);
-        const int p0 = (i0 < g.N0 / 2) ? i0 : i0 - g.N0;
-        const int p1 = (i1 < g.N1 / 2) ? i1 : i1 - g.N1;
-        const int p2 = (g.d == 3) ? ((i2 < g.N2 / 2) ? i2 : i2 - g.N2) : 0;
-        const double q = (p0 * dmu0) * (p0 * dmu0) + (p1 * dmu1) * (p1 * dmu1) + (p2 * dmu2) * (p2 * dmu2) + m2;
-        const double f = scale / (c0 + 0.5 * ((q > 0.0) ? pow(q, s) : 0.0));
-        const double2 v = gsd::up(a[i]);
-        a[i] = gsd::down<R>(double2{v.x * f, v.y * f});
-    }
-}
-
 // out = a + c b (c complex, FP64); out may be a.
 template <typename R>
 __global__ void k_gs_axpy(const typename CT<R>::T* a, const typename CT<R>::T* __restrict__ b,

@@ -136,6 +136,53 @@ __global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<
 }
 
 // ---------------------------------------------------------------------------
+// Fourier derivative along a strided axis in one pass: forward FFT of the
+// column, times i mu_p * scale (mu_p = p * dmu, p = e for e < N/2, else
+// e - N, the Nyquist index kept as -N/2), inverse FFT with the reversed plan
+// (no LDS traffic between the two), out of place allowed.
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__device__ __forceinline__ void cols_deriv_body(const typename CT<R>::T* in, typename CT<R>::T* out, int B2,
+                                                const typename CT<R>::T* twN, double dmu, double scale, int bx,
+                                                int by, typename CT<R>::T* lds) {
+    using T = typename CT<R>::T;
+    using C = ColCfg<R, N>;
+    constexpr int W = C::W, TPL = C::TPL;
+    constexpr int P = pitch_cols<N>(N);
+    using FF = Fft<T, N, false, TPL, FwdPlan<N>>;
+    using FI = Fft<T, N, true, TPL, InvPlan<N>>;
+    const int l = threadIdx.x % W, jt = threadIdx.x / W;
+    const int col0 = bx * W;
+    const bool lv = (col0 + l) < B2;
+    T* line = lds + l * P;
+    const T* g = in + (long)by * N * B2 + col0 + l;
+    T* o = out + (long)by * N * B2 + col0 + l;
+    typename FF::In v;
+    typename FF::Out u;
+    for_pos<N, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = lv ? g[(long)e * B2] : T{0, 0}; });
+    FF::run(v, u, line, jt, twN);
+    for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
+        const R f = R(((e < N / 2) ? e : e - N) * dmu * scale);
+        u[b][r] = T{-u[b][r].y * f, u[b][r].x * f};
+    });
+    typename FI::Out w;
+    __syncthreads();
+    FI::run(u, w, line, jt, twN);
+    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+        if (lv) o[(long)e * B2] = w[b][r];
+    });
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols_deriv(const typename CT<R>::T* in,
+                                                                     typename CT<R>::T* out, int B2,
+                                                                     const typename CT<R>::T* twN, double dmu,
+                                                                     double scale) {
+    __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols<N>(N)];
+    cols_deriv_body<R, N>(in, out, B2, twN, dmu, scale, blockIdx.x, blockIdx.y, lds);
+}
+
+// ---------------------------------------------------------------------------
 // Zero-padded transforms of a strided axis as one length-M = 2N transform
 // per column: PAD = 1, forward, N rows in (the first stage skips the zero
 // half) and 2N rows out; PAD = 2, inverse, 2N rows in and only the first N
@@ -301,6 +348,45 @@ __global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
     const typename CT<R>::T* twN, const typename CT<R>::T* tw2) {
     __shared__ typename CT<R>::T lds[LineCfg<R, N, (MODE) == 0>::LPB * LineCfg<R, N, (MODE) == 0>::SUB * LineCfg<R, N, (MODE) == 0>::P];
     lines_body<R, N, MODE>(data, nlines, mult, li, twN, tw2, blockIdx.x, blockIdx.y, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Fourier derivative along the contiguous axis in one pass (as
+// cols_deriv_body, whole lines), out of place allowed.
+// ---------------------------------------------------------------------------
+template <typename R, int N>
+__global__ __launch_bounds__((LineCfg<R, N, false>::NTH)) void k_lines_deriv(const typename CT<R>::T* in,
+                                                                              typename CT<R>::T* out, int nlines,
+                                                                              const typename CT<R>::T* twN,
+                                                                              double dmu, double scale) {
+    using T = typename CT<R>::T;
+    using C = LineCfg<R, N, false>;
+    constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
+    constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
+    using FF = Fft<T, N, false, TPL, FwdPlan<N>, WS, 2>;
+    using FI = Fft<T, N, true, TPL, InvPlan<N>, WS, 2>;
+    __shared__ T lds[LPB * P];
+    const int jt = threadIdx.x % TPL;
+    const int dl = threadIdx.x / TPL;
+    const int gl = blockIdx.x * LPB + dl;
+    const bool valid = gl < nlines;
+    T* line = lds + dl * P;
+    const T* g = in + (long)(valid ? gl : 0) * N;  // a line past the end reads line 0 and stores nothing
+    T* o = out + (long)gl * N;
+    typename FF::In v;
+    typename FF::Out u;
+    for_pos<N, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = g[e]; });
+    FF::run(v, u, line, jt, twN);
+    for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
+        const R f = R(((e < N / 2) ? e : e - N) * dmu * scale);
+        u[b][r] = T{-u[b][r].y * f, u[b][r].x * f};
+    });
+    typename FI::Out w;
+    lds_sync<WS>();
+    FI::run(u, w, line, jt, twN);
+    for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
+        if (valid) o[e] = w[b][r];
+    });
 }
 
 // ---------------------------------------------------------------------------
@@ -665,10 +751,12 @@ static __global__ void k_b_time(const BInst* __restrict__ bi, int count, int nst
 // Kinetic phase table Q[k0][k1][k2] = scale * exp(-i tau omega/2),
 // omega = (|mu|^2 + m^2)^s, mu_j = k_j * dmu_j, k_j = 0..N_j/2 (the table is
 // even in each frequency index).  FP64 arithmetic, rounded to the path type.
+// kind 1: the real resolvent scale / (c0 + omega/2) instead; kind 2: the real
+// symbol scale * omega/2.
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void k_build_kin(typename CT<R>::T* __restrict__ Q, int T0, int T1, int T2, double dmu0, double dmu1,
-                            double dmu2, double s, double m2, double tau, double scale) {
+                            double dmu2, double s, double m2, int kind, double tau, double c0, double scale) {
     using T = typename CT<R>::T;
     const long n = (long)T0 * T1 * T2;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -679,6 +767,14 @@ __global__ void k_build_kin(typename CT<R>::T* __restrict__ Q, int T0, int T1, i
         const double a = k0 * dmu0, b = k1 * dmu1, c = k2 * dmu2;
         const double q = a * a + b * b + c * c + m2;
         const double om = (q > 0.0) ? pow(q, s) : 0.0;
+        if (kind == 1) {  // resolvent [c0 + omega/2]^{-1} (the P_Delta preconditioner, c0 = 1/dt)
+            Q[i] = T{R(scale / (c0 + 0.5 * om)), R(0)};
+            continue;
+        }
+        if (kind == 2) {  // the kinetic symbol omega/2 itself
+            Q[i] = T{R(scale * 0.5 * om), R(0)};
+            continue;
+        }
         double sn, cs;
         sincos(-0.5 * tau * om, &sn, &cs);
         if constexpr (sizeof(R) == 4) {
@@ -855,34 +951,8 @@ static __global__ __launch_bounds__(RED_THREADS) void k_red_final(const double* 
 }
 
 // ---------------------------------------------------------------------------
-// Elementwise helpers for the diagnostics and H*psi.
+// Elementwise helper for H*psi.
 // ---------------------------------------------------------------------------
-// out = in * f(k) * scale; f = i mu_axis (WHAT 0) or omega/2 (WHAT 1).
-template <typename R>
-__global__ void k_fourier_mult(const typename CT<R>::T* __restrict__ in, typename CT<R>::T* __restrict__ out, long n,
-                               GridGeom g, int what, int axis, double dmu0, double dmu1, double dmu2, double s,
-                               double m2, double scale) {
-    using T = typename CT<R>::T;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        int i0, i1, i2;
-        decode(i, g, i0, i1, i2);
-        const int p0 = (i0 < g.N0 / 2) ? i0 : i0 - g.N0;
-        const int p1 = (i1 < g.N1 / 2) ? i1 : i1 - g.N1;
-        const int p2 = (g.d == 3) ? ((i2 < g.N2 / 2) ? i2 : i2 - g.N2) : 0;
-        const T v = in[i];
-        if (what == 0) {
-            const double mu = (axis == 0) ? p0 * dmu0 : (axis == 1 ? p1 * dmu1 : p2 * dmu2);
-            const double f = mu * scale;
-            out[i] = T{R(-v.y * f), R(v.x * f)};
-        } else {
-            const double a = p0 * dmu0, b = p1 * dmu1, c = p2 * dmu2;
-            const double q = a * a + b * b + c * c + m2;
-            const double f = 0.5 * ((q > 0.0) ? pow(q, s) : 0.0) * scale;
-            out[i] = T{R(v.x * f), R(v.y * f)};
-        }
-    }
-}
-
 // H psi accumulation:
 //   WHAT 0: H += i Omega x D  (D = D_y psi)
 //   WHAT 1: H += -i Omega y D (D = D_x psi)
