@@ -27,7 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "grid-point-steps/s and % HBM roofline, 3D 256³ split step, FP32-batched vs FP64"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_m0_256cube.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_split_step_256cube.json")
 
 
 def kernel_source_hash():
@@ -381,7 +381,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="m0", choices=["m0", "cfg2", "cfg1"])
+    ap.add_argument("--workload", default="dipole3d_256", choices=["dipole3d_256", "dipole3d_128", "plain2d"])
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--no-c64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -423,7 +423,7 @@ def main():
         ops["c64"] = run_ops(p, fse.C64)
     cases = {}
     if args.cases:
-        for name, steps in (("cfg2", 1000), ("cfg1", 100)):
+        for name, steps in (("dipole3d_128", 1000), ("plain2d", 100)):
             q = W.preset(name)
             print(f"[bench] case {q.name}: {steps} steps", file=sys.stderr, flush=True)
             cases[q.name] = {"c128": run_case(q, fse.C128, steps)}
@@ -431,7 +431,7 @@ def main():
                 cases[q.name]["c64"] = run_case(q, fse.C64, steps)
     gs = None
     if args.gs_steps > 0:
-        q = W.preset("cfg5")
+        q = W.preset("gs3d_256")
         print(f"[bench] ground state {q.name}: {args.gs_steps} steps", file=sys.stderr, flush=True)
         gs = {"workload": (f"{q.name}: {'x'.join(map(str, q.N))} on [-{q.L[0]:g},{q.L[0]:g}]^3, s={q.s}, "
                            f"Omega={q.Omega}, beta={q.beta}, lambda={q.lam} z-dipole GauSum, dt={q.dt}, "

@@ -88,7 +88,7 @@ def test_apply_H_eigenstates_s1():
 
 def test_apply_H_expectation_is_energy_plus_interactions():
     # <psi, H psi> = E + E_int + E_non (the chemical-potential identity).
-    p = W.preset("cfg1")
+    p = W.preset("plain2d")
     pr = scheme.Problem.from_params(p)
     psi = W.harmonic_vortex_2d(p.N, p.L, seed=4)
     vol = np.prod(pr.h)
@@ -99,7 +99,7 @@ def test_apply_H_expectation_is_energy_plus_interactions():
 
 
 def test_apply_H_frozen_density():
-    p = W.preset("cfg1")
+    p = W.preset("plain2d")
     pr = scheme.Problem.from_params(p)
     psi = W.harmonic_vortex_2d(p.N, p.L, seed=5)
     rho = np.abs(psi) ** 2

@@ -97,7 +97,7 @@ def test_nonlinear_substep_solves_the_pointwise_ode():
 
 
 def test_mass_conserved_and_step_reversible():
-    p = W.preset("cfg1")
+    p = W.preset("plain2d")
     pr = scheme.Problem.from_params(p)
     psi0 = W.harmonic_vortex_2d(p.N, p.L, seed=0)
     psi, t = pr.run(psi0, 20, p.dt)

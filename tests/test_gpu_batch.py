@@ -72,7 +72,7 @@ def test_batch_graph_replays_with_eager_work_between():
     states = _states(params, seed0=20)
     b = fse.Batch(params, fse.C128)
     x = b.pack(states)
-    other = fse.Plan.from_params(W.preset("cfg1"), fse.C128)
+    other = fse.Plan.from_params(W.preset("plain2d"), fse.C128)
     y = torch.from_numpy(W.harmonic_vortex_2d((64, 64), (8.0, 8.0), seed=1)).cuda()
     for rep in range(1, 4):
         b.step(x, 2)          # first call captures, the others replay the same graph

@@ -34,7 +34,7 @@ def _require_gpu():
 
 @pytest.fixture(scope="module")
 def oracle_run():
-    p = W.preset("cfg1")
+    p = W.preset("plain2d")
     psi0 = W.initial_state(p, seed=0)
     pr = scheme.Problem.from_params(p)
     ref, t = pr.run(psi0, STEPS, p.dt)

@@ -60,7 +60,7 @@ def _oracle_problem(p):
 
 def P(name, **kw):
     base = dict(
-        cfg1=W.preset("cfg1"),
+        plain2d=W.preset("plain2d"),
         aniso2d=W.Params(d=2, N=(48, 96), L=(6.0, 9.0), s=1.2, Omega=0.6, gamma=(1.0, 1.4), beta=30.0, lam=2.0,
                          kernel="coulomb", coef=1.0, dt=2e-3, name="aniso2d"),
         coul3d=W.Params(d=3, N=(32, 24, 16), L=(6.0, 5.0, 4.0), s=0.8, Omega=0.7, gamma=(1.0, 1.3, 2.0),
@@ -90,7 +90,7 @@ def _psi0(p, seed=0):
     return W.anisotropic_gaussian(p.N, p.L, p.gamma, seed=seed)
 
 
-CASES = ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d"]
+CASES = ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -123,12 +123,12 @@ def test_one_step_c64(name):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d"])
 def test_many_steps_fsal_against_plain_oracle(name):
     # merged half steps inside one call vs the oracle's plain scheme; the
     # anisotropic rotating cases exercise the time-dependent trap integral.
     p = P(name)
-    n = 100 if name == "cfg1" else 20
+    n = 100 if name == "plain2d" else 20
     _note(f"[parity] {n} steps c128 {name}")
     psi0 = _psi0(p)
     ref, t = _oracle_problem(p).run(psi0, n, p.dt)
@@ -153,7 +153,7 @@ def test_split_calls_continue_the_trajectory():
     assert _rel(_host(a), ref) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "big2d", "big2d_t", "rad3_3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "big2d", "big2d_t", "rad3_3d"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_nonlocal_potential(name, prec):
     p = P(name)
@@ -175,7 +175,7 @@ def test_symbol_of_plan_matches_oracle():
     assert np.max(np.abs(K - Ko)) < 1e-11 * np.max(np.abs(Ko))
 
 
-@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "local3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local3d"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_diagnostics(name, prec):
     p = P(name)
@@ -196,7 +196,7 @@ def test_diagnostics(name, prec):
     assert abs(lz - dg.angular_momentum(xin, p.N, p.L)) < tol
 
 
-@pytest.mark.parametrize("name", ["cfg1", "aniso2d", "coul3d", "ddi3d", "local2d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d"])
 @pytest.mark.parametrize("frozen", [False, True])
 def test_apply_H(name, frozen):
     p = P(name)
@@ -215,7 +215,7 @@ def test_apply_H(name, frozen):
 
 
 def test_apply_H_c64():
-    p = P("cfg1")
+    p = P("plain2d")
     psi0 = _psi0(p, seed=4)
     ref = dg.apply_H(_oracle_problem(p), psi0)
     plan = fse.Plan.from_params(p, fse.C64)
@@ -264,7 +264,7 @@ def test_deterministic_rerun():
 
 
 def test_invalid_calls_raise():
-    p = P("cfg1")
+    p = P("plain2d")
     plan = fse.Plan.from_params(p, fse.C128)
     x = _dev(_psi0(p))
     with pytest.raises(fse.FseError):
@@ -284,7 +284,7 @@ def test_invalid_calls_raise():
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_full_size_free_evolution(prec):
-    p = W.preset("m0").replace(beta=0.0, lam=0.0, kernel="none", gamma=(0.0, 0.0, 0.0))
+    p = W.preset("dipole3d_256").replace(beta=0.0, lam=0.0, kernel="none", gamma=(0.0, 0.0, 0.0))
     _note(f"[full] free evolution 256^3 prec={prec}")
     psi0 = W.anisotropic_gaussian(p.N, p.L, (1.0, 1.0, 2.0), seed=0)
     plan = fse.Plan.from_params(p, prec)
@@ -315,8 +315,8 @@ def test_full_size_potential_closed_form():
 
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_full_size_step_invariants(prec):
-    p = W.preset("m0")
-    _note(f"[full] m0 invariants prec={prec}")
+    p = W.preset("dipole3d_256")
+    _note(f"[full] 256^3 invariants prec={prec}")
     psi0 = W.initial_state(p, seed=0)
     plan = fse.Plan.from_params(p, prec)
     x = _dev(psi0, prec)
@@ -332,7 +332,7 @@ def test_full_size_step_invariants(prec):
 
 
 def test_full_size_fsal_split_equals_single_call():
-    p = W.preset("m0")
+    p = W.preset("dipole3d_256")
     psi0 = W.initial_state(p, seed=1)
     a = _dev(psi0)
     b = _dev(psi0)
@@ -342,13 +342,13 @@ def test_full_size_fsal_split_equals_single_call():
     pb.step(b, 2, p.dt)
     pb.step(b, 2, p.dt)
     err = _rel(_host(a), _host(b))
-    _note(f"[full] m0 4 steps vs 2+2: {err:.3e}")
+    _note(f"[full] 256^3 4 steps vs 2+2: {err:.3e}")
     assert err < 1e-13
 
 
-def test_cfg2_against_oracle_two_steps():
-    p = W.preset("cfg2")
-    _note("[full] cfg2 128^3 two steps vs oracle")
+def test_dipole3d_128_against_oracle_two_steps():
+    p = W.preset("dipole3d_128")
+    _note("[full] 128^3 dipolar two steps vs oracle")
     psi0 = W.initial_state(p, seed=0)
     ref, _ = _oracle_problem(p).run(psi0, 2, p.dt)
     for prec, tol in [(fse.C128, 1e-12), (fse.C64, 1e-5)]:

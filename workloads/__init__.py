@@ -171,30 +171,30 @@ def vortex_lattice_2d(N, L, seed=0, nv=7, radius=1.5, jitter=0.05, width2=2.0):
 
 # ---------------------------------------------------------------------------
 # Named parameter sets.
-#   cfg1: 2D plain method, 64^2 on [-8,8]^2, Coulomb GauSum on 128^2 padding.
-#   cfg2: 3D 128^3 on [-12,12]^3, z-dipole GauSum on 256^3 padding.
-#   m0:   the same physics as cfg2 on a 256^3 grid (512^3 padding): the
+#   plain2d:      2D plain method, 64^2 on [-8,8]^2, Coulomb GauSum on 128^2 padding.
+#   dipole3d_128: 3D 128^3 on [-12,12]^3, z-dipole GauSum on 256^3 padding.
+#   dipole3d_256: the same physics on a 256^3 grid (512^3 padding): the
 #         headline 3D 256^3 split step.
-#   cfg4: 3D 96^3 Coulomb (used here only as a parity case).
+#   coulomb3d_96: 3D 96^3 Coulomb (used here only as a parity case).
 # ---------------------------------------------------------------------------
 PRESETS = {
-    "cfg1": Params(d=2, N=(64, 64), L=(8.0, 8.0), s=0.75, Omega=0.5, gamma=(1.0, 1.0),
+    "plain2d": Params(d=2, N=(64, 64), L=(8.0, 8.0), s=0.75, Omega=0.5, gamma=(1.0, 1.0),
                    beta=100.0, lam=1.0, kernel="coulomb", mu=1.0, dt=1e-3, steps=100,
-                   name="cfg1-2d-64"),
-    "cfg2": Params(d=3, N=(128, 128, 128), L=(12.0, 12.0, 12.0), s=0.8, Omega=0.7,
+                   name="plain2d-64"),
+    "dipole3d_128": Params(d=3, N=(128, 128, 128), L=(12.0, 12.0, 12.0), s=0.8, Omega=0.7,
                    gamma=(1.0, 1.0, 2.0), beta=200.0, lam=50.0, kernel="ddi3", mu=1.0,
-                   dt=5e-4, steps=1000, name="cfg2-3d-128-ddi"),
-    "m0": Params(d=3, N=(256, 256, 256), L=(12.0, 12.0, 12.0), s=0.8, Omega=0.7,
+                   dt=5e-4, steps=1000, name="dipole3d-128"),
+    "dipole3d_256": Params(d=3, N=(256, 256, 256), L=(12.0, 12.0, 12.0), s=0.8, Omega=0.7,
                  gamma=(1.0, 1.0, 2.0), beta=200.0, lam=50.0, kernel="ddi3", mu=1.0,
-                 dt=5e-4, steps=100, name="m0-3d-256-ddi"),
-    "cfg4": Params(d=3, N=(96, 96, 96), L=(12.0, 12.0, 12.0), s=0.6, Omega=0.4,
+                 dt=5e-4, steps=100, name="dipole3d-256"),
+    "coulomb3d_96": Params(d=3, N=(96, 96, 96), L=(12.0, 12.0, 12.0), s=0.6, Omega=0.4,
                    gamma=(1.0, 1.0, 1.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0,
-                   dt=1e-3, steps=200, name="cfg4-3d-96-coulomb"),
+                   dt=1e-3, steps=200, name="coulomb3d-96"),
     # ground-state solve at scale: trap and time step not stated; gamma = 1 and
     # the paper's ground-state time step dt = 1e-3 are taken
-    "cfg5": Params(d=3, N=(256, 256, 256), L=(16.0, 16.0, 16.0), s=0.9, Omega=0.8,
+    "gs3d_256": Params(d=3, N=(256, 256, 256), L=(16.0, 16.0, 16.0), s=0.9, Omega=0.8,
                    gamma=(1.0, 1.0, 1.0), beta=1000.0, lam=-50.0, kernel="ddi3", mu=1.0,
-                   dt=1e-3, steps=2, name="cfg5-3d-256-gs"),
+                   dt=1e-3, steps=2, name="groundstate3d-256"),
 }
 
 
@@ -205,7 +205,7 @@ def preset(name: str, **kw) -> Params:
 
 def initial_state(p: Params, seed: int = 0) -> np.ndarray:
     """The seeded initial state used for a parameter set (complex128)."""
-    if p.d == 2 and p.name.startswith("cfg1"):
+    if p.d == 2 and p.name.startswith("plain2d"):
         return harmonic_vortex_2d(p.N, p.L, seed=seed)
     if p.d == 2:
         return vortex_lattice_2d(p.N, p.L, seed=seed)
