@@ -22,9 +22,14 @@ the readings below, which the paper leaves open:
   truncated 1/(4 pi |x|) kernel.  This is the kernel's own symbol in eq.
   Kernel; the displayed reformulation at the end of Section 2 carries a sign
   and factor slip.
+* 2D dipole along n = (n_perp, n3): Phi = -(3/2)(d_{n_perp n_perp} - n3^2
+  Lap_perp)(1/(2 pi |x|)) * rho (eq. Kernel), i.e. the multiplier
+  (3/2)[(n_perp.kappa)^2 - n3^2 |kappa|^2] Khat_C with Khat_C the symbol of
+  the truncated 1/(2 pi |x|) kernel; applying the Coulomb kernel to the
+  modified density of Section 2 is the same product in Fourier space.
 
 Parity: pinned by closed forms (erf(r)/r Coulomb potential of a 3D
-Gaussian, the 2D Bessel form, the dipolar derivative form), a brute-force
+Gaussian, the 2D Bessel form, the 3D and 2D dipolar derivative forms), a brute-force
 O(N^{2d}) linear convolution on tiny grids, the Gaussian-sum accuracy check
 and two independent evaluations of the 1D integrals G (tests/oracle).
 """
@@ -164,11 +169,26 @@ def ddi3_symbol(N, L, delta=None, ht=0.14, axis=(0.0, 0.0, 1.0)):
     return -1.0 + 3.0 * nk ** 2 * KC
 
 
-def symbol(N, L, kernel, mu=1.0, c=1.0, delta=None):
+def ddi2_symbol(N, L, delta=None, ht=0.14, axis=(0.0, 0.0, 1.0)):
+    """2D dipolar multiplier (3/2)[(n_perp.kappa)^2 - n3^2 |kappa|^2] Khat_C, Khat_C for 1/(2 pi |x|)."""
+    KC = coulomb_symbol(N, L, mu=1.0, c=1.0 / (2.0 * math.pi), delta=delta, ht=ht)
+    kap = padded_frequencies(N, L)
+    k0, k1 = kap[0][:, None], kap[1][None, :]
+    nk = axis[0] * k0 + axis[1] * k1
+    return 1.5 * (nk ** 2 - axis[2] ** 2 * (k0 ** 2 + k1 ** 2)) * KC
+
+
+def symbol(N, L, kernel, mu=1.0, c=1.0, delta=None, axis=(0.0, 0.0, 1.0)):
     if kernel == "coulomb":
         return coulomb_symbol(N, L, mu=mu, c=c, delta=delta)
     if kernel == "ddi3":
-        return ddi3_symbol(N, L, delta=delta)
+        if len(N) != 3:
+            raise ValueError("the 3D dipolar kernel needs d = 3")
+        return ddi3_symbol(N, L, delta=delta, axis=axis)
+    if kernel == "ddi2":
+        if len(N) != 2:
+            raise ValueError("the 2D dipolar kernel needs d = 2")
+        return ddi2_symbol(N, L, delta=delta, axis=axis)
     raise ValueError(kernel)
 
 
@@ -182,10 +202,10 @@ def convolve(rho, K):
     return np.real(out[tuple(slice(0, n) for n in N)])
 
 
-def potential(rho, N, L, kernel, mu=1.0, c=1.0, delta=None, K=None):
+def potential(rho, N, L, kernel, mu=1.0, c=1.0, delta=None, K=None, axis=(0.0, 0.0, 1.0)):
     """Phi[rho] = (U * rho) on the grid, via the GauSum multiplier."""
     if K is None:
-        K = symbol(N, L, kernel, mu=mu, c=c, delta=delta)
+        K = symbol(N, L, kernel, mu=mu, c=c, delta=delta, axis=axis)
     return convolve(rho, K)
 
 

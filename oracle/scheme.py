@@ -11,7 +11,7 @@ Oracle (test infrastructure only).  Follows Section 4.2 of the paper:
 * Nonlinear sub-step (eqs. 2stepA/B): the density is constant in time, so
   the solution is phi * exp(-i[tau beta rho + lam * K~ * rho + P]) with
   K~ = tau * U for a Coulomb kernel or a dipole along z (the rotating axis
-  m(t) = A^{-1} n equals n then), and P = int V(A(s) x~) ds (eq. int_poten).
+  m(t) = A^{-1} n equals n then; any fixed axis without rotation), and P = int V(A(s) x~) ds (eq. int_poten).
 * TS2-GauSum (eqs. tssp1-tssp3): half linear step, full nonlinear step,
   half linear step.
 
@@ -115,18 +115,23 @@ class Problem:
     """Parameters of one instance plus its GauSum multiplier (built once)."""
 
     def __init__(self, d, N, L, s, Omega, gamma, beta, lam, kernel="coulomb", mu=1.0, c=1.0,
-                 m=0.0, delta=None):
+                 m=0.0, delta=None, axis=(0.0, 0.0, 1.0)):
         self.d, self.N, self.L = int(d), tuple(int(n) for n in N), tuple(float(x) for x in L)
         self.s, self.Omega, self.gamma = float(s), float(Omega), tuple(float(g) for g in gamma)
         self.beta, self.lam, self.kernel = float(beta), float(lam), kernel
         self.mu, self.c, self.m = float(mu), float(c), float(m)
         self.delta = delta
+        self.axis = tuple(float(a) for a in axis)
+        if kernel in ("ddi2", "ddi3") and self.Omega != 0.0 and (self.axis[0] != 0.0 or self.axis[1] != 0.0):
+            # in the rotating Lagrangian frame the axis m(t) = A^{-1}(t) n turns
+            # unless n is the rotation axis (eq. Kernel_Rot)
+            raise NotImplementedError("a rotating dipole axis m(t) is not implemented")
         self._K = None
 
     @classmethod
     def from_params(cls, p):
         return cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kernel=p.kernel,
-                   mu=p.mu, c=p.c, m=p.m)
+                   mu=p.mu, c=p.c, m=p.m, axis=p.axis)
 
     @property
     def h(self):
@@ -136,7 +141,7 @@ class Problem:
     def K(self):
         if self._K is None and self.kernel != "none" and self.lam != 0.0:
             self._K = gausum.symbol(self.N, self.L, self.kernel, mu=self.mu, c=self.c,
-                                    delta=self.delta)
+                                    delta=self.delta, axis=self.axis)
         return self._K
 
     def potential(self, rho):

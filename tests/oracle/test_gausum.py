@@ -47,17 +47,19 @@ def test_coulomb_2d_gaussian_closed_form():
     assert abs(vol * np.sum(phi * rho) - c * math.sqrt(math.pi / 2.0)) < 1e-13
 
 
-def test_ddi3_gaussian_closed_form():
-    # Phi = -rho - 3 d_zz [erf(r)/(4 pi r)] for the z-dipole kernel.
+@pytest.mark.parametrize("ax", [2, 0, 1])
+def test_ddi3_gaussian_closed_form(ax):
+    # Phi = -rho - 3 d_nn [erf(r)/(4 pi r)] for a dipole along coordinate axis ax.
     N, L = (48, 48, 48), (6.0, 6.0, 6.0)
     X, r = _radius(N, L)
     rho = math.pi ** -1.5 * np.exp(-r ** 2)
-    phi = gausum.potential(rho, N, L, "ddi3")
+    axis = tuple(1.0 if j == ax else 0.0 for j in range(3))
+    phi = gausum.potential(rho, N, L, "ddi3", axis=axis)
     rs = np.where(r > 0, r, 1.0)
     g = 2.0 / math.sqrt(math.pi) * np.exp(-rs ** 2)
     fp = g / rs - special.erf(rs) / rs ** 2
     fpp = -2.0 * g - 2.0 * g / rs ** 2 + 2.0 * special.erf(rs) / rs ** 3
-    z = X[2]
+    z = X[ax]
     dzz = fpp * z ** 2 / rs ** 2 + fp * (1.0 / rs - z ** 2 / rs ** 3)
     dzz = np.where(r > 0, dzz, -4.0 / (3.0 * math.sqrt(math.pi)))
     exact = -rho - 3.0 * dzz / (4.0 * math.pi)
@@ -85,6 +87,64 @@ def test_ddi3_anisotropic_energy_by_radial_quadrature():
         return (-1.0 + 3.0 * u * u) * radial
     val, _ = integrate.quad(integrand, -1.0, 1.0, epsabs=1e-15, epsrel=1e-14)
     exact = 2.0 * math.pi * val / (2.0 * math.pi) ** 3
+    assert abs(got - exact) < 1e-12 * max(1.0, abs(exact))
+
+
+def _ddi2_exact(X, axis):
+    # Phi = -(3/2)[d_{n_perp n_perp} - n3^2 Lap_perp] f with f = c sqrt(pi) e^{-a} I0(a),
+    # a = r^2/2, c = 1/(2 pi) (the 2D Coulomb potential of rho = exp(-r^2)/pi).
+    # With g(a) = e^{-a} I0(a): d_ij f = c sqrt(pi) [g'(a) delta_ij + g''(a) x_i x_j].
+    x, y = X
+    a = (x * x + y * y) / 2.0
+    i0, i1 = special.i0e(a), special.i1e(a)
+    i1_over_a = np.where(a > 0, i1 / np.where(a > 0, a, 1.0), 0.5)
+    g1 = i1 - i0
+    g2 = 2.0 * i0 - 2.0 * i1 - i1_over_a
+    pre = math.sqrt(math.pi) / (2.0 * math.pi)
+    dxx, dyy, dxy = pre * (g1 + g2 * x * x), pre * (g1 + g2 * y * y), pre * g2 * x * y
+    n1, n2, n3 = axis
+    return -1.5 * (n1 * n1 * dxx + 2.0 * n1 * n2 * dxy + n2 * n2 * dyy - n3 * n3 * (dxx + dyy))
+
+
+@pytest.mark.parametrize("axis", [(0.0, 0.0, 1.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.6, 0.0, 0.8),
+                                  (0.36, 0.48, 0.8)])
+def test_ddi2_gaussian_closed_form(axis):
+    # 2D dipole (eq. Kernel): Phi = -(3/2)(d_{n_perp n_perp} - n3^2 Lap_perp)(1/(2 pi |x|)) * rho,
+    # rho = exp(-r^2)/pi, against the second derivatives of the Bessel form.
+    # A non-square box separates the two in-plane axes.
+    N, L = (64, 56), (8.0, 7.0)
+    X, r = _radius(N, L)
+    rho = np.exp(-r ** 2) / math.pi
+    phi = gausum.potential(rho, N, L, "ddi2", axis=axis)
+    exact = _ddi2_exact(X, axis)
+    assert np.linalg.norm(phi - exact) / np.linalg.norm(exact) < 1e-12
+    # Interaction energy (2 pi)^-2 int m(k) |rho_hat|^2 dk with rho_hat = exp(-k^2/4):
+    # m = (3/2)|k|[(n_perp.k_hat)^2 - n3^2]; angular mean of (n_perp.k_hat)^2 is |n_perp|^2/2.
+    vol = np.prod([2 * l / n for n, l in zip(N, L)])
+    nperp2 = axis[0] ** 2 + axis[1] ** 2
+    exact_e = 1.5 * (nperp2 / 2.0 - axis[2] ** 2) * math.sqrt(math.pi / 2.0) / (2.0 * math.pi)
+    assert abs(vol * np.sum(phi * rho) - exact_e) < 1e-12
+
+
+def test_ddi2_energy_of_anisotropic_gaussian_by_angular_quadrature():
+    # rho with widths (a, b): int Phi rho = (2 pi)^-2 int m(k) |rho_hat|^2 dk,
+    # |rho_hat|^2 = exp(-(k1^2 a^2 + k2^2 b^2)/2); the radial integral in closed form.
+    a, b = 1.0, 0.6
+    axis = (1.0, 0.0, 0.0)
+    N, L = (64, 64), (8.0, 8.0)
+    X, _ = _radius(N, L)
+    rho = np.exp(-X[0] ** 2 / a ** 2 - X[1] ** 2 / b ** 2) / (math.pi * a * b)
+    phi = gausum.potential(rho, N, L, "ddi2", axis=axis)
+    vol = np.prod([2 * l / n for n, l in zip(N, L)])
+    got = vol * np.sum(phi * rho)
+
+    def integrand(th):
+        c, s = math.cos(th), math.sin(th)
+        s2 = c * c * a * a + s * s * b * b
+        radial = math.sqrt(math.pi / 2.0) / s2 ** 1.5  # int_0^inf k^2 exp(-k^2 s2/2) dk
+        return 1.5 * (c * c) * radial
+    val, _ = integrate.quad(integrand, 0.0, 2.0 * math.pi, epsabs=1e-15, epsrel=1e-14)
+    exact = val / (2.0 * math.pi) ** 2
     assert abs(got - exact) < 1e-12 * max(1.0, abs(exact))
 
 

@@ -41,8 +41,9 @@ class Params:
     d: dimension (2 or 3); N: points per axis; L: half-widths of the box
     [-L_j, L_j]; s: fractional order; Omega: rotation speed; gamma: trap
     frequencies of V = sum_v gamma_v^2 v^2 / 2; beta, lam: local and nonlocal
-    interaction strengths; kernel: "none", "coulomb" or "ddi3" (dipole along
-    z); mu: Coulomb exponent; coef: prefactor c of U = c/|x|^mu (the paper's
+    interaction strengths; kernel: "none", "coulomb", "ddi3" or "ddi2";
+    axis: unit dipole axis n (a 2D dipole keeps its third component as the
+    out-of-plane part n3); mu: Coulomb exponent; coef: prefactor c of U = c/|x|^mu (the paper's
     Coulomb-type kernel uses c = 1/(2^{d-1} pi)); m: mass term of the
     fractional operator; dt: time step; steps: number of steps of the run.
     """
@@ -56,6 +57,7 @@ class Params:
     beta: float
     lam: float
     kernel: str = "coulomb"
+    axis: tuple = (0.0, 0.0, 1.0)
     mu: float = 1.0
     coef: float | None = None
     m: float = 0.0
