@@ -6,7 +6,11 @@ Oracle (test infrastructure only).  Definitions from the paper:
   + (lam/2) Phi |psi|^2 - Omega psi^* Lz psi ] (eq. energy), split here
   into its five parts,
 * <Lz> = int psi^* Lz psi with Lz = -i (x d_y - y d_x) (eq. AME),
-* centre of mass x_c = int x |psi|^2 (eq. CoM),
+* centre of mass x_c = int x |psi|^2 (eq. CoM) and condensate widths
+  delta_v = int v^2 |psi|^2 (eq. ConWidth, no square root), both in the lab
+  frame: a state held in rotating Lagrangian coordinates x~ is read through
+  x = A(t) x~ (eq. Amatrix), A = [[cos wt, sin wt], [-sin wt, cos wt]] on (x, y),
+  w = Omega,
 * H psi, the right-hand side operator of eq. SFSE in the lab frame, with an
   optional frozen density (the operator A^{BE,n} of Section 3.2 without its
   I/dt part uses rho = |phi^n|^2).
@@ -71,6 +75,25 @@ def center_of_mass(psi, N, L):
     rho = np.abs(psi) ** 2
     vol = _vol(N, L)
     return np.array([vol * float(np.sum(Xj * rho)) for Xj in X])
+
+
+def moments(psi, N, L, Omega=0.0, t=0.0):
+    """(mass, x_c, delta) in the lab frame (eqs. mass, CoM, ConWidth).
+
+    psi is given on the rotating-frame grid x~; with x = A(t) x~ the moments
+    are transformed by rotating every grid point and summing directly.
+    """
+    d = len(N)
+    X = np.meshgrid(*axes(N, L), indexing="ij")
+    th = Omega * t
+    lab = list(X)
+    lab[0] = np.cos(th) * X[0] + np.sin(th) * X[1]
+    lab[1] = -np.sin(th) * X[0] + np.cos(th) * X[1]
+    rho = np.abs(psi) ** 2
+    vol = _vol(N, L)
+    xc = np.array([vol * float(np.sum(lab[j] * rho)) for j in range(d)])
+    width = np.array([vol * float(np.sum(lab[j] ** 2 * rho)) for j in range(d)])
+    return vol * float(np.sum(rho)), xc, width
 
 
 def apply_H(prob, psi, rho_frozen=None):

@@ -108,3 +108,30 @@ def test_apply_H_frozen_density():
     diff = dg.apply_H(pr, psi, rho_frozen=rho2) - dg.apply_H(pr, psi)
     expect = (pr.beta * (rho2 - rho) + pr.lam * pr.potential(rho2 - rho)) * psi
     assert np.max(np.abs(diff - expect)) < 1e-11
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_lab_frame_moments_of_rotated_anisotropic_gaussian(d):
+    # |psi|^2 is a Gaussian with mean c and covariance S = diag(a_j^2 / 2) in the
+    # rotating coordinates x~; in the lab frame x = A(t) x~ its mean is A c and
+    # its covariance A S A^T, so x_c = A c and delta_v = (A S A^T)_vv + (A c)_v^2.
+    N = (64, 72, 48)[:d]
+    L = (9.0, 10.0, 8.0)[:d]
+    a = np.array([1.0, 0.7, 1.3][:d])
+    c = np.array([0.8, -0.5, 0.3][:d])
+    X = np.meshgrid(*scheme.axes(N, L), indexing="ij")
+    psi = np.exp(-sum((X[j] - c[j]) ** 2 / (2 * a[j] ** 2) for j in range(d))) / math.sqrt(math.pi ** (d / 2) * np.prod(a))
+    Om, t = 0.6, 1.3
+    th = Om * t
+    A = np.eye(d)
+    A[:2, :2] = [[math.cos(th), math.sin(th)], [-math.sin(th), math.cos(th)]]
+    S = np.diag(a ** 2 / 2)
+    mean = A @ c
+    cov = A @ S @ A.T
+    m, xc, width = dg.moments(psi, N, L, Omega=Om, t=t)
+    assert abs(m - 1.0) < 1e-13
+    assert np.max(np.abs(xc - mean)) < 1e-13
+    assert np.max(np.abs(width - (np.diag(cov) + mean ** 2))) < 1e-12
+    # without rotation the moments are those of the grid coordinates
+    m0, xc0, w0 = dg.moments(psi, N, L)
+    assert np.max(np.abs(xc0 - c)) < 1e-13 and np.max(np.abs(w0 - (a ** 2 / 2 + c ** 2))) < 1e-12

@@ -187,3 +187,25 @@ def test_energy_conserved_to_second_order():
         drift.append(abs(dg.energy_parts(pr, psi, t)[-1] - e0))
     assert drift[1] < drift[0] / 3.0
     assert drift[1] < 1e-4
+
+
+def test_widths_follow_2d_virial_law_at_s1():
+    # s = 1, isotropic trap gamma, cubic nonlinearity, d = 2: the virial
+    # identity gives d^2<r^2>/dt^2 = 4 E0 - 4 gamma^2 <r^2>, E0 the energy
+    # without the rotation term (conserved, like <Lz>, for a radial trap), so
+    # for a real initial state <r^2>(t) = E0/gamma^2 + (<r^2>(0) - E0/gamma^2) cos(2 gamma t).
+    # <r^2> = delta_x + delta_y (eq. ConWidth) read in the lab frame.
+    N, L = (64, 64), (8.0, 8.0)
+    gam, Om = 1.2, 0.5
+    pr = scheme.Problem(2, N, L, 1.0, Om, (gam, gam), 5.0, 0.0, kernel="none")
+    X = np.meshgrid(*scheme.axes(N, L), indexing="ij")
+    psi = W.normalize(np.exp(-(X[0] - 0.4) ** 2 / 1.6 - X[1] ** 2 / 0.9) + 0j, pr.h)
+    ek, ep, ei, _, _, _ = dg.energy_parts(pr, psi)
+    E0 = ek + ep + ei
+    r0 = float(np.sum(dg.moments(psi, N, L)[2]))
+    T, n = 1.0, 1000
+    psi, t = pr.run(psi, n, T / n)
+    r2 = float(np.sum(dg.moments(psi, N, L, Omega=Om, t=t)[2]))
+    exact = E0 / gam ** 2 + (r0 - E0 / gam ** 2) * math.cos(2 * gam * t)
+    # second-order splitting error: 6e-7, 1.5e-7, 3.4e-8 at 500, 1000, 2000 steps
+    assert abs(r2 - exact) < 5e-7
