@@ -63,14 +63,22 @@ typedef enum { FSE_C128 = 0, FSE_C64 = 1 } fse_precision;
  *   FSE_K_COULOMB -- U = prefactor / |x|^mu, 0 < mu <= d-1; the paper's
  *                    Coulomb-type kernel has prefactor 1/(2^{d-1} pi);
  *   FSE_K_DDI3    -- d = 3 dipole-dipole kernel -delta - 3 d_nn (1/(4 pi |x|))
- *                    with dipole axis n; only n = (0,0,1) is implemented. */
-typedef enum { FSE_K_NONE = 0, FSE_K_COULOMB = 1, FSE_K_DDI3 = 2 } fse_kernel_kind;
+ *                    with unit dipole axis n;
+ *   FSE_K_DDI2    -- d = 2 dipole-dipole kernel
+ *                    -(3/2)(d_{n_perp n_perp} - n3^2 Lap_perp)(1/(2 pi |x|)),
+ *                    n = (n_perp, n3) a unit vector.
+ * The multiplier is stored for non-negative frequencies, so it must be even
+ * in each: a 3D axis is a coordinate axis, a 2D axis has n_perp along x or y
+ * (any n3); otherwise FSE_ERR_UNSUPPORTED.  With Omega != 0 the axis must be
+ * (0, 0, +-1): any other axis turns in the rotating Lagrangian frame
+ * (eq. Kernel_Rot), which is not implemented. */
+typedef enum { FSE_K_NONE = 0, FSE_K_COULOMB = 1, FSE_K_DDI3 = 2, FSE_K_DDI2 = 3 } fse_kernel_kind;
 
 typedef struct {
     int kind;          /* fse_kernel_kind */
-    double mu;         /* Coulomb exponent (ignored for DDI3) */
-    double prefactor;  /* c in U = c/|x|^mu (ignored for DDI3, which uses 1/(4 pi)) */
-    double n[3];       /* dipole axis for DDI3 */
+    double mu;         /* Coulomb exponent (ignored for the dipoles) */
+    double prefactor;  /* c in U = c/|x|^mu (ignored for the dipoles, which use 1/(4 pi), 1/(2 pi)) */
+    double n[3];       /* unit dipole axis (DDI3, DDI2) */
     double delta;      /* near-field radius of the GauSum split; <= 0 selects 1e-4 * max L */
     double ht;         /* sinc-quadrature step of the Gaussian sum; <= 0 selects 0.14 */
 } fse_kernel;
@@ -129,6 +137,17 @@ fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* str
 
 /* <Lz> = h^d sum psi^* (-i)(x D_y - y D_x) psi (eq. AME) -> out_dev[0]. */
 fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev, void* stream);
+
+/* Mass, centre of mass and condensate widths in the lab frame at the plan's
+ * time (eqs. mass, CoM, ConWidth; the width is int v^2 |psi|^2, no square
+ * root).  psi is in rotating coordinates x~ and is read through x = A(t) x~,
+ * A = [[cos Omega t, sin Omega t], [-sin Omega t, cos Omega t]] on (x, y):
+ * out_dev[0..6] = N, x_c, y_c, z_c, delta_x, delta_y, delta_z (z entries 0 in
+ * 2D), each h^d times an FP64 sum over the grid.  One pass over psi; no
+ * allocation; asynchronous on `stream`.  Shares the plan's reduction scratch
+ * with the other diagnostics, so calls on one plan must be ordered on one
+ * stream. */
+fse_status fse_moments(fse_plan plan, const void* psi, double* out_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Ground state: one step of the gradient flow with discrete normalisation,

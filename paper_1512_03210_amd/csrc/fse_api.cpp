@@ -135,12 +135,25 @@ fse_status check_args(int d, const int* N, const double* L, double s, double Ome
             if (!(kernel->mu > 0.0) || kernel->mu > d - 1 + 1e-15)
                 return fail(FSE_ERR_ARG, "Coulomb exponent mu must lie in (0, d-1]");
             if (!std::isfinite(kernel->prefactor)) return fail(FSE_ERR_ARG, "kernel prefactor must be finite");
-        } else if (kernel->kind == FSE_K_DDI3) {
-            if (d != 3) return fail(FSE_ERR_ARG, "the 3D dipolar kernel needs d = 3");
-            const double nn = kernel->n[0] * kernel->n[0] + kernel->n[1] * kernel->n[1] + kernel->n[2] * kernel->n[2];
+        } else if (kernel->kind == FSE_K_DDI3 || kernel->kind == FSE_K_DDI2) {
+            const bool three = kernel->kind == FSE_K_DDI3;
+            if (d != (three ? 3 : 2))
+                return fail(FSE_ERR_ARG, "the %dD dipolar kernel needs d = %d", three ? 3 : 2, three ? 3 : 2);
+            const double* n = kernel->n;
+            if (!std::isfinite(n[0]) || !std::isfinite(n[1]) || !std::isfinite(n[2]))
+                return fail(FSE_ERR_ARG, "dipole axis must be finite");
+            const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
             if (std::fabs(nn - 1.0) > 1e-12) return fail(FSE_ERR_ARG, "dipole axis must be a unit vector");
-            if (kernel->n[0] != 0.0 || kernel->n[1] != 0.0)
-                return fail(FSE_ERR_UNSUPPORTED, "only the dipole axis (0,0,1) is implemented");
+            // The multiplier is stored for non-negative frequencies only, so it
+            // must be even in each of them: no cross term n_i n_j kappa_i kappa_j.
+            const int nz = (n[0] != 0.0) + (n[1] != 0.0) + (three && n[2] != 0.0);
+            if (nz > 1)
+                return fail(FSE_ERR_UNSUPPORTED, three ? "the 3D dipole axis must be a coordinate axis"
+                                                       : "the in-plane part of the 2D dipole axis must lie along x or y");
+            // With rotation the axis seen in the rotating Lagrangian frame turns
+            // unless it is the rotation axis z.
+            if (Omega != 0.0 && (n[0] != 0.0 || n[1] != 0.0))
+                return fail(FSE_ERR_UNSUPPORTED, "with Omega != 0 the dipole axis must be (0, 0, +-1)");
         } else if (kernel->kind != FSE_K_NONE) {
             return fail(FSE_ERR_ARG, "unknown kernel kind %d", kernel->kind);
         }
@@ -482,6 +495,16 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     return FSE_OK;
 }
 
+// Lab-frame mass, centre of mass and widths: one moment pass, then the
+// rotation x = A(t) x~ applied to the FP64 totals.
+template <typename R> fse_status moments_impl(fse_plan p, const void* psi, double* out, hipStream_t st) {
+    const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
+    const double th = p->Omega * p->t;
+    HIPCHK(fse::Launch<R>::red_moments(psi, p->n, geom(p), p->partials, kRedBlocks, st));
+    HIPCHK(fse::launch_moments_final(p->partials, kRedBlocks, vol, std::cos(th), std::sin(th), out, st));
+    return FSE_OK;
+}
+
 template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void* H, const void* rho, hipStream_t st) {
     using L = fse::Launch<R>;
     fse_status s = ensure_diag(p);
@@ -799,7 +822,7 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
             p->khat = donor->khat;
         } else {
             p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor,
-                                              p->kernel.delta, p->kernel.ht);
+                                              p->kernel.delta, p->kernel.ht, p->kernel.n);
         }
         double scale = 1.0;
         for (int j = 0; j < d; ++j) scale /= (2.0 * N[j]);
@@ -968,7 +991,7 @@ fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fs
     fse_status st = check_args(d, N, L, 1.0, 0.0, gam, 0.0, 1.0, kernel, FSE_C128);
     if (st != FSE_OK) return st;
     std::vector<double> k = fse::gausum_symbol(d, N, L, kernel->kind, kernel->mu, kernel->prefactor, kernel->delta,
-                                               kernel->ht);
+                                               kernel->ht, kernel->n);
     std::memcpy(out, k.data(), k.size() * sizeof(double));
     return FSE_OK;
 }
@@ -1063,6 +1086,14 @@ fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* str
                                   : reduce_impl<float>(plan, psi, 1, out_dev, st);
 }
 
+fse_status fse_moments(fse_plan plan, const void* psi, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? moments_impl<double>(plan, psi, out_dev, st)
+                                  : moments_impl<float>(plan, psi, out_dev, st);
+}
+
 fse_status fse_angular_momentum(fse_plan plan, const void* psi, double* out_dev, void* stream) {
     g_err.clear();
     if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
@@ -1110,7 +1141,8 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
             if (r.N[0] == q.N[0] && r.N[1] == q.N[1] && r.L[0] == q.L[0] && r.L[1] == q.L[1] &&
                 r.kernel.kind == q.kernel.kind && r.kernel.mu == q.kernel.mu &&
                 r.kernel.prefactor == q.kernel.prefactor && r.kernel.delta == q.kernel.delta &&
-                r.kernel.ht == q.kernel.ht && b->plans[j]->khat) {
+                r.kernel.ht == q.kernel.ht && r.kernel.n[0] == q.kernel.n[0] && r.kernel.n[1] == q.kernel.n[1] &&
+                r.kernel.n[2] == q.kernel.n[2] && b->plans[j]->khat) {
                 donor = b->plans[j];
                 break;
             }

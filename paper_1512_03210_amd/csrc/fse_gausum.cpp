@@ -12,8 +12,11 @@
 //   * C0, C2: the near-field correction of eq. taylor, integrating
 //     U - U_GS over the ball |y| < delta against the constant and the
 //     Laplacian terms of the Taylor polynomial;
-//   * the 3D dipole (axis z) multiplier -1 + 3 kappa_z^2 Khat_C, Khat_C for
-//     the kernel 1/(4 pi |x|) (eq. Kernel).
+//   * the 3D dipole multiplier -1 + 3 (n.kappa)^2 Khat_C, Khat_C for the
+//     kernel 1/(4 pi |x|), and the 2D dipole multiplier
+//     (3/2)[(n_perp.kappa)^2 - n3^2 |kappa|^2] Khat_C, Khat_C for
+//     1/(2 pi |x|) (both eq. Kernel); n has at most one nonzero component
+//     among those that multiply a frequency, so (n.kappa)^2 = sum n_j^2 kappa_j^2.
 // kappa_j = pi k / D_j for k = 0..N_j: the non-negative frequencies of the
 // 2N_j-point padded grid; Khat is even in every kappa_j.
 //
@@ -188,14 +191,23 @@ void near_field(int d, double mu, double c, double delta, const std::vector<doub
 }
 
 std::vector<double> gausum_symbol(int d, const int* N, const double* L, int kind, double mu, double c, double delta,
-                                  double ht) {
+                                  double ht, const double* n) {
     double Lmax = 0.0;
     for (int j = 0; j < d; ++j) Lmax = std::max(Lmax, L[j]);
     if (delta <= 0.0) delta = 1e-4 * Lmax;
     if (ht <= 0.0) ht = 0.14;
-    if (kind == 2) {  // dipole: Coulomb part 1/(4 pi |x|)
+    // dipoles: Coulomb part 1/(4 pi |x|) in 3D, 1/(2 pi |x|) in 2D
+    if (kind == 2 || kind == 3) {
         mu = 1.0;
-        c = 1.0 / (4.0 * kPi);
+        c = (kind == 2) ? 1.0 / (4.0 * kPi) : 1.0 / (2.0 * kPi);
+    }
+    // derivative factor sum_j a_j kappa_j^2 applied to Khat_C
+    double a[3] = {0.0, 0.0, 0.0};
+    if (kind == 2) {
+        for (int j = 0; j < 3; ++j) a[j] = 3.0 * n[j] * n[j];
+    } else if (kind == 3) {
+        a[0] = 1.5 * (n[0] * n[0] - n[2] * n[2]);
+        a[1] = 1.5 * (n[1] * n[1] - n[2] * n[2]);
     }
     std::vector<double> w, tau;
     sinc_gaussian_sum(mu, c, d, Lmax, delta, ht, w, tau);
@@ -221,20 +233,21 @@ std::vector<double> gausum_symbol(int d, const int* N, const double* L, int kind
     const int K0 = K[0], K1 = K[1], K2 = (d == 3) ? K[2] : 1;
     std::vector<double> out((size_t)K0 * K1 * K2);
     parallel_for(K0, [&](int k0) {
-        std::vector<double> a(Q), row(K2);
+        std::vector<double> wg(Q), row(K2);
         const double kap0 = kPi * k0 / D[0];
         for (int k1 = 0; k1 < K1; ++k1) {
-            for (int q = 0; q < Q; ++q) a[q] = w[q] * G[0][(size_t)q * K0 + k0] * G[1][(size_t)q * K1 + k1];
+            for (int q = 0; q < Q; ++q) wg[q] = w[q] * G[0][(size_t)q * K0 + k0] * G[1][(size_t)q * K1 + k1];
             const double kap1 = kPi * k1 / D[1];
             if (d == 2) {
                 double s = 0.0;
-                for (int q = 0; q < Q; ++q) s += a[q];
-                out[(size_t)k0 * K1 + k1] = s + C0 - C2 * (kap0 * kap0 + kap1 * kap1);
+                for (int q = 0; q < Q; ++q) s += wg[q];
+                const double kc = s + C0 - C2 * (kap0 * kap0 + kap1 * kap1);
+                out[(size_t)k0 * K1 + k1] = (kind == 3) ? (a[0] * kap0 * kap0 + a[1] * kap1 * kap1) * kc : kc;
                 continue;
             }
             std::fill(row.begin(), row.end(), 0.0);
             for (int q = 0; q < Q; ++q) {
-                const double aq = a[q];
+                const double aq = wg[q];
                 const double* g2 = &G[2][(size_t)q * K2];
                 for (int k2 = 0; k2 < K2; ++k2) row[k2] += aq * g2[k2];
             }
@@ -242,7 +255,7 @@ std::vector<double> gausum_symbol(int d, const int* N, const double* L, int kind
             for (int k2 = 0; k2 < K2; ++k2) {
                 const double kap2 = kPi * k2 / D[2];
                 const double kc = row[k2] + C0 - C2 * (kap0 * kap0 + kap1 * kap1 + kap2 * kap2);
-                o[k2] = (kind == 2) ? -1.0 + 3.0 * kap2 * kap2 * kc : kc;
+                o[k2] = (kind == 2) ? -1.0 + (a[0] * kap0 * kap0 + a[1] * kap1 * kap1 + a[2] * kap2 * kap2) * kc : kc;
             }
         }
     });

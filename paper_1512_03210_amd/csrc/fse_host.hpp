@@ -16,8 +16,11 @@ void near_field(int d, double mu, double c, double delta, const std::vector<doub
                 double& C0, double& C2);
 
 // Multiplier on the non-negative octant, (N_j + 1) values per axis, row-major.
-// kind: 1 Coulomb c/|x|^mu, 2 dipole along z.  delta, ht <= 0 select defaults.
+// kind: 1 Coulomb c/|x|^mu, 2 3D dipole, 3 2D dipole, along the unit axis n
+// (kinds 2 and 3; the multiplier must be even in every frequency, so n has no
+// two nonzero components among those that enter it).  delta, ht <= 0 select
+// defaults.
 std::vector<double> gausum_symbol(int d, const int* N, const double* L, int kind, double mu, double c, double delta,
-                                  double ht);
+                                  double ht, const double* n);
 
 }  // namespace fse

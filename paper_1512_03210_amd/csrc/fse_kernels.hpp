@@ -904,6 +904,64 @@ __global__ __launch_bounds__(RED_THREADS) void k_red_lz(const typename CT<R>::T*
     block_reduce_store<1>(acc, partials, slot0, gridDim.x);
 }
 
+// Moments of rho = |psi|^2 on the rotating-frame grid: slots 0 sum rho,
+// 1..3 sum x~_j rho, 4..6 sum x~_j^2 rho, 7 sum x~ y~ rho (z terms 0 in 2D).
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_red_moments(const typename CT<R>::T* __restrict__ psi, long n,
+                                                             GridGeom g, double* partials) {
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (long i = blockIdx.x * (long)RED_THREADS + threadIdx.x; i < n; i += (long)gridDim.x * RED_THREADS) {
+        int i0, i1, i2;
+        decode(i, g, i0, i1, i2);
+        const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy, z = (g.d == 3) ? g.z0 + i2 * g.hz : 0.0;
+        const auto v = psi[i];
+        const double rho = (double)v.x * v.x + (double)v.y * v.y;
+        const double xr = x * rho, yr = y * rho, zr = z * rho;
+        acc[0] += rho;
+        acc[1] += xr;
+        acc[2] += yr;
+        acc[3] += zr;
+        acc[4] += x * xr;
+        acc[5] += y * yr;
+        acc[6] += z * zr;
+        acc[7] += x * yr;
+    }
+    block_reduce_store<8>(acc, partials, 0, gridDim.x);
+}
+
+// Lab-frame mass, centre of mass and widths (eqs. mass, CoM, ConWidth) from
+// the eight moment slots, with x = A x~, A = [[c, s], [-s, c]] on (x, y):
+//   out = {N, x_c, y_c, z_c, delta_x, delta_y, delta_z}.  One block.
+static __global__ __launch_bounds__(RED_THREADS) void k_moments_final(const double* __restrict__ partials, int nblk,
+                                                               double vol, double c, double s, double* out) {
+    __shared__ double tot[8];
+    __shared__ double red[RED_THREADS / 64];
+    for (int k = 0; k < 8; ++k) {
+        double x = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += RED_THREADS) x += partials[(long)k * nblk + b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+            tot[k] = vol * t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double mx = tot[1], my = tot[2], sxx = tot[4], syy = tot[5], sxy = tot[7];
+        out[0] = tot[0];
+        out[1] = c * mx + s * my;
+        out[2] = -s * mx + c * my;
+        out[3] = tot[3];
+        out[4] = c * c * sxx + 2.0 * c * s * sxy + s * s * syy;
+        out[5] = s * s * sxx - 2.0 * c * s * sxy + c * c * syy;
+        out[6] = tot[6];
+    }
+}
+
 // Final combination (one block).  tot[s] = sum over blocks of slot s.
 //   KIND 0 (mass):   out[0] = vol * tot[0]
 //   KIND 1 (energy): out = {kin, pot, int, non, rot, total} from

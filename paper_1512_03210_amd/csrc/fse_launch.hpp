@@ -43,6 +43,8 @@ template <typename R> struct Launch {
                               double s, double m2, double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_lz(const void* psi, const void* D, long n, const GridGeom& g, int coord_axis,
                              double* partials, int slot0, int nblk, hipStream_t st);
+    static hipError_t red_moments(const void* psi, long n, const GridGeom& g, double* partials, int nblk,
+                                  hipStream_t st);
     static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi, long n,
                               const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
                               double g1, double g2, hipStream_t st);
@@ -76,5 +78,10 @@ hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);
+
+// out[0..6] = lab-frame {N, x_c, y_c, z_c, delta_x, delta_y, delta_z} from
+// the eight moment slots; (c, s) = (cos, sin) of the frame angle.
+hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
+                                hipStream_t st);
 
 }  // namespace fse

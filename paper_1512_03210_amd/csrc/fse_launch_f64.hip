@@ -40,4 +40,10 @@ hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kin
     return hipGetLastError();
 }
 
+hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
+                                hipStream_t st) {
+    k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, out);
+    return hipGetLastError();
+}
+
 }  // namespace fse

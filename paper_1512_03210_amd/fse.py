@@ -21,13 +21,13 @@ FSE_OK = 0
 STATUS = {0: "FSE_OK", -1: "FSE_ERR_ARG", -2: "FSE_ERR_UNSUPPORTED", -3: "FSE_ERR_NOMEM",
           -4: "FSE_ERR_HIP", -5: "FSE_ERR_NUMERIC", -6: "FSE_ERR_STATE"}
 C128, C64 = 0, 1
-K_NONE, K_COULOMB, K_DDI3 = 0, 1, 2
-KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3}
+K_NONE, K_COULOMB, K_DDI3, K_DDI2 = 0, 1, 2, 3
+KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_DDI2}
 
 EXPORTS = [
     "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
     "fse_set_time", "fse_get_time", "fse_step", "fse_apply_H", "fse_nonlocal_potential",
-    "fse_mass", "fse_energy", "fse_angular_momentum", "fse_gausum_symbol_host",
+    "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
     "fse_batch_reduce", "fse_batch_times", "fse_gs_step",
@@ -84,6 +84,7 @@ def lib():
         "fse_mass": (st, [vp, vp, vp, vp]),
         "fse_energy": (st, [vp, vp, vp, vp]),
         "fse_angular_momentum": (st, [vp, vp, vp, vp]),
+        "fse_moments": (st, [vp, vp, vp, vp]),
         "fse_gausum_symbol_host": (st, [i, ip, dp, kp, dp]),
         "fse_get_symbol": (st, [vp, dp]),
         "fse_last_error": (ctypes.c_char_p, []),
@@ -189,7 +190,7 @@ class Plan:
 
     @classmethod
     def from_params(cls, p, precision=C128, stream=None, **kw):
-        kern = None if p.kernel == "none" else make_kernel(p.kernel, mu=p.mu, prefactor=p.c, **kw)
+        kern = None if p.kernel == "none" else make_kernel(p.kernel, mu=p.mu, prefactor=p.c, axis=p.axis, **kw)
         return cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kern, precision, p.m, stream)
 
     def close(self):
@@ -264,6 +265,11 @@ class Plan:
     def angular_momentum(self, psi, stream=None):
         return self._scalar(lib().fse_angular_momentum, psi, 1, stream)
 
+    def moments(self, psi, stream=None):
+        """Device tensor [N, x_c, y_c, z_c, delta_x, delta_y, delta_z], lab frame at the plan's time
+        (fse_moments)."""
+        return self._scalar(lib().fse_moments, psi, 7, stream)
+
     def gs_step(self, psi, dt: float, tol: float = 1e-12, maxit: int = 1000, stream=None) -> dict:
         """One backward-Euler gradient-flow step toward the ground state, in place on psi
         (fse_gs_step); returns the solver statistics."""
@@ -310,7 +316,8 @@ class Batch:
             q.L = (ctypes.c_double * 2)(*p.L)
             q.s, q.Omega, q.beta, q.lam, q.dt, q.m = p.s, p.Omega, p.beta, p.lam, p.dt, p.m
             q.gamma = (ctypes.c_double * 2)(*p.gamma)
-            q.kernel = make_kernel(p.kernel, mu=p.mu, prefactor=p.c) if p.kernel != "none" else make_kernel("none")
+            q.kernel = (make_kernel(p.kernel, mu=p.mu, prefactor=p.c, axis=p.axis) if p.kernel != "none"
+                        else make_kernel("none"))
         self._h = ctypes.c_void_p()
         _check(lib().fse_batch_create(ctypes.byref(self._h), self.count, arr, precision, _stream(stream)))
         off = (ctypes.c_size_t * (self.count + 1))()

@@ -50,7 +50,7 @@ _K_CACHE = {}
 
 def _oracle_problem(p):
     pr = scheme.Problem.from_params(p)
-    key = (p.N, p.L, p.kernel, p.mu, p.c)
+    key = (p.N, p.L, p.kernel, p.mu, p.c, p.axis)
     if pr.kernel != "none" and pr.lam != 0.0:
         if key not in _K_CACHE:
             _K_CACHE[key] = pr.K
@@ -77,6 +77,14 @@ def P(name, **kw):
                        kernel="coulomb", dt=1e-3, name="big2d"),
         big2d_t=W.Params(d=2, N=(512, 384), L=(8.0, 8.0), s=0.9, Omega=0.8, gamma=(1.0, 1.0), beta=500.0,
                          lam=1.0, kernel="coulomb", dt=1e-3, name="big2d_t"),
+        # 2D dipoles (eq. Kernel): along the rotation axis with rotation, tilted in the x-z plane without
+        ddi2z=W.Params(d=2, N=(48, 64), L=(6.0, 8.0), s=0.8, Omega=0.6, gamma=(1.0, 1.2), beta=30.0, lam=8.0,
+                       kernel="ddi2", dt=1e-3, name="ddi2z"),
+        ddi2xz=W.Params(d=2, N=(64, 48), L=(8.0, 6.0), s=1.1, Omega=0.0, gamma=(1.0, 0.9), beta=30.0, lam=-8.0,
+                        kernel="ddi2", axis=(0.6, 0.0, 0.8), dt=1e-3, name="ddi2xz"),
+        # 3D dipole along y, no rotation
+        ddi3y=W.Params(d=3, N=(24, 32, 16), L=(5.0, 6.0, 4.0), s=0.9, Omega=0.0, gamma=(1.0, 1.2, 1.5),
+                       beta=100.0, lam=30.0, kernel="ddi3", axis=(0.0, 1.0, 0.0), dt=5e-4, name="ddi3y"),
         # radix-3 lengths in every pass
         rad3_3d=W.Params(d=3, N=(48, 96, 24), L=(6.0, 8.0, 4.0), s=0.6, Omega=0.4, gamma=(1.0, 0.9, 1.3),
                          beta=100.0, lam=2.0, kernel="coulomb", dt=1e-3, name="rad3_3d"),
@@ -90,7 +98,8 @@ def _psi0(p, seed=0):
     return W.anisotropic_gaussian(p.N, p.L, p.gamma, seed=seed)
 
 
-CASES = ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d"]
+CASES = ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d", "ddi2z",
+         "ddi2xz", "ddi3y"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -123,7 +132,7 @@ def test_one_step_c64(name):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "ddi2z", "ddi2xz"])
 def test_many_steps_fsal_against_plain_oracle(name):
     # merged half steps inside one call vs the oracle's plain scheme; the
     # anisotropic rotating cases exercise the time-dependent trap integral.
@@ -153,7 +162,8 @@ def test_split_calls_continue_the_trajectory():
     assert _rel(_host(a), ref) < 1e-11
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "big2d", "big2d_t", "rad3_3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "big2d", "big2d_t", "rad3_3d", "ddi2z",
+                                  "ddi2xz", "ddi3y"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_nonlocal_potential(name, prec):
     p = P(name)
@@ -175,7 +185,7 @@ def test_symbol_of_plan_matches_oracle():
     assert np.max(np.abs(K - Ko)) < 1e-11 * np.max(np.abs(Ko))
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local3d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local3d", "ddi2z", "ddi2xz", "ddi3y"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_diagnostics(name, prec):
     p = P(name)
@@ -196,7 +206,7 @@ def test_diagnostics(name, prec):
     assert abs(lz - dg.angular_momentum(xin, p.N, p.L)) < tol
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "ddi2z", "ddi2xz"])
 @pytest.mark.parametrize("frozen", [False, True])
 def test_apply_H(name, frozen):
     p = P(name)
@@ -220,6 +230,51 @@ def test_apply_H_c64():
     ref = dg.apply_H(_oracle_problem(p), psi0)
     plan = fse.Plan.from_params(p, fse.C64)
     assert _rel(_host(plan.apply_H(_dev(psi0, fse.C64))), ref) < 1e-5
+
+
+@pytest.mark.parametrize("name", ["aniso2d", "coul3d", "ddi2xz", "local3d"])
+@pytest.mark.parametrize("prec", [fse.C128, fse.C64])
+def test_moments(name, prec):
+    # lab-frame mass, centre of mass and widths (eqs. CoM, ConWidth) of an
+    # off-centre state at a time where the frame has turned
+    p = P(name)
+    psi0 = _psi0(p, seed=6)
+    X = np.meshgrid(*scheme.axes(p.N, p.L), indexing="ij")
+    psi0 = psi0 * np.exp(-0.1 * (X[0] - 0.7) ** 2 + 0.05 * X[1])
+    plan = fse.Plan.from_params(p, prec)
+    plan.time = 1.37
+    x = _dev(psi0, prec)
+    got = plan.moments(x).cpu().numpy()
+    m, xc, wd = dg.moments(_host(x), p.N, p.L, Omega=p.Omega, t=1.37)
+    ref = np.zeros(7)
+    ref[0] = m
+    ref[1:1 + p.d] = xc
+    ref[4:4 + p.d] = wd
+    tol = 1e-12 if prec == fse.C128 else 1e-6
+    _note(f"[parity] moments {name} prec={prec}: max diff {np.max(np.abs(got - ref)):.3e}")
+    assert np.all(np.abs(got - ref) <= tol * np.maximum(1.0, np.abs(ref)))
+
+
+def test_widths_follow_virial_law_on_the_gpu():
+    # s = 1, isotropic trap, cubic term, d = 2: delta_x + delta_y =
+    # E0/g^2 + (<r^2>(0) - E0/g^2) cos(2 g t) for a real initial state; the
+    # run is in rotating coordinates and the moments are read in the lab frame.
+    g, Om = 1.2, 0.5
+    p = W.Params(d=2, N=(64, 64), L=(8.0, 8.0), s=1.0, Omega=Om, gamma=(g, g), beta=5.0, lam=0.0, kernel="none",
+                 dt=1e-3, name="virial")
+    X = np.meshgrid(*scheme.axes(p.N, p.L), indexing="ij")
+    psi0 = W.normalize(np.exp(-(X[0] - 0.4) ** 2 / 1.6 - X[1] ** 2 / 0.9) + 0j, p.h)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0)
+    e = plan.energy(x).cpu().numpy()
+    E0 = e[0] + e[1] + e[2]
+    r0 = float(np.sum(plan.moments(x).cpu().numpy()[4:6]))
+    plan.step(x, 1000, p.dt)
+    t = plan.time
+    r2 = float(np.sum(plan.moments(x).cpu().numpy()[4:6]))
+    exact = E0 / g ** 2 + (r0 - E0 / g ** 2) * math.cos(2 * g * t)
+    _note(f"[parity] virial law: <r^2> = {r2:.12f}, law {exact:.12f}")
+    assert abs(r2 - exact) < 5e-7
 
 
 def test_reversibility_and_mass():

@@ -61,6 +61,30 @@ def test_plan_check_3d_and_unsupported_axis():
     assert fse.plan_check(3, (512, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k) == -1
 
 
+def test_plan_check_dipole_axes():
+    # coordinate axes pass without rotation; an axis whose multiplier has a
+    # cross term (odd in a frequency) is unsupported; with rotation only z
+    ok3 = [((1.0, 0.0, 0.0), 0.0), ((0.0, 1.0, 0.0), 0.0), ((0.0, 0.0, -1.0), 0.7)]
+    for axis, Om in ok3:
+        k = fse.make_kernel("ddi3", axis=axis)
+        assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, Om, (1, 1, 2), 200, 50, k) == 0, axis
+    k = fse.make_kernel("ddi3", axis=(0.6, 0.8, 0.0))
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.0, (1, 1, 2), 200, 50, k) == -2
+    ok2 = [((0.0, 0.0, 1.0), 0.5), ((0.6, 0.0, 0.8), 0.0), ((0.0, 1.0, 0.0), 0.0), ((1.0, 0.0, 0.0), 0.0)]
+    for axis, Om in ok2:
+        k = fse.make_kernel("ddi2", axis=axis)
+        assert fse.plan_check(2, (64, 48), (8.0, 6.0), 0.8, Om, (1, 1), 20, 5, k) == 0, axis
+    bad2 = [((0.36, 0.48, 0.8), 0.0, -2), ((0.6, 0.0, 0.8), 0.5, -2), ((0.6, 0.0, 0.0), 0.0, -1),
+            ((float("nan"), 0.0, 1.0), 0.0, -1)]
+    for axis, Om, want in bad2:
+        k = fse.make_kernel("ddi2", axis=axis)
+        assert fse.plan_check(2, (64, 48), (8.0, 6.0), 0.8, Om, (1, 1), 20, 5, k) == want, axis
+    k = fse.make_kernel("ddi2")
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.0, (1, 1, 2), 200, 50, k) == -1
+    k = fse.make_kernel("ddi3")
+    assert fse.plan_check(2, (64, 48), (8.0, 6.0), 0.8, 0.0, (1, 1), 20, 5, k) == -1
+
+
 @pytest.mark.parametrize("d,N,L,kind,c", [
     (2, (64, 64), (8.0, 8.0), "coulomb", 1 / (2 * math.pi)),
     (2, (48, 96), (6.0, 9.0), "coulomb", 1.0),
@@ -85,6 +109,34 @@ def test_host_ddi3_symbol_matches_oracle():
     scale = 1.0 + 3.0 * kz[None, None, :] ** 2 * np.max(np.abs(KC))
     assert np.max(np.abs(K - Ko) / scale) < 1e-14
     assert abs(K[0, 0, 0] + 1.0) < 1e-15  # kappa = 0: -1
+
+
+@pytest.mark.parametrize("ax", [0, 1])
+def test_host_ddi3_symbol_other_axes(ax):
+    N, L = (24, 32, 16), (5.0, 6.0, 4.0)
+    axis = tuple(1.0 if j == ax else 0.0 for j in range(3))
+    K = fse.gausum_symbol_host(3, N, L, fse.make_kernel("ddi3", axis=axis))
+    Ko = gausum.ddi3_symbol(N, L, axis=axis)[tuple(slice(0, n + 1) for n in N)]
+    KC = gausum.coulomb_symbol(N, L, mu=1.0, c=1 / (4 * math.pi))
+    k = math.pi * np.arange(N[ax] + 1) / (2 * L[ax])
+    shape = [1, 1, 1]
+    shape[ax] = -1
+    scale = 1.0 + 3.0 * k.reshape(shape) ** 2 * np.max(np.abs(KC))
+    assert np.max(np.abs(K - Ko) / scale) < 1e-14
+
+
+@pytest.mark.parametrize("axis", [(0.0, 0.0, 1.0), (1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.6, 0.0, 0.8),
+                                  (0.0, -0.8, 0.6)])
+def test_host_ddi2_symbol_matches_oracle(axis):
+    N, L = (48, 64), (6.0, 8.0)
+    K = fse.gausum_symbol_host(2, N, L, fse.make_kernel("ddi2", axis=axis))
+    Ko = gausum.ddi2_symbol(N, L, axis=axis)[tuple(slice(0, n + 1) for n in N)]
+    KC = gausum.coulomb_symbol(N, L, mu=1.0, c=1 / (2 * math.pi))
+    k0 = math.pi * np.arange(N[0] + 1) / (2 * L[0])
+    k1 = math.pi * np.arange(N[1] + 1) / (2 * L[1])
+    scale = 1.0 + 1.5 * (k0[:, None] ** 2 + k1[None, :] ** 2) * np.max(np.abs(KC))
+    assert np.max(np.abs(K - Ko) / scale) < 1e-14
+    assert K[0, 0] == 0.0  # kappa = 0: no mean-field term in 2D
 
 
 def test_gpu_entry_points_fail_cleanly_without_device():
