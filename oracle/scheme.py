@@ -14,6 +14,11 @@ Oracle (test infrastructure only).  Follows Section 4.2 of the paper:
   m(t) = A^{-1} n equals n then; any fixed axis without rotation), and P = int V(A(s) x~) ds (eq. int_poten).
 * TS2-GauSum (eqs. tssp1-tssp3): half linear step, full nonlinear step,
   half linear step.
+* Fourth order: the paper notes that TS2 extends to higher-order splitting
+  (end of Section 4.2) without giving a scheme.  Reading: the symmetric
+  triple-jump composition of Yoshida (1990), TS2 steps of lengths w1 dt,
+  w0 dt, w1 dt with w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 (negative); each
+  sub-step is exact for negative lengths too.
 
 Readings of the paper's text:
 * Grid: N points per axis, x_l = -L + l h, h = 2L/N (the periodic endpoint
@@ -168,3 +173,17 @@ class Problem:
         for _ in range(int(nsteps)):
             psi, t = self.step(psi, t, dt)
         return psi, t
+
+    def step4(self, psi, t, dt):
+        """One fourth-order step: TS2 steps of lengths w1 dt, w0 dt, w1 dt."""
+        w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        for w in (w1, 1.0 - 2.0 * w1, w1):
+            psi, _ = self.step(psi, t, w * dt)
+            t = t + w * dt
+        return psi, t
+
+    def run4(self, psi, nsteps, dt, t=0.0):
+        t0 = t
+        for k in range(int(nsteps)):
+            psi, _ = self.step4(psi, t0 + k * dt, dt)
+        return psi, t0 + nsteps * dt

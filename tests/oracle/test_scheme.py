@@ -209,3 +209,31 @@ def test_widths_follow_2d_virial_law_at_s1():
     exact = E0 / gam ** 2 + (r0 - E0 / gam ** 2) * math.cos(2 * gam * t)
     # second-order splitting error: 6e-7, 1.5e-7, 3.4e-8 at 500, 1000, 2000 steps
     assert abs(r2 - exact) < 5e-7
+
+
+def test_fourth_order_composition_converges_at_order_4():
+    # the triple-jump composition of TS2 steps: error ratio ~16 per halving
+    # (TS2 itself gives ~4), rotating anisotropic trap and Coulomb kernel
+    N, L = (64, 64), (8.0, 8.0)
+    pr = scheme.Problem(2, N, L, 0.8, 0.6, (1.0, 1.3), 30.0, 2.0, kernel="coulomb", c=1 / (2 * math.pi))
+    psi0 = W.harmonic_vortex_2d(N, L, seed=3)
+    T = 0.4
+    ref, tr = pr.run4(psi0, 256, T / 256)
+    assert abs(tr - T) < 1e-15
+    errs = []
+    for n in (8, 16, 32):
+        p, _ = pr.run4(psi0, n, T / n)
+        errs.append(np.linalg.norm(p - ref) / np.linalg.norm(ref))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(3.6 < o < 4.4 for o in orders), (errs, orders)
+
+
+def test_fourth_order_free_evolution_is_exact():
+    # no trap and no interaction: every sub-step is the exact kinetic flow and
+    # the lengths sum to dt, so n steps equal one kinetic step of length n dt
+    N, L = (32, 48), (6.0, 7.0)
+    pr = scheme.Problem(2, N, L, 0.7, 0.0, (0.0, 0.0), 0.0, 0.0, kernel="none")
+    psi0 = W.harmonic_vortex_2d(N, L, seed=4)
+    p, _ = pr.run4(psi0, 5, 0.03)
+    q = scheme.kinetic(psi0, N, L, 0.7, 0.15)
+    assert np.linalg.norm(p - q) / np.linalg.norm(q) < 1e-13
