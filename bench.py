@@ -266,6 +266,7 @@ def run_ops(p, prec, reps=10):
         "mass": lambda: plan.mass(x),
         "energy": lambda: plan.energy(x),
         "angular_momentum": lambda: plan.angular_momentum(x),
+        "moments": lambda: plan.moments(x),
         "apply_H": lambda: plan.apply_H(x, out),
         "apply_H_frozen_rho": lambda: plan.apply_H(x, out, rho_frozen=rho),
     }
@@ -286,6 +287,35 @@ def run_ops(p, prec, reps=10):
     del plan, x, out, rho
     torch.cuda.empty_cache()
     return res
+
+
+def run_order4(p, prec, steps=20, warmup=2):
+    """Fourth-order steps (triple-jump composition of the TS2 step) on the
+    headline grid: time per step and its ratio to the TS2 step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_1512_03210_amd import fse
+
+    psi0 = W.initial_state(p, seed=0)
+    dtype = np.complex128 if prec == fse.C128 else np.complex64
+    plan = fse.Plan.from_params(p, prec)
+    x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
+    del psi0
+    plan.step(x, warmup, p.dt, order=4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan.step(x, steps, p.dt, order=4)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    mass = plan.mass(x).item()
+    del plan, x
+    torch.cuda.empty_cache()
+    return {"steps": steps, "ms_per_step": round(ms, 4), "grid_point_steps_per_s": p.npts / (ms * 1e-3),
+            "mass_after": mass}
 
 
 def run_gs(p, prec, steps, tol, maxit=200):
@@ -421,6 +451,12 @@ def main():
     ops = {"c128": run_ops(p, fse.C128)}
     if not args.no_c64:
         ops["c64"] = run_ops(p, fse.C64)
+    print("[bench] fourth-order steps", file=sys.stderr, flush=True)
+    order4 = {"c128": run_order4(p, fse.C128)}
+    order4["c128"]["cost_vs_ts2"] = round(order4["c128"]["ms_per_step"] / r64["ms_per_step"], 3)
+    if not args.no_c64:
+        order4["c64"] = run_order4(p, fse.C64)
+        order4["c64"]["cost_vs_ts2"] = round(order4["c64"]["ms_per_step"] / r32["ms_per_step"], 3)
     cases = {}
     if args.cases:
         for name, steps in (("dipole3d_128", 1000), ("plain2d", 100)):
@@ -490,6 +526,7 @@ def main():
         "cpu_baseline": cpu,
         "variants": variants,
         "reductions_and_H": ops,
+        "fourth_order": order4,
         "cases": cases,
         "ground_state": gs,
         "passes": r64["passes"],

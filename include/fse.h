@@ -114,6 +114,15 @@ fse_status fse_get_time(fse_plan plan, double* t);
  * dt may be negative (backward in time); nsteps >= 0.  t += nsteps*dt. */
 fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
+/* nsteps fourth-order steps of size dt, in place on psi: each step is the
+ * symmetric triple-jump composition of TS2-GauSum steps of lengths w1 dt,
+ * w0 dt, w1 dt, w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 < 0 (the paper notes
+ * that TS2 extends to higher-order splitting, end of Section 4.2; the
+ * composition is Yoshida's).  Same state convention, arguments, stream
+ * semantics and time update as fse_step; a step costs three nonlinear and
+ * three kinetic sub-steps (half linear steps that meet are merged). */
+fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
+
 /* H psi in the lab frame (the operator of eq. SFSE; with a frozen density it
  * is the operator A^{BE,n} of Section 3.2 without its I/dt part):
  *   H psi = (1/2)(-Lap+m^2)^s psi + (V + beta rho + lambda Phi[rho]) psi - Omega Lz psi,

@@ -81,8 +81,8 @@ struct fse_plan_s {
     std::vector<double> khat_host;
     void* X1 = nullptr;
     void* X2 = nullptr;
-    void* kin[2] = {nullptr, nullptr};
-    double kin_tau[2] = {NAN, NAN};
+    void* kin[3] = {nullptr, nullptr, nullptr};
+    double kin_tau[3] = {NAN, NAN, NAN};
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
     double* gs_out = nullptr;
@@ -262,8 +262,10 @@ fse::GridGeom geom(const fse_plan p) {
 
 double dmu(const fse_plan p, int j) { return (j < p->d) ? 2.0 * kPi / (2.0 * p->L[j]) : 0.0; }
 
-// Kinetic table for step length tau; slot 0 holds the half step, slot 1 the
-// full step, each rebuilt only when its tau changes.
+// Kinetic table for step length tau; slot 0 holds the half step at the ends
+// of a call, slot 1 the merged halves between steps, slot 2 the merged halves
+// between the sub-steps of a composed step; each is rebuilt only when its tau
+// changes.
 template <typename R> fse_status kin_table(fse_plan p, double tau, int slot, void** out, hipStream_t st) {
     if (p->kin[slot] && p->kin_tau[slot] == tau) {
         *out = p->kin[slot];
@@ -383,13 +385,31 @@ fse_status ensure_diag(fse_plan p) {
     return dev_alloc(p, &p->diag, (size_t)p->n * (2 * p->csize + p->rsize));
 }
 
-template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, hipStream_t st) {
+// One call advances nsteps steps.  A step is a composition of TS2 sub-steps
+// of lengths w_j dt: the Strang step itself (order 2), or the symmetric
+// triple jump w = (w1, 1 - 2 w1, w1), w1 = 1/(2 - 2^{1/3}) (order 4).  The
+// half linear steps that meet between sub-steps are merged into one kinetic
+// pass of length (w_j + w_{j+1}) dt / 2.
+template <typename R>
+fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hipStream_t st) {
     using L = fse::Launch<R>;
-    void *kh = nullptr, *kf = nullptr;
-    fse_status s = kin_table<R>(p, 0.5 * dt, 0, &kh, st);
+    double w[3] = {1.0, 0.0, 0.0};
+    int nw = 1;
+    if (order == 4) {
+        const double w1 = 1.0 / (2.0 - std::cbrt(2.0));
+        w[0] = w[2] = w1;
+        w[1] = 1.0 - 2.0 * w1;
+        nw = 3;
+    }
+    void *kh = nullptr, *kf = nullptr, *ki_tab = nullptr;
+    fse_status s = kin_table<R>(p, 0.5 * w[0] * dt, 0, &kh, st);
     if (s != FSE_OK) return s;
     if (nsteps > 1) {
-        s = kin_table<R>(p, dt, 1, &kf, st);
+        s = kin_table<R>(p, 0.5 * (w[nw - 1] + w[0]) * dt, 1, &kf, st);
+        if (s != FSE_OK) return s;
+    }
+    if (nw > 1) {  // symmetric weights: every inner junction has the same length
+        s = kin_table<R>(p, 0.5 * (w[0] + w[1]) * dt, 2, &ki_tab, st);
         if (s != FSE_OK) return s;
     }
     const int N0 = p->N[0];
@@ -405,34 +425,38 @@ template <typename R> fse_status step_impl(fse_plan p, void* psi, int nsteps, do
     if (p->d == 3)
         PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     for (int k = 0; k < nsteps; ++k) {
-        const double tn = p->t + k * dt;
-        const fse::PhaseArgs pa = phase_args(p, tn, dt);
-        if (p->nl) {
-            PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
-            if (p->d == 3) {
-                PLAUNCH(p, FSE_PASS_PAD_FWD, st,
-                        L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
-                PLAUNCH(p, FSE_PASS_CONV, st,
-                        L::line(N2, 0, p->X2, (N0 + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2],
-                                st));
-                PLAUNCH(p, FSE_PASS_CROP_INV, st,
-                        L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
+        double tj = p->t + k * dt;
+        for (int j = 0; j < nw; ++j) {
+            const double tau = w[j] * dt;
+            const fse::PhaseArgs pa = phase_args(p, tj, tau);
+            tj += tau;
+            if (p->nl) {
+                PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
+                if (p->d == 3) {
+                    PLAUNCH(p, FSE_PASS_PAD_FWD, st,
+                            L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
+                    PLAUNCH(p, FSE_PASS_CONV, st,
+                            L::line(N2, 0, p->X2, (N0 + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2],
+                                    st));
+                    PLAUNCH(p, FSE_PASS_CROP_INV, st,
+                            L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
+                } else {
+                    PLAUNCH(p, FSE_PASS_CONV, st,
+                            L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
+                }
+                PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
+                        L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
             } else {
-                PLAUNCH(p, FSE_PASS_CONV, st,
-                        L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
+                PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
+                        L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
             }
-            PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
-                    L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
-        } else {
-            PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
-                    L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+            void* tab = (j < nw - 1) ? ki_tab : (k == nsteps - 1) ? kh : kf;
+            if (p->d == 3)
+                PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+            PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, tab, ki, p->tw[NL], nullptr, st));
+            if (p->d == 3)
+                PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
         }
-        if (p->d == 3)
-            PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
-        PLAUNCH(p, FSE_PASS_KIN, st,
-                L::line(NL, 1, psi, nlines, (k == nsteps - 1) ? kh : kf, ki, p->tw[NL], nullptr, st));
-        if (p->d == 3)
-            PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     }
     PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
     p->t += nsteps * dt;
@@ -1037,8 +1061,19 @@ fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* strea
     if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
     if (nsteps == 0) return FSE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, st)
-                                  : step_impl<float>(plan, psi, nsteps, dt, st);
+    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 2, st)
+                                  : step_impl<float>(plan, psi, nsteps, dt, 2, st);
+}
+
+fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream) {
+    g_err.clear();
+    if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
+    if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
+    if (nsteps == 0) return FSE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 4, st)
+                                  : step_impl<float>(plan, psi, nsteps, dt, 4, st);
 }
 
 fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* rho_frozen, void* stream) {

@@ -26,7 +26,7 @@ KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_
 
 EXPORTS = [
     "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
-    "fse_set_time", "fse_get_time", "fse_step", "fse_apply_H", "fse_nonlocal_potential",
+    "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
@@ -79,6 +79,7 @@ def lib():
         "fse_set_time": (st, [vp, d]),
         "fse_get_time": (st, [vp, dp]),
         "fse_step": (st, [vp, vp, i, d, vp]),
+        "fse_step4": (st, [vp, vp, i, d, vp]),
         "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
         "fse_nonlocal_potential": (st, [vp, vp, vp, vp]),
         "fse_mass": (st, [vp, vp, vp, vp]),
@@ -223,9 +224,14 @@ class Plan:
         _check(lib().fse_workspace_size(self._h, ctypes.byref(b)))
         return b.value
 
-    def step(self, psi, nsteps: int, dt: float, stream=None):
+    def step(self, psi, nsteps: int, dt: float, stream=None, order: int = 2):
+        """nsteps steps in place: TS2-GauSum (order 2, fse_step) or its fourth-order
+        triple-jump composition (order 4, fse_step4)."""
         self._check_psi(psi)
-        _check(lib().fse_step(self._h, _ptr(psi), int(nsteps), float(dt), _stream(stream)))
+        if order not in (2, 4):
+            raise ValueError("order must be 2 or 4")
+        fn = lib().fse_step if order == 2 else lib().fse_step4
+        _check(fn(self._h, _ptr(psi), int(nsteps), float(dt), _stream(stream)))
         return psi
 
     def apply_H(self, psi, out=None, rho_frozen=None, stream=None):

@@ -277,6 +277,61 @@ def test_widths_follow_virial_law_on_the_gpu():
     assert abs(r2 - exact) < 5e-7
 
 
+@pytest.mark.parametrize("name", ["aniso2d", "ddi3d", "local3d", "ddi2xz", "rad3_3d"])
+@pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-11), (fse.C64, 1e-5)])
+def test_fourth_order_steps_against_oracle(name, prec, tol):
+    p = P(name)
+    psi0 = _psi0(p, seed=7)
+    pr = _oracle_problem(p)
+    for n in (1, 4):
+        ref, t = pr.run4(psi0, n, p.dt)
+        plan = fse.Plan.from_params(p, prec)
+        x = _dev(psi0, prec)
+        plan.step(x, n, p.dt, order=4)
+        err = _rel(_host(x), ref)
+        _note(f"[parity] order 4 {name} prec={prec} steps={n}: {err:.3e}")
+        assert err < tol
+        assert abs(plan.time - t) < 1e-15
+
+
+def test_orders_mixed_on_one_plan():
+    # the kinetic tables of both schedules live side by side in the plan:
+    # alternating the orders must follow the oracle's trajectory
+    p = P("aniso2d")
+    psi = _psi0(p, seed=8)
+    pr = _oracle_problem(p)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi)
+    t = 0.0
+    for order, n, dt in [(4, 3, p.dt), (2, 3, p.dt), (4, 2, 2 * p.dt), (2, 1, p.dt), (4, 1, -p.dt)]:
+        psi, t = (pr.run4 if order == 4 else pr.run)(psi, n, dt, t=t)
+        plan.step(x, n, dt, order=order)
+    assert _rel(_host(x), psi) < 1e-11
+    assert abs(plan.time - t) < 1e-14
+
+
+def test_fourth_order_converges_at_order_4_on_the_gpu():
+    # the oracle pin's problem (s = 0.8; at s = 1.2 with noise in every mode
+    # these step sizes are not yet asymptotic, on either side)
+    p = W.Params(d=2, N=(64, 64), L=(8.0, 8.0), s=0.8, Omega=0.6, gamma=(1.0, 1.3), beta=30.0, lam=2.0,
+                 kernel="coulomb", dt=0.05, name="order4")
+    psi0 = W.harmonic_vortex_2d(p.N, p.L, seed=3)
+    T = 0.4
+    plan = fse.Plan.from_params(p, fse.C128)
+    ref = _dev(psi0)
+    plan.step(ref, 512, T / 512, order=4)
+    ref = _host(ref)
+    errs = []
+    for n in (8, 16, 32):
+        plan.time = 0.0
+        x = _dev(psi0)
+        plan.step(x, n, T / n, order=4)
+        errs.append(_rel(_host(x), ref))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    _note(f"[parity] order-4 errors {errs}, orders {orders}")
+    assert all(3.6 < o < 4.4 for o in orders)
+
+
 def test_reversibility_and_mass():
     p = P("ddi3d")
     psi0 = _psi0(p, seed=5)
