@@ -45,6 +45,12 @@ def derivative(psi, N, L, axis):
     return np.fft.ifftn(1j * _bcast(mu, axis, len(N)) * np.fft.fftn(psi))
 
 
+def apply_Lz(psi, N, L):
+    """Lz psi = -i (x D_y - y D_x) psi (eq. AME's operator) with spectral derivatives."""
+    X = np.meshgrid(*axes(N, L), indexing="ij")
+    return -1j * (X[0] * derivative(psi, N, L, 1) - X[1] * derivative(psi, N, L, 0))
+
+
 def angular_momentum(psi, N, L):
     """<Lz> = h^d sum psi^* (-i)(x D_y - y D_x) psi (real part)."""
     X = np.meshgrid(*axes(N, L), indexing="ij")
@@ -63,7 +69,10 @@ def energy_parts(prob, psi, t=0.0):
     ph = np.fft.fftn(psi)
     ekin = 0.5 * vol / n * float(np.sum(om * np.abs(ph) ** 2))
     rho = np.abs(psi) ** 2
-    epot = vol * float(np.sum(trap(N, L, prob.gamma, prob.Omega, t) * rho))
+    W = trap(N, L, prob.gamma, prob.Omega, t)
+    if getattr(prob, "U", None) is not None:
+        W = W + prob.U
+    epot = vol * float(np.sum(W * rho))
     eint = 0.5 * prob.beta * vol * float(np.sum(rho ** 2))
     enon = 0.5 * prob.lam * vol * float(np.sum(prob.potential(rho) * rho))
     erot = -prob.Omega * angular_momentum(psi, N, L)
@@ -103,6 +112,12 @@ def apply_H(prob, psi, rho_frozen=None):
     kin = np.fft.ifftn(0.5 * om * np.fft.fftn(psi))
     rho = np.abs(psi) ** 2 if rho_frozen is None else rho_frozen
     V = trap(N, L, prob.gamma, 0.0, 0.0)
+    if getattr(prob, "U", None) is not None:
+        if prob.Omega != 0.0:
+            # U is static in the rotating Lagrangian coordinates, which turn
+            # against the frame of H unless Omega = 0
+            raise NotImplementedError("an external potential needs Omega = 0 in H psi")
+        V = V + prob.U
     pot = (V + prob.beta * rho + prob.lam * prob.potential(rho)) * psi
     X = np.meshgrid(*axes(N, L), indexing="ij")
     Lz = -1j * (X[0] * derivative(psi, N, L, 1) - X[1] * derivative(psi, N, L, 0))

@@ -89,7 +89,12 @@ class GroundState:
     def frozen(self, phi_n):
         """W^n = V + beta rho^n + lam Phi^n of the time level phi^n."""
         rho = np.abs(phi_n) ** 2
-        return self.V + self.prob.beta * rho + self.prob.lam * self.prob.potential(rho)
+        V = self.V
+        if getattr(self.prob, "U", None) is not None:
+            if self.prob.Omega != 0.0:
+                raise NotImplementedError("an external potential needs Omega = 0 in the ground-state step")
+            V = V + self.prob.U
+        return V + self.prob.beta * rho + self.prob.lam * self.prob.potential(rho)
 
     def A_TF(self, W, v):
         return W * v - self.prob.Omega * self.Lz(v)

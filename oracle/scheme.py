@@ -127,6 +127,9 @@ class Problem:
         self.mu, self.c, self.m = float(mu), float(c), float(m)
         self.delta = delta
         self.axis = tuple(float(a) for a in axis)
+        # optional real potential U(x~) on the computational grid, added to the
+        # nonlinear phase as dt * U (static in the rotating Lagrangian coordinates)
+        self.U = None
         if kernel in ("ddi2", "ddi3") and self.Omega != 0.0 and (self.axis[0] != 0.0 or self.axis[1] != 0.0):
             # in the rotating Lagrangian frame the axis m(t) = A^{-1}(t) n turns
             # unless n is the rotation axis (eq. Kernel_Rot)
@@ -160,6 +163,8 @@ class Problem:
         rho = np.abs(phi) ** 2
         theta = tau * self.beta * rho + self.lam * tau * self.potential(rho)
         theta = theta + trap_integral(self.N, self.L, self.gamma, self.Omega, t, tau)
+        if self.U is not None:
+            theta = theta + tau * self.U
         return phi * np.exp(-1j * theta)
 
     def step(self, psi, t, dt):
