@@ -123,6 +123,38 @@ fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* strea
  * three kinetic sub-steps (half linear steps that meet are merged). */
 fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
+/* Optional real potential U(x~) on the plan's grid, added to the nonlinear
+ * phase of fse_step and fse_step4 as dt * U and to the potential energy of
+ * fse_energy (eq. SFSE with V + U; U is static in the rotating Lagrangian
+ * coordinates x~ of the step).  U: device array [N0][N1]([N2]) of doubles
+ * (complex128 plans) or floats (complex64 plans), caller-owned; the plan keeps
+ * the pointer, not a copy, so the array must stay valid and unchanged while
+ * calls that use it run.  NULL clears it.  fse_apply_H and fse_gs_step add U
+ * only when Omega = 0 (with rotation the two frames differ) and return
+ * FSE_ERR_UNSUPPORTED otherwise. */
+fse_status fse_set_potential(fse_plan plan, const void* U);
+
+/* Adjoint (reverse-mode derivative) of nsteps TS2-GauSum steps of size dt
+ * from psi0 at the plan's time t.  The paper gives none: this is the discrete
+ * adjoint of fse_step, derived by hand (conjugate kinetic phases, reversed
+ * FFT order, the self-adjoint GauSum convolution, the linearised nonlinear
+ * phase).  Gradient convention, for a real loss L: g = dL/dRe(psi) +
+ * i dL/dIm(psi), so that dL = Re sum conj(g) dpsi.
+ *   grad:   on entry dL/dpsi(t + nsteps dt), on exit dL/dpsi0 (in place);
+ *   grad_U: NULL, or a real array (plan precision) to which dL/dU is added.
+ * psi0 is not modified and must not alias grad; the plan's time is unchanged.
+ * The forward states of the segment are recomputed from psi0, so a caller
+ * keeps one checkpoint per segment.  The first call, or a longer segment
+ * than before, allocates nsteps * N * (complex + real) bytes of workspace
+ * (synchronising the device); later calls allocate nothing. */
+fse_status fse_step_adjoint(fse_plan plan, const void* psi0, int nsteps, double dt,
+                            void* grad, void* grad_U, void* stream);
+
+/* out = Lz psi = -i (x d_y - y d_x) psi with Fourier derivatives (the
+ * operator of eq. AME, whose expectation fse_angular_momentum returns).
+ * out must not alias psi. */
+fse_status fse_apply_Lz(fse_plan plan, const void* psi, void* out, void* stream);
+
 /* H psi in the lab frame (the operator of eq. SFSE; with a frozen density it
  * is the operator A^{BE,n} of Section 3.2 without its I/dt part):
  *   H psi = (1/2)(-Lap+m^2)^s psi + (V + beta rho + lambda Phi[rho]) psi - Omega Lz psi,

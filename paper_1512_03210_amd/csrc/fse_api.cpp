@@ -20,6 +20,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -81,9 +82,12 @@ struct fse_plan_s {
     std::vector<double> khat_host;
     void* X1 = nullptr;
     void* X2 = nullptr;
-    void* kin[3] = {nullptr, nullptr, nullptr};
-    double kin_tau[3] = {NAN, NAN, NAN};
+    void* kin[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    double kin_tau[7] = {NAN, NAN, NAN, NAN, NAN, NAN, NAN};
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
+    const void* U = nullptr;  // optional caller-owned real potential on the grid (fse_set_potential)
+    void* adj = nullptr;      // adjoint workspace (fse_step_adjoint), grown on demand
+    size_t adj_bytes = 0;
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
     double* gs_out = nullptr;
     void* pd = nullptr;    // P_Delta table (layout of the kinetic tables) for pd_c0 = 1/dt
@@ -103,6 +107,12 @@ struct fse_plan_s {
 };
 
 namespace {
+
+void dev_free(fse_plan p, void* ptr, size_t bytes) {
+    (void)hipFree(ptr);
+    p->allocs.erase(std::remove(p->allocs.begin(), p->allocs.end(), ptr), p->allocs.end());
+    p->bytes -= bytes;
+}
 
 fse_status dev_alloc(fse_plan p, void** ptr, size_t bytes) {
     hipError_t e = hipMalloc(ptr, bytes);
@@ -264,8 +274,8 @@ double dmu(const fse_plan p, int j) { return (j < p->d) ? 2.0 * kPi / (2.0 * p->
 
 // Kinetic table for step length tau; slot 0 holds the half step at the ends
 // of a call, slot 1 the merged halves between steps, slot 2 the merged halves
-// between the sub-steps of a composed step; each is rebuilt only when its tau
-// changes.
+// between the sub-steps of a composed step, slots 3-6 the adjoint's +dt/2,
+// +dt, -dt/2, -dt; each is rebuilt only when its tau changes.
 template <typename R> fse_status kin_table(fse_plan p, double tau, int slot, void** out, hipStream_t st) {
     if (p->kin[slot] && p->kin_tau[slot] == tau) {
         *out = p->kin[slot];
@@ -346,6 +356,8 @@ fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
     a.cs = (gx2 - gy2) / 4.0 * ss;
     a.bdt = p->beta * dt;
     a.ldt = p->lambda * dt;
+    a.U = p->U;
+    a.udt = dt;
     return a;
 }
 
@@ -471,7 +483,7 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     const fse::GridGeom g = geom(p);
     const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
     if (kind == 0) {
-        HIPCHK(L::red_local(psi, nullptr, p->n, g, 0, 0, 0, 0, p->partials, 0, kRedBlocks, st));
+        HIPCHK(L::red_local(psi, nullptr, nullptr, p->n, g, 0, 0, 0, 0, p->partials, 0, kRedBlocks, st));
         HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, 1, 0, vol, (double)p->n, p->beta, p->lambda, p->Omega,
                                      out, st));
         return FSE_OK;
@@ -492,7 +504,7 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
         const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
         const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
         const double th = 2.0 * p->Omega * p->t;
-        HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
+        HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, p->U, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
                             (gx2 - gy2) / 4.0 * std::cos(th), (gx2 - gy2) / 4.0 * std::sin(th), p->partials, 0,
                             kRedBlocks, st));
     } else {
@@ -516,6 +528,95 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     }
     HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, nslot, kind, vol, (double)p->n, p->beta, p->lambda, p->Omega,
                                  out, st));
+    return FSE_OK;
+}
+
+// Kinetic flow over all axes, dst = K src with K = exp(-i tau omega/2) (tab
+// built for tau): physical space in and out, out of place allowed.
+template <typename R> fse_status kin_full(fse_plan p, const void* src, void* dst, void* tab, hipStream_t st) {
+    using L = fse::Launch<R>;
+    const int N0 = p->N[0], NL = p->last();
+    HIPCHK(L::strided(N0, false, 0, src, dst, 1, p->C0, p->tw[N0], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, dst, dst, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::line(NL, 1, dst, (int)p->lines_last(), tab, kin_index(p), p->tw[NL], nullptr, st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, dst, dst, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::strided(N0, true, 0, dst, dst, 1, p->C0, p->tw[N0], nullptr, st));
+    return FSE_OK;
+}
+
+// Adjoint workspace: the state psi1 = K(dt/2) psi of every step of a segment
+// (complex), its phase theta (real), and two real arrays (q, Phi).
+fse_status ensure_adj(fse_plan p, int nsteps) {
+    const size_t need = (size_t)nsteps * p->n * (p->csize + p->rsize) + 2 * (size_t)p->n * p->rsize;
+    if (p->adj && p->adj_bytes >= need) return FSE_OK;
+    if (p->adj) {
+        dev_free(p, p->adj, p->adj_bytes);
+        p->adj = nullptr;
+        p->adj_bytes = 0;
+    }
+    fse_status s = dev_alloc(p, &p->adj, need);
+    if (s != FSE_OK) return s;
+    p->adj_bytes = need;
+    return FSE_OK;
+}
+
+// Reverse of nsteps TS2 steps from psi0 at the plan's time: g holds dL/dpsi at
+// the end of the segment on entry and dL/dpsi0 on exit; gU (optional) gains
+// dL/dU.  The forward states of the segment are recomputed first (the caller
+// keeps checkpoints), then the steps are reversed with the kinetic halves that
+// meet merged into one pass of -dt.
+template <typename R>
+fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, void* g, void* gU, hipStream_t st) {
+    using L = fse::Launch<R>;
+    fse_status s = ensure_adj(p, nsteps);
+    if (s != FSE_OK) return s;
+    void *kp_h = nullptr, *kp_f = nullptr, *km_h = nullptr, *km_f = nullptr;
+    if ((s = kin_table<R>(p, 0.5 * dt, 3, &kp_h, st)) != FSE_OK) return s;
+    if ((s = kin_table<R>(p, -0.5 * dt, 5, &km_h, st)) != FSE_OK) return s;
+    if (nsteps > 1) {
+        if ((s = kin_table<R>(p, dt, 4, &kp_f, st)) != FSE_OK) return s;
+        if ((s = kin_table<R>(p, -dt, 6, &km_f, st)) != FSE_OK) return s;
+    }
+    const size_t cb = (size_t)p->n * p->csize, rb = (size_t)p->n * p->rsize;
+    char* base = static_cast<char*>(p->adj);
+    char* thb = base + (size_t)nsteps * cb;
+    auto S = [&](int k) { return static_cast<void*>(base + (size_t)k * cb); };
+    auto TH = [&](int k) { return static_cast<void*>(thb + (size_t)k * rb); };
+    void* q = thb + (size_t)nsteps * rb;
+    void* Phi = thb + (size_t)(nsteps + 1) * rb;
+    const fse::GridGeom gg = geom(p);
+    // forward: psi1 and theta of every step
+    if ((s = kin_full<R>(p, psi0, S(0), kp_h, st)) != FSE_OK) return s;
+    for (int k = 0; k < nsteps; ++k) {
+        if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, st)) != FSE_OK) return s;
+        const fse::PhaseArgs pa = phase_args(p, p->t + k * dt, dt);
+        void* next = (k + 1 < nsteps) ? S(k + 1) : nullptr;
+        HIPCHK(L::adj_theta(S(k), p->nl ? Phi : nullptr, p->U, TH(k), next, p->n, gg, pa, st));
+        if (next && (s = kin_full<R>(p, next, next, kp_f, st)) != FSE_OK) return s;
+    }
+    // reverse
+    if ((s = kin_full<R>(p, g, g, km_h, st)) != FSE_OK) return s;
+    for (int k = nsteps - 1; k >= 0; --k) {
+        HIPCHK(L::adj_q(g, S(k), TH(k), q, gU, p->n, dt, st));
+        if (p->nl && (s = potential_impl<R>(p, q, 2, Phi, st)) != FSE_OK) return s;
+        HIPCHK(L::adj_g1(g, S(k), TH(k), q, p->nl ? Phi : nullptr, p->n, p->beta * dt, p->lambda * dt, st));
+        if ((s = kin_full<R>(p, g, g, (k > 0) ? km_f : km_h, st)) != FSE_OK) return s;
+    }
+    return FSE_OK;
+}
+
+// out = Lz psi = -i (x D_y - y D_x) psi.
+template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void* out, hipStream_t st) {
+    using L = fse::Launch<R>;
+    fse_status s = ensure_diag(p);
+    if (s != FSE_OK) return s;
+    void* B = static_cast<char*>(p->diag) + (size_t)p->n * p->csize;
+    const fse::GridGeom g = geom(p);
+    HIPCHK(hipMemsetAsync(out, 0, (size_t)p->n * p->csize, st));
+    HIPCHK(deriv_axis<R>(p, 1, psi, B, st));
+    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 0, -1.0, 0, 0, 0, 0, 0, st));
+    HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
+    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, -1.0, 0, 0, 0, 0, 0, st));
     return FSE_OK;
 }
 
@@ -559,11 +660,11 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
     if (p->Omega != 0.0) {
         // -Omega Lz psi = i Omega (x D_y psi - y D_x psi), one derivative pass per axis
         HIPCHK(deriv_axis<R>(p, 1, psi, B, st));
-        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, 0, p->Omega, 0, 0, 0, 0, 0, st));
+        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, nullptr, p->n, g, 0, p->Omega, 0, 0, 0, 0, 0, st));
         HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
-        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, p->n, g, 1, p->Omega, 0, 0, 0, 0, 0, st));
+        HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, p->Omega, 0, 0, 0, 0, 0, st));
     }
-    HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, p->n, g, 2, p->Omega, p->beta, p->lambda,
+    HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, p->U, p->n, g, 2, p->Omega, p->beta, p->lambda,
                       p->gamma[0], p->gamma[1], (p->d == 3) ? p->gamma[2] : 0.0, st));
     return FSE_OK;
 }
@@ -686,7 +787,7 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     if (p->nl) {
         if ((s = potential_impl<R>(p, psi, 1, b.Phi, st)) != FSE_OK) return s;
     }
-    HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
+    HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, p->U, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
                         (p->d == 3) ? p->gamma[2] : 0.0, st));
     if ((s = pd_table<R>(p, c0, st)) != FSE_OK) return s;
     // right-hand side P_Delta psi/dt, held in sv until r is formed
@@ -1080,6 +1181,8 @@ fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* r
     g_err.clear();
     if (!plan || !psi || !Hpsi) return fail(FSE_ERR_ARG, "plan, psi and Hpsi must not be NULL");
     if (psi == Hpsi) return fail(FSE_ERR_ARG, "psi and Hpsi must not alias");
+    if (plan->U && plan->Omega != 0.0)
+        return fail(FSE_ERR_UNSUPPORTED, "a grid potential set by fse_set_potential needs Omega = 0 in H psi");
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? apply_H_impl<double>(plan, psi, Hpsi, rho_frozen, st)
                                   : apply_H_impl<float>(plan, psi, Hpsi, rho_frozen, st);
@@ -1092,6 +1195,8 @@ fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxi
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FSE_ERR_ARG, "dt must be finite and > 0");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite and > 0");
     if (maxit < 1) return fail(FSE_ERR_ARG, "maxit must be >= 1");
+    if (plan->U && plan->Omega != 0.0)
+        return fail(FSE_ERR_UNSUPPORTED, "a grid potential set by fse_set_potential needs Omega = 0 in the ground-state step");
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? gs_step_impl<double>(plan, psi, dt, tol, maxit, stats, st)
                                   : gs_step_impl<float>(plan, psi, dt, tol, maxit, stats, st);
@@ -1119,6 +1224,35 @@ fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* str
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 1, out_dev, st)
                                   : reduce_impl<float>(plan, psi, 1, out_dev, st);
+}
+
+fse_status fse_set_potential(fse_plan plan, const void* U) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    plan->U = U;
+    return FSE_OK;
+}
+
+fse_status fse_step_adjoint(fse_plan plan, const void* psi0, int nsteps, double dt, void* grad, void* grad_U,
+                            void* stream) {
+    g_err.clear();
+    if (!plan || !psi0 || !grad) return fail(FSE_ERR_ARG, "plan, psi0 and grad must not be NULL");
+    if (psi0 == grad) return fail(FSE_ERR_ARG, "psi0 and grad must not alias");
+    if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
+    if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
+    if (nsteps == 0) return FSE_OK;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? adjoint_impl<double>(plan, psi0, nsteps, dt, grad, grad_U, st)
+                                  : adjoint_impl<float>(plan, psi0, nsteps, dt, grad, grad_U, st);
+}
+
+fse_status fse_apply_Lz(fse_plan plan, const void* psi, void* out, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out) return fail(FSE_ERR_ARG, "plan, psi and out must not be NULL");
+    if (psi == out) return fail(FSE_ERR_ARG, "psi and out must not alias");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? apply_Lz_impl<double>(plan, psi, out, st)
+                                  : apply_Lz_impl<float>(plan, psi, out, st);
 }
 
 fse_status fse_moments(fse_plan plan, const void* psi, double* out_dev, void* stream) {

@@ -22,18 +22,19 @@ __device__ __forceinline__ double2 cm(double2 a, double2 b) {
 }
 }  // namespace gsd
 
-// W = V(x) + beta |psi|^2 + lam Phi, with the trap V unrotated (the frame in
-// which the energy carries -Omega Lz).
+// W = V(x) + beta |psi|^2 + lam Phi (+ U, an optional potential on the grid),
+// with the trap V unrotated (the frame in which the energy carries -Omega Lz).
 template <typename R>
-__global__ void k_gs_frozen(const typename CT<R>::T* __restrict__ psi, const R* __restrict__ Phi, R* __restrict__ W,
-                            long n, GridGeom g, double beta, double lam, double g0, double g1, double g2) {
+__global__ void k_gs_frozen(const typename CT<R>::T* __restrict__ psi, const R* __restrict__ Phi,
+                            const R* __restrict__ U, R* __restrict__ W, long n, GridGeom g, double beta, double lam,
+                            double g0, double g1, double g2) {
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         decode(i, g, i0, i1, i2);
         const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy, z = (g.d == 3) ? g.z0 + i2 * g.hz : 0.0;
         const double2 v = gsd::up(psi[i]);
         const double V = 0.5 * (g0 * g0 * x * x + g1 * g1 * y * y + g2 * g2 * z * z);
-        W[i] = R(V + beta * (v.x * v.x + v.y * v.y) + (Phi ? lam * (double)Phi[i] : 0.0));
+        W[i] = R(V + beta * (v.x * v.x + v.y * v.y) + (Phi ? lam * (double)Phi[i] : 0.0) + (U ? (double)U[i] : 0.0));
     }
 }
 

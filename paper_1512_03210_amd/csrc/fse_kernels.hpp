@@ -618,12 +618,14 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
         }
         const R y2 = yv * yv;
         const R base = R(pa.cz) * (zv * zv) + R(pa.ca - pa.cc) * y2;
+        const R* Ux = static_cast<const R*>(pa.U);
         for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
             const R x = R(pa.x0 + e * pa.hx);
             const R Pv = base + R(pa.ca + pa.cc) * (x * x) + R(pa.cs) * (R(2) * x * yv);
             const T v = psi[b][r];
             const R rho = v.x * v.x + v.y * v.y;
-            const R th = R(pa.bdt) * rho + R(pa.ldt) * phi[b][r] + Pv;
+            R th = R(pa.bdt) * rho + R(pa.ldt) * phi[b][r] + Pv;
+            if (Ux && lv) th += R(pa.udt) * Ux[(long)e * C + c];
             R sn, cs;
             fsincos(th, &sn, &cs);
             psi[b][r] = T{v.x * cs + v.y * sn, v.y * cs - v.x * sn};  // v * exp(-i th)
@@ -675,6 +677,8 @@ __device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
     pa.cs = (b.Omega == 0.0) ? 0.0 : b.gdiff * sin(b.Omega * (2.0 * tn + b.dt)) * f;
     pa.bdt = b.bdt;
     pa.ldt = b.ldt;
+    pa.U = nullptr;
+    pa.udt = 0.0;
     return pa;
 }
 
@@ -844,12 +848,12 @@ __device__ __forceinline__ void decode(long i, const GridGeom& g, int& i0, int& 
 }
 
 // slots: 0 sum rho, 1 sum W rho, 2 sum rho^2, 3 sum Phi rho.
-// W = wa (x^2+y^2) + wz z^2 + wc (x^2-y^2) + ws 2xy.
+// W = wa (x^2+y^2) + wz z^2 + wc (x^2-y^2) + ws 2xy, plus U when given.
 template <typename R>
 __global__ __launch_bounds__(RED_THREADS) void k_red_local(const typename CT<R>::T* __restrict__ psi,
-                                                           const R* __restrict__ Phi, long n, GridGeom g, double wa,
-                                                           double wz, double wc, double ws, double* partials,
-                                                           int slot0) {
+                                                           const R* __restrict__ Phi, const R* __restrict__ U, long n,
+                                                           GridGeom g, double wa, double wz, double wc, double ws,
+                                                           double* partials, int slot0) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (long i = blockIdx.x * (long)RED_THREADS + threadIdx.x; i < n; i += (long)gridDim.x * RED_THREADS) {
         int i0, i1, i2;
@@ -857,7 +861,8 @@ __global__ __launch_bounds__(RED_THREADS) void k_red_local(const typename CT<R>:
         const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy, z = (g.d == 3) ? g.z0 + i2 * g.hz : 0.0;
         const auto v = psi[i];
         const double rho = (double)v.x * v.x + (double)v.y * v.y;
-        const double Wv = wa * (x * x + y * y) + wz * z * z + wc * (x * x - y * y) + ws * 2.0 * x * y;
+        double Wv = wa * (x * x + y * y) + wz * z * z + wc * (x * x - y * y) + ws * 2.0 * x * y;
+        if (U) Wv += (double)U[i];
         acc[0] += rho;
         acc[1] += Wv * rho;
         acc[2] += rho * rho;
@@ -1018,8 +1023,8 @@ static __global__ __launch_bounds__(RED_THREADS) void k_red_final(const double* 
 template <typename R>
 __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R>::T* __restrict__ D,
                           const typename CT<R>::T* __restrict__ psi, const R* __restrict__ rho_in,
-                          const R* __restrict__ Phi, long n, GridGeom g, int what, double Omega, double beta,
-                          double lam, double g0, double g1, double g2) {
+                          const R* __restrict__ Phi, const R* __restrict__ U, long n, GridGeom g, int what,
+                          double Omega, double beta, double lam, double g0, double g1, double g2) {
     using T = typename CT<R>::T;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
@@ -1034,7 +1039,7 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
             const T v = psi[i];
             const double rho = rho_in ? (double)rho_in[i] : (double)v.x * v.x + (double)v.y * v.y;
             const double V = 0.5 * (g0 * g0 * x * x + g1 * g1 * y * y + g2 * g2 * z * z);
-            const double f = V + beta * rho + (Phi ? lam * (double)Phi[i] : 0.0);
+            const double f = V + beta * rho + (Phi ? lam * (double)Phi[i] : 0.0) + (U ? (double)U[i] : 0.0);
             h = T{R(h.x + f * v.x), R(h.y + f * v.y)};
         }
         H[i] = h;

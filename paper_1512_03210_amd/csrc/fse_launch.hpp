@@ -37,25 +37,33 @@ template <typename R> struct Launch {
     // scale * exp(-i tau omega/2), kind 1 the resolvent scale / (c0 + omega/2), kind 2 scale * omega/2.
     static hipError_t build_kin(void* Q, int T0, int T1, int T2, double dmu0, double dmu1, double dmu2, double s,
                                 double m2, int kind, double tau, double c0, double scale, hipStream_t st);
-    static hipError_t red_local(const void* psi, const void* Phi, long n, const GridGeom& g, double wa, double wz,
-                                double wc, double ws, double* partials, int slot0, int nblk, hipStream_t st);
+    static hipError_t red_local(const void* psi, const void* Phi, const void* U, long n, const GridGeom& g, double wa,
+                                double wz, double wc, double ws, double* partials, int slot0, int nblk,
+                                hipStream_t st);
     static hipError_t red_kin(const void* ph, long n, const GridGeom& g, double dmu0, double dmu1, double dmu2,
                               double s, double m2, double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_lz(const void* psi, const void* D, long n, const GridGeom& g, int coord_axis,
                              double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_moments(const void* psi, long n, const GridGeom& g, double* partials, int nblk,
                                   hipStream_t st);
-    static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi, long n,
-                              const GridGeom& g, int what, double Omega, double beta, double lam, double g0,
-                              double g1, double g2, hipStream_t st);
+    static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi,
+                              const void* U, long n, const GridGeom& g, int what, double Omega, double beta,
+                              double lam, double g0, double g1, double g2, hipStream_t st);
     // Fourier derivative along one axis in one pass, out = D in (out of place allowed): strided axis of
     // [B0][N][B2] (line = false) or nlines = B0 contiguous lines of N points (line = true); the
     // multiplier is i p dmu scale for frequency index p (Nyquist kept as -N/2).
     static hipError_t deriv(int N, bool line, const void* in, void* out, int B0, int B2, const void* twN,
                             double dmu, double scale, hipStream_t st);
     // Ground-state step (kernels in fse_gs.hpp).
-    static hipError_t gs_frozen(const void* psi, const void* Phi, void* W, long n, const GridGeom& g, double beta,
-                                double lam, double g0, double g1, double g2, hipStream_t st);
+    static hipError_t gs_frozen(const void* psi, const void* Phi, const void* U, void* W, long n, const GridGeom& g,
+                                double beta, double lam, double g0, double g1, double g2, hipStream_t st);
+    // Adjoint of the split step (kernels in fse_adjoint.hpp).
+    static hipError_t adj_theta(const void* psi1, const void* Phi, const void* U, void* theta, void* psi2, long n,
+                                const GridGeom& g, const PhaseArgs& pa, hipStream_t st);
+    static hipError_t adj_q(const void* g2, const void* psi1, const void* theta, void* q, void* gU, long n,
+                            double udt, hipStream_t st);
+    static hipError_t adj_g1(void* g, const void* psi1, const void* theta, const void* q, const void* Phiq, long n,
+                             double bdt, double ldt, hipStream_t st);
     static hipError_t gs_tf(const void* v, const void* Dx, const void* Dy, const void* W, void* u, long n,
                             const GridGeom& g, double Omega, hipStream_t st);
     static hipError_t gs_axpy(const void* a, const void* b, void* out, long n, double cr, double ci, hipStream_t st);

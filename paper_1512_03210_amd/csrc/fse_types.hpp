@@ -25,6 +25,8 @@ struct PhaseArgs {
     double cs;                       // coefficient of 2 x~ y~
     double bdt;                      // beta * dt
     double ldt;                      // lambda * dt
+    const void* U;                   // optional real potential on the grid (plan precision) or null
+    double udt;                      // dt, the factor of U in the phase
 };
 
 // Grid geometry for the elementwise kernels and reductions.

@@ -26,7 +26,7 @@ KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_
 
 EXPORTS = [
     "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
-    "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_apply_H", "fse_nonlocal_potential",
+    "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_set_potential", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
@@ -80,6 +80,9 @@ def lib():
         "fse_get_time": (st, [vp, dp]),
         "fse_step": (st, [vp, vp, i, d, vp]),
         "fse_step4": (st, [vp, vp, i, d, vp]),
+        "fse_set_potential": (st, [vp, vp]),
+        "fse_step_adjoint": (st, [vp, vp, i, d, vp, vp, vp]),
+        "fse_apply_Lz": (st, [vp, vp, vp, vp]),
         "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
         "fse_nonlocal_potential": (st, [vp, vp, vp, vp]),
         "fse_mass": (st, [vp, vp, vp, vp]),
@@ -184,6 +187,7 @@ class Plan:
         self.cdtype = torch.complex128 if precision == C128 else torch.complex64
         self.rdtype = torch.float64 if precision == C128 else torch.float32
         self._h = ctypes.c_void_p()
+        self._U = None
         _check(lib().fse_plan_create(ctypes.byref(self._h), self.d, _iarr(self.N), _darr(self.L), s, Omega,
                                      _darr(gamma), beta, lam,
                                      ctypes.byref(kernel) if kernel is not None else None,
@@ -208,6 +212,38 @@ class Plan:
     def _check_psi(self, psi):
         if psi.dtype != self.cdtype or tuple(psi.shape) != self.N or not psi.is_contiguous() or not psi.is_cuda:
             raise ValueError(f"psi must be a contiguous {self.cdtype} device tensor of shape {self.N}")
+
+    def _check_real(self, a, what):
+        if a.dtype != self.rdtype or tuple(a.shape) != self.N or not a.is_contiguous() or not a.is_cuda:
+            raise ValueError(f"{what} must be a contiguous {self.rdtype} device tensor of shape {self.N}")
+
+    def set_potential(self, U=None):
+        """Grid potential U(x~) added to the step's phase and the energy (fse_set_potential);
+        the plan holds a reference to the tensor.  None clears it."""
+        if U is not None:
+            self._check_real(U, "U")
+        _check(lib().fse_set_potential(self._h, None if U is None else _ptr(U)))
+        self._U = U
+
+    def step_adjoint(self, psi0, nsteps: int, dt: float, grad, grad_U=None, stream=None):
+        """Reverse of nsteps steps from psi0 at the plan's time (fse_step_adjoint): grad is
+        dL/dpsi at the end on entry and dL/dpsi0 on exit; grad_U, if given, gains dL/dU."""
+        self._check_psi(psi0)
+        self._check_psi(grad)
+        if grad_U is not None:
+            self._check_real(grad_U, "grad_U")
+        _check(lib().fse_step_adjoint(self._h, _ptr(psi0), int(nsteps), float(dt), _ptr(grad),
+                                      None if grad_U is None else _ptr(grad_U), _stream(stream)))
+        return grad
+
+    def apply_Lz(self, psi, out=None, stream=None):
+        """Lz psi = -i (x d_y - y d_x) psi (fse_apply_Lz)."""
+        import torch
+        self._check_psi(psi)
+        out = torch.empty_like(psi) if out is None else out
+        self._check_psi(out)
+        _check(lib().fse_apply_Lz(self._h, _ptr(psi), _ptr(out), _stream(stream)))
+        return out
 
     @property
     def time(self) -> float:

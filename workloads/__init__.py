@@ -178,6 +178,9 @@ def vortex_lattice_2d(N, L, seed=0, nv=7, radius=1.5, jitter=0.05, width2=2.0):
 #   dipole3d_256: the same physics on a 256^3 grid (512^3 padding): the
 #         headline 3D 256^3 split step.
 #   coulomb3d_96: 3D 96^3 Coulomb (used here only as a parity case).
+#   adjoint3d_96: the differentiation case: the same physics with the trap
+#         given as a grid potential V(x) = |x|^2/2 (gamma = 0 in the plan), the
+#         parameter whose gradient is taken.
 # ---------------------------------------------------------------------------
 PRESETS = {
     "plain2d": Params(d=2, N=(64, 64), L=(8.0, 8.0), s=0.75, Omega=0.5, gamma=(1.0, 1.0),
@@ -192,6 +195,9 @@ PRESETS = {
     "coulomb3d_96": Params(d=3, N=(96, 96, 96), L=(12.0, 12.0, 12.0), s=0.6, Omega=0.4,
                    gamma=(1.0, 1.0, 1.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0,
                    dt=1e-3, steps=200, name="coulomb3d-96"),
+    "adjoint3d_96": Params(d=3, N=(96, 96, 96), L=(12.0, 12.0, 12.0), s=0.6, Omega=0.4,
+                   gamma=(0.0, 0.0, 0.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0,
+                   dt=1e-3, steps=200, name="adjoint3d-96"),
     # ground-state solve at scale: trap and time step not stated; gamma = 1 and
     # the paper's ground-state time step dt = 1e-3 are taken
     "gs3d_256": Params(d=3, N=(256, 256, 256), L=(16.0, 16.0, 16.0), s=0.9, Omega=0.8,
@@ -212,6 +218,25 @@ def initial_state(p: Params, seed: int = 0) -> np.ndarray:
     if p.d == 2:
         return vortex_lattice_2d(p.N, p.L, seed=seed)
     return anisotropic_gaussian(p.N, p.L, p.gamma, seed=seed)
+
+
+def harmonic_potential(N, L, gamma) -> np.ndarray:
+    """V(x) = sum_v gamma_v^2 v^2 / 2 sampled on the grid (float64)."""
+    V = np.zeros(tuple(int(n) for n in N))
+    for g, X in zip(gamma, mesh(N, L)):
+        V = V + 0.5 * g * g * X ** 2
+    return V
+
+
+def adjoint_target(N, L, seed=1):
+    """Target state of the differentiation case: a Gaussian displaced by half a
+    unit along x with a phase ramp along y, plus seeded noise, normalised."""
+    grids = mesh(N, L)
+    arg = (grids[0] - 0.5) ** 2
+    for X in grids[1:]:
+        arg = arg + X ** 2
+    psi = np.exp(-arg / 2.0 + 0.3j * grids[1]) * (1.0 + _noise(grids[0].shape, seed, 1e-3))
+    return normalize(psi, [2.0 * Lj / Nj for Nj, Lj in zip(N, L)])
 
 
 def batch_sweep(count=64, sizes=(128, 256, 384, 512), seed=0, beta=500.0, lam=1.0,
