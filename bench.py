@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -318,6 +319,118 @@ def run_order4(p, prec, steps=20, warmup=2):
             "mass_after": mass}
 
 
+def adjoint_inputs(p):
+    """psi0, V(x) = |x|^2/2 and the target state of the differentiation case (float64 / complex128)."""
+    import workloads as W
+    return (W.anisotropic_gaussian(p.N, p.L, (1.0, 1.0, 1.0), seed=0),
+            W.harmonic_potential(p.N, p.L, (1.0, 1.0, 1.0)), W.adjoint_target(p.N, p.L, seed=1))
+
+
+def adjoint_loss_grad(plan, p, psi0, V, tgt, checkpoint):
+    """Loss |<psi_t, psi(T)>|^2 + 0.1 <Lz> through the checkpointed adjoint; returns
+    (loss, dL/dpsi0, dL/dV, forward seconds, backward seconds)."""
+    import torch
+
+    from paper_1512_03210_amd import autograd as fag
+
+    x0 = torch.from_numpy(psi0).to("cuda:0", plan.cdtype).requires_grad_(True)
+    U = torch.from_numpy(V).to("cuda:0", plan.rdtype).requires_grad_(True)
+    t = torch.from_numpy(tgt).to("cuda:0", plan.cdtype)
+    vol = math.prod(p.h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.time = 0.0
+    xT = fag.evolve(plan, x0, U, p.steps, p.dt, checkpoint)
+    o = vol * torch.sum(torch.conj(t) * xT)
+    loss = torch.abs(o) ** 2 + 0.1 * fag.angular_momentum(plan, xT)
+    lv = float(loss)
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return lv, x0.grad.detach(), U.grad.detach(), t1 - t0, t2 - t1
+
+
+def adjoint_fd(p, psi0, V, tgt, gpsi, gV, ndir, eps=1e-5, seed=7):
+    """Central differences of the FP64 forward loss in ndir seeded directions
+    (dpsi complex, dV real, each of unit discrete norm) against the adjoint's
+    directional derivative Re <gpsi, dpsi> + <gV, dV> (sums, no volume factor)."""
+    import numpy as np
+    import torch
+
+    from paper_1512_03210_amd import fse
+
+    plan = fse.Plan.from_params(p, fse.C128)
+    vol = math.prod(p.h)
+    t = torch.from_numpy(tgt).to("cuda:0")
+    x0 = torch.from_numpy(psi0).to("cuda:0")
+    U0 = torch.from_numpy(V).to("cuda:0")
+    gp = gpsi.to(torch.complex128)
+    gv = gV.to(torch.float64)
+
+    def loss(x, Uv):
+        plan.time = 0.0
+        plan.set_potential(Uv)
+        x = x.clone()
+        plan.step(x, p.steps, p.dt)
+        o = vol * torch.sum(torch.conj(t) * x)
+        return float(torch.abs(o) ** 2 + 0.1 * plan.angular_momentum(x)[0])
+
+    rng = np.random.default_rng(seed)
+    errs = []
+    for _ in range(ndir):
+        dpsi = rng.standard_normal(p.N) + 1j * rng.standard_normal(p.N)
+        dpsi /= math.sqrt(vol * float(np.sum(np.abs(dpsi) ** 2)))
+        dV = rng.standard_normal(p.N)
+        dV /= math.sqrt(vol * float(np.sum(dV ** 2)))
+        dp = torch.from_numpy(dpsi).to("cuda:0")
+        dv = torch.from_numpy(dV).to("cuda:0")
+        fd = (loss(x0 + eps * dp, (U0 + eps * dv).contiguous())
+              - loss(x0 - eps * dp, (U0 - eps * dv).contiguous())) / (2 * eps)
+        an = float(torch.real(torch.sum(torch.conj(gp) * dp)) + torch.sum(gv * dv))
+        errs.append(abs(an - fd) / max(abs(fd), 1e-300))
+    del plan
+    return errs
+
+
+def run_adjoint(p, checkpoint=20, ndir=32):
+    """The differentiation case: nsteps steps forward with a checkpoint every
+    `checkpoint` steps, the loss, and the adjoint back to psi0 and V, in
+    complex64 and complex128; central finite differences of the FP64 forward
+    in ndir directions check both gradients."""
+    import statistics
+
+    import torch
+
+    from paper_1512_03210_amd import fse
+
+    psi0, V, tgt = adjoint_inputs(p)
+    out = {"checkpoint": checkpoint, "steps": p.steps}
+    grads = {}
+    for name, prec in (("c64", fse.C64), ("c128", fse.C128)):
+        plan = fse.Plan.from_params(p, prec)
+        adjoint_loss_grad(plan, p, psi0, V, tgt, checkpoint)  # warm-up: workspace, tables
+        lv, gpsi, gV, tf, tb = adjoint_loss_grad(plan, p, psi0, V, tgt, checkpoint)
+        grads[name] = (gpsi, gV)
+        out[name] = {"loss": lv, "forward_ms": round(1e3 * tf, 3), "backward_ms": round(1e3 * tb, 3),
+                     "forward_ms_per_step": round(1e3 * tf / p.steps, 4),
+                     "backward_ms_per_step": round(1e3 * tb / p.steps, 4),
+                     "backward_over_forward": round(tb / tf, 2)}
+        del plan
+        torch.cuda.empty_cache()
+    g64, g128 = grads["c64"], grads["c128"]
+
+    def rel(a, b):
+        return float(torch.linalg.vector_norm((a.to(b.dtype) - b).flatten()) / torch.linalg.vector_norm(b.flatten()))
+    out["c64_vs_c128_rel_l2"] = {"dL_dpsi0": rel(g64[0], g128[0]), "dL_dV": rel(g64[1], g128[1])}
+    for name in ("c128", "c64"):
+        errs = adjoint_fd(p, psi0, V, tgt, grads[name][0], grads[name][1], ndir)
+        out[name]["fd_directions"] = ndir
+        out[name]["fd_rel_err_max"] = max(errs)
+        out[name]["fd_rel_err_median"] = statistics.median(errs)
+    return out
+
+
 def run_gs(p, prec, steps, tol, maxit=200):
     """Ground-state steps (backward-Euler GFDN, preconditioned BiCGStab) from the
     rotating initial guess; time per step and per Krylov iteration."""
@@ -417,6 +530,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched sweep (0: skip)")
     ap.add_argument("--gs-steps", type=int, default=2, help="ground-state steps at 256^3 complex64 (0: skip)")
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="skip the differentiation case (96^3, 200 steps, adjoint with checkpoints)")
     ap.add_argument("--no-cases", dest="cases", action="store_false",
                     help="skip the 128^3 (1000 steps) and 64^2 (100 steps) cases")
     args = ap.parse_args()
@@ -473,6 +588,15 @@ def main():
                            f"Omega={q.Omega}, beta={q.beta}, lambda={q.lam} z-dipole GauSum, dt={q.dt}, "
                            "initial guess ((1-Omega) phi_ho + Omega phi_ho^v) x z-Gaussian"),
               "c64": run_gs(q, fse.C64, args.gs_steps, 1e-6)}
+    adjoint = None
+    if args.adjoint:
+        q = W.preset("adjoint3d_96")
+        print(f"[bench] differentiation case {q.name}: {q.steps} steps, adjoint", file=sys.stderr, flush=True)
+        adjoint = {"workload": (f"{q.name}: {'x'.join(map(str, q.N))} on [-{q.L[0]:g},{q.L[0]:g}]^3, s={q.s}, "
+                                f"Omega={q.Omega}, beta={q.beta}, lambda={q.lam} Coulomb GauSum on "
+                                f"{'x'.join(str(2 * n) for n in q.N)}, V(x) = |x|^2/2 as a grid potential, "
+                                f"dt={q.dt}, loss |<psi_t, psi(T)>|^2 + 0.1 <Lz>"),
+                   **run_adjoint(q)}
     if args.batch_steps > 0:
         print(f"[bench] batched sweep, {args.batch_steps} steps", file=sys.stderr, flush=True)
         variants["batch_c64"] = run_batch(args.batch_steps)
@@ -529,6 +653,7 @@ def main():
         "fourth_order": order4,
         "cases": cases,
         "ground_state": gs,
+        "differentiation": adjoint,
         "passes": r64["passes"],
         "mass_after": r64["mass_after"],
         "kernel_source_hash": kernel_source_hash(),
