@@ -136,3 +136,34 @@ def test_invalid_arguments():
         plan.gs_step(x, 0.1, tol=0.0)
     with pytest.raises(fse.FseError):
         plan.gs_step(x, 0.1, maxit=0)
+
+
+@pytest.mark.parametrize("prec,gate", [(fse.C128, 1e-10), (fse.C64, 1e-5)])
+def test_optical_lattice_ground_state_steps(prec, gate):
+    # the non-rotating harmonic + optical lattice trap of the paper's second
+    # ground-state example, V = (x^2+y^2)/2 + 10 (sin^2 pi x + sin^2 pi y),
+    # beta = 0, lam = 64 (2D Coulomb): the lattice part as a grid potential;
+    # box [-4,4]^2 at h = 1/8 instead of the paper's 2048^2 grid
+    p = W.Params(d=2, N=(64, 64), L=(4.0, 4.0), s=0.8, Omega=0.0, gamma=(1.0, 1.0), beta=0.0, lam=64.0,
+                 kernel="coulomb", coef=1.0 / (2.0 * math.pi), dt=0.05, name="lattice")
+    X = np.meshgrid(*axes(p.N, p.L), indexing="ij")
+    lattice = 10.0 * (np.sin(math.pi * X[0]) ** 2 + np.sin(math.pi * X[1]) ** 2)
+    pr = _oracle(p)
+    pr.U = lattice
+    g = ogs.GroundState(pr, p.dt)
+    psi = _psi0(p)
+    plan = fse.Plan.from_params(p, prec)
+    rd = torch.float64 if prec == fse.C128 else torch.float32
+    plan.set_potential(torch.from_numpy(lattice).to("cuda:0", rd))
+    x = _dev(psi, prec)
+    tol = 1e-12 if prec == fse.C128 else 1e-6
+    E = [plan.energy(x).cpu().numpy()[5]]
+    for _ in range(5):
+        psi, _ = g.step(psi, rtol=1e-12)
+        st = plan.gs_step(x, p.dt, tol=tol, maxit=500)
+        assert st["converged"]
+        E.append(plan.energy(x).cpu().numpy()[5])
+    err = _rel(x.cpu().numpy().astype(np.complex128), psi)
+    _note(f"[gs] optical lattice prec={prec}: 5 steps rel L2 {err:.3e}, E {E[0]:.6f} -> {E[-1]:.6f}")
+    assert err < gate
+    assert np.all(np.diff(E) <= 1e-6)
