@@ -7,6 +7,8 @@ potential of the step; it is differentiable in psi0 and U.  The forward pass
 keeps psi at the start of every segment of `checkpoint` steps; the backward
 pass reverses the segments last to first, each call of fse_step_adjoint
 recomputing its own forward states from the segment's checkpoint.
+The plan is left with U as its grid potential and its time advanced by
+nsteps dt, as after the same fse_step calls.
 angular_momentum(plan, psi) is <Lz> with the gradient 2 h^d Lz psi.
 
 Gradients follow torch's convention for complex tensors,

@@ -16,6 +16,16 @@
 //   exit:   I0                                                     -> psi
 // ([..] = 3D only.)  The kinetic table carries 1/prod(N_j), the GauSum
 // multiplier 1/prod(2 N_j); every FFT is unnormalised.
+//
+// fse_step_adjoint over a segment of K steps from a checkpoint:
+//   forward  psi1_0 = K(dt/2) psi0; per step: Phi[|psi1_k|^2] (r2c, conv,
+//            C2R), theta_k and psi2 (pointwise), psi1_{k+1} = K(dt) psi2;
+//            psi1_k and theta_k are kept for the whole segment
+//   reverse  g = K(-dt/2) g; per step, last to first: q (pointwise, dL/dU),
+//            Phi[q] (r2c of a real array, conv, C2R), g1 (pointwise),
+//            g = K(-dt) g1 (K(-dt/2) after the first step)
+// where K(tau) is a full kinetic pass: F0, [F1], line(F_last * kin * I_last),
+// [I1], I0.
 #include "../../include/fse.h"
 
 #include <hip/hip_runtime.h>
