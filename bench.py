@@ -91,7 +91,7 @@ def pass_bytes(p, csize):
     }
 
 
-def run_precision(p, prec, steps, warmup, prof_steps):
+def run_precision(p, prec, steps, warmup, prof_steps, tune=True):
     import numpy as np
     import torch
 
@@ -102,6 +102,8 @@ def run_precision(p, prec, steps, warmup, prof_steps):
     dtype = np.complex128 if prec == fse.C128 else np.complex64
     csize = 16 if prec == fse.C128 else 8
     plan = fse.Plan.from_params(p, prec)
+    default_schedule = plan.schedule()["schedule"]
+    sched = plan.tune() if tune else plan.schedule()
     x = torch.from_numpy(psi0.astype(dtype)).to("cuda:0")
     del psi0
     if warmup > 0:
@@ -152,6 +154,8 @@ def run_precision(p, prec, steps, warmup, prof_steps):
         "step_hbm_gbs": step_bytes / t_step / 1e9,
         "step_hbm_frac": step_bytes / t_step / 1e9 / HBM_PEAK_GBS,
         "passes": passes,
+        "schedule": {"default": default_schedule, "used": sched["schedule"], "tuned_ms": sched["tuned_ms"],
+                     "tuned": tune},
     }
 
 
@@ -343,7 +347,7 @@ def adjoint_loss_grad(plan, p, psi0, V, tgt, checkpoint):
     xT = fag.evolve(plan, x0, U, p.steps, p.dt, checkpoint)
     o = vol * torch.sum(torch.conj(t) * xT)
     loss = torch.abs(o) ** 2 + 0.1 * fag.angular_momentum(plan, xT)
-    lv = float(loss)
+    lv = float(loss.detach())
     t1 = time.perf_counter()
     loss.backward()
     torch.cuda.synchronize()
@@ -527,6 +531,8 @@ def main():
     ap.add_argument("--workload", default="dipole3d_256", choices=["dipole3d_256", "dipole3d_128", "plain2d"])
     ap.add_argument("--prof-steps", type=int, default=20)
     ap.add_argument("--no-c64", action="store_true")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="time the default pass schedule instead of the autotuned one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=500, help="steps of the batched sweep (0: skip)")
     ap.add_argument("--gs-steps", type=int, default=2, help="ground-state steps at 256^3 complex64 (0: skip)")
@@ -551,16 +557,16 @@ def main():
     p = W.preset(args.workload)
     print(f"[bench] {p.name} N={p.N} c128: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
           flush=True)
-    r64 = run_precision(p, fse.C128, args.steps, args.warmup, args.prof_steps)
+    r64 = run_precision(p, fse.C128, args.steps, args.warmup, args.prof_steps, args.tune)
     print(f"[bench] c128 {r64['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     variants = {}
     if not args.no_c64:
-        r32 = run_precision(p, fse.C64, args.steps, args.warmup, args.prof_steps)
+        r32 = run_precision(p, fse.C64, args.steps, args.warmup, args.prof_steps, args.tune)
         print(f"[bench] c64 {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         variants["c64"] = {
             "value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "c64 (FP64 reductions)",
             "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
-            "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"],
+            "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"], "schedule": r32["schedule"],
         }
     print("[bench] reductions and H psi", file=sys.stderr, flush=True)
     ops = {"c128": run_ops(p, fse.C128)}
@@ -655,6 +661,7 @@ def main():
         "ground_state": gs,
         "differentiation": adjoint,
         "passes": r64["passes"],
+        "schedule": r64["schedule"],
         "mass_after": r64["mass_after"],
         "kernel_source_hash": kernel_source_hash(),
     }

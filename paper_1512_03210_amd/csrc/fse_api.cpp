@@ -36,7 +36,10 @@
 #include <cstdio>
 #include <cstdint>
 #include <cstring>
+#include <array>
+#include <functional>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -97,6 +100,11 @@ struct fse_plan_s {
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
     const void* U = nullptr;  // optional caller-owned real potential on the grid (fse_set_potential)
     void* adj = nullptr;      // adjoint workspace (fse_step_adjoint), grown on demand
+    // pass schedule: [0] radix variant of the kinetic line transforms, [1] of
+    // the convolution line transforms, [2] kinetic visit order (1 mirrored,
+    // 3D only); defaults set at creation, changed by fse_plan_tune/set_schedule
+    int sched[3] = {0, 0, 0};
+    double tune_ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // ms per step of each schedule, last fse_plan_tune
     size_t adj_bytes = 0;
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
     double* gs_out = nullptr;
@@ -168,8 +176,9 @@ fse_status check_args(int d, const int* N, const double* L, double s, double Ome
             // must be even in each of them: no cross term n_i n_j kappa_i kappa_j.
             const int nz = (n[0] != 0.0) + (n[1] != 0.0) + (three && n[2] != 0.0);
             if (nz > 1)
-                return fail(FSE_ERR_UNSUPPORTED, three ? "the 3D dipole axis must be a coordinate axis"
-                                                       : "the in-plane part of the 2D dipole axis must lie along x or y");
+                return fail(FSE_ERR_UNSUPPORTED, three
+                                                     ? "the 3D dipole axis must be a coordinate axis"
+                                                     : "the in-plane part of the 2D dipole axis must lie along x or y");
             // With rotation the axis seen in the rotating Lagrangian frame turns
             // unless it is the rotation axis z.
             if (Omega != 0.0 && (n[0] != 0.0 || n[1] != 0.0))
@@ -314,9 +323,9 @@ fse::LineIdx kin_index(const fse_plan p) {
         li.F1 = p->N[1];
         li.T1 = p->N[1] / 2 + 1;
         li.T2 = p->N[2] / 2 + 1;
-        // the four lines (+-k0, +-k1) share a table row: visited together in
-        // FP64 (measured faster there; slower for the complex64 table)
-        li.X0 = li.X1 = (p->prec == FSE_C128) ? 1 : 0;
+        // the four lines (+-k0, +-k1) share a table row: visited together when
+        // the schedule says so
+        li.X0 = li.X1 = p->sched[2];
     } else {
         li.D1 = 1;
         li.F0 = p->N[0];
@@ -377,11 +386,12 @@ template <typename R> fse_status conv_passes(fse_plan p, hipStream_t st) {
     if (p->d == 3) {
         const int N1 = p->N[1], N2 = p->N[2];
         HIPCHK(L::strided(N1, false, 1, p->X1, p->X2, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
-        HIPCHK(L::line(N2, 0, p->X2, (p->N[0] + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2], st));
+        HIPCHK(L::line(N2, 0, p->X2, (p->N[0] + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2], st,
+                       p->sched[1]));
         HIPCHK(L::strided(N1, true, 2, p->X2, p->X1, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
     } else {
         const int N1 = p->N[1];
-        HIPCHK(L::line(N1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
+        HIPCHK(L::line(N1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st, p->sched[1]));
     }
     return FSE_OK;
 }
@@ -443,7 +453,7 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
     PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->d == 3)
         PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], nullptr, st));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], nullptr, st, p->sched[0]));
     if (p->d == 3)
         PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     for (int k = 0; k < nsteps; ++k) {
@@ -459,12 +469,13 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                             L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
                     PLAUNCH(p, FSE_PASS_CONV, st,
                             L::line(N2, 0, p->X2, (N0 + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2],
-                                    st));
+                                    st, p->sched[1]));
                     PLAUNCH(p, FSE_PASS_CROP_INV, st,
                             L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
                 } else {
                     PLAUNCH(p, FSE_PASS_CONV, st,
-                            L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st));
+                            L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st,
+                                    p->sched[1]));
                 }
                 PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
                         L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
@@ -475,7 +486,7 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
             void* tab = (j < nw - 1) ? ki_tab : (k == nsteps - 1) ? kh : kf;
             if (p->d == 3)
                 PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
-            PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, tab, ki, p->tw[NL], nullptr, st));
+            PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, tab, ki, p->tw[NL], nullptr, st, p->sched[0]));
             if (p->d == 3)
                 PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
         }
@@ -548,7 +559,7 @@ template <typename R> fse_status kin_full(fse_plan p, const void* src, void* dst
     const int N0 = p->N[0], NL = p->last();
     HIPCHK(L::strided(N0, false, 0, src, dst, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, dst, dst, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
-    HIPCHK(L::line(NL, 1, dst, (int)p->lines_last(), tab, kin_index(p), p->tw[NL], nullptr, st));
+    HIPCHK(L::line(NL, 1, dst, (int)p->lines_last(), tab, kin_index(p), p->tw[NL], nullptr, st, p->sched[0]));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, dst, dst, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
     HIPCHK(L::strided(N0, true, 0, dst, dst, 1, p->C0, p->tw[N0], nullptr, st));
     return FSE_OK;
@@ -630,6 +641,123 @@ template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void
     return FSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner.  Candidates: the radix schedule of the kinetic line transform
+// (plain or alternative), the radix schedule of the convolution line
+// transform, and the kinetic visit order (3D: plain or mirrored).  Every
+// combination is timed on whole steps over the plan's scratch state (the data
+// does not change the work; timing single passes instead misleads where a
+// repeated pass stays in the last-level cache), and another schedule replaces
+// the current one only if it is 2 % faster, so that repeated tuning gives the
+// same schedule.  Choices are cached per device
+// name, architecture, grid, precision and kernel presence for the process, and
+// optionally in a text file of "key<TAB>k c o" lines.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 3>> g_tune_cache;
+
+std::string tune_key(const fse_plan p) {
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s|%s|d%d|%dx%dx%d|%s|%s", prop.name, prop.gcnArchName, p->d, p->N[0], p->N[1],
+             (p->d == 3) ? p->N[2] : 1, p->prec == FSE_C128 ? "c128" : "c64", p->nl ? "conv" : "local");
+    for (char* c = buf; *c; ++c)
+        if (*c == '\t' || *c == '\n') *c = ' ';
+    return std::string(buf);
+}
+
+// Times the candidates fs[c] (each one launch): after two warm-up launches of
+// each, five rounds in which every candidate runs ten launches back to back;
+// ms[c] is the best round's average (rounds interleave the candidates, so
+// slow drifts of clock or temperature affect them alike).
+fse_status time_candidates(const std::vector<std::function<hipError_t()>>& fs, hipStream_t st, double* ms) {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(FSE_ERR_HIP, "hipEventCreate failed");
+    }
+    fse_status s = FSE_OK;
+    for (size_t c = 0; c < fs.size(); ++c) ms[c] = 1e30;
+    for (int round = -1; round < 5 && s == FSE_OK; ++round) {
+        for (size_t c = 0; c < fs.size() && s == FSE_OK; ++c) {
+            const int reps = (round < 0) ? 2 : 10;
+            if (hipEventRecord(e0, st) != hipSuccess) s = fail(FSE_ERR_HIP, "hipEventRecord failed");
+            for (int k = 0; k < reps && s == FSE_OK; ++k) {
+                const hipError_t e = fs[c]();
+                if (e != hipSuccess) s = fail(FSE_ERR_HIP, "tuning launch failed: %s", hipGetErrorString(e));
+            }
+            if (s == FSE_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                s = fail(FSE_ERR_HIP, "event wait failed");
+            float t = 0.0f;
+            if (s == FSE_OK && round >= 0 && hipEventElapsedTime(&t, e0, e1) == hipSuccess)
+                ms[c] = std::min(ms[c], (double)t / reps);
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+bool kin_has_alt(const fse_plan p) { return fse::line_has_alt(p->last()); }
+bool conv_has_alt(const fse_plan p) {
+    const int n = p->last();
+    return p->nl && ((2 * n <= 512) ? fse::line_has_alt(2 * n) : fse::line_has_alt(n));
+}
+
+// Times every schedule the plan allows on whole steps (two TS2 steps on the
+// plan's scratch state, so that each pass meets the caches as in a run) and
+// keeps the fastest; tune_ms[k + 2c + 4o] is the time per step of schedule
+// {k, c, o}.  The plan's time is restored.
+template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
+    fse_status s = ensure_diag(p);
+    if (s != FSE_OK) return s;
+    void* A = p->diag;
+    HIPCHK(hipMemsetAsync(A, 0, (size_t)p->n * p->csize, st));
+    const double dt = std::isnan(p->kin_tau[1]) ? 1e-3 : p->kin_tau[1];
+    const double t_keep = p->t;
+    const bool prof_keep = p->prof;
+    p->prof = false;
+    const int keep[3] = {p->sched[0], p->sched[1], p->sched[2]};
+    for (double& t : p->tune_ms) t = -1.0;
+    std::vector<std::array<int, 3>> cands;
+    for (int o = 0; o < ((p->d == 3) ? 2 : 1); ++o)
+        for (int c = 0; c < (conv_has_alt(p) ? 2 : 1); ++c)
+            for (int k = 0; k < (kin_has_alt(p) ? 2 : 1); ++k) cands.push_back({k, c, o});
+    std::vector<std::function<hipError_t()>> fs;
+    for (const auto& cd : cands)
+        fs.push_back([=]() {
+            for (int q = 0; q < 3; ++q) p->sched[q] = cd[q];
+            return step_impl<R>(p, A, 2, dt, 2, st) == FSE_OK ? hipSuccess : hipErrorLaunchFailure;
+        });
+    std::vector<double> ms(fs.size());
+    s = time_candidates(fs, st, ms.data());
+    p->t = t_keep;
+    p->prof = prof_keep;
+    for (int q = 0; q < 3; ++q) p->sched[q] = keep[q];
+    if (s != FSE_OK) return s;
+    int best = -1;
+    double tbest = 0.0;
+    for (size_t c = 0; c < cands.size(); ++c) {
+        const auto& cd = cands[c];
+        p->tune_ms[cd[0] + 2 * cd[1] + 4 * cd[2]] = 0.5 * ms[c];
+        if (cd[0] == keep[0] && cd[1] == keep[1] && cd[2] == keep[2]) {
+            best = (int)c;
+            tbest = ms[c];
+        }
+    }
+    // keep the current schedule unless another one is 2 % faster
+    for (size_t c = 0; c < cands.size(); ++c)
+        if (ms[c] < 0.98 * tbest) {
+            tbest = ms[c];
+            best = (int)c;
+        }
+    for (int q = 0; q < 3; ++q) p->sched[q] = cands[best][q];
+    return FSE_OK;
+}
+
 // Lab-frame mass, centre of mass and widths: one moment pass, then the
 // rotation x = A(t) x~ applied to the FP64 totals.
 template <typename R> fse_status moments_impl(fse_plan p, const void* psi, double* out, hipStream_t st) {
@@ -664,7 +792,7 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
     const int N0 = p->N[0], NL = p->last();
     HIPCHK(L::strided(N0, false, 0, psi, H, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, H, H, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
-    HIPCHK(L::line(NL, 1, H, (int)p->lines_last(), p->ks, kin_index(p), p->tw[NL], nullptr, st));
+    HIPCHK(L::line(NL, 1, H, (int)p->lines_last(), p->ks, kin_index(p), p->tw[NL], nullptr, st, p->sched[0]));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, H, H, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
     HIPCHK(L::strided(N0, true, 0, H, H, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->Omega != 0.0) {
@@ -726,7 +854,7 @@ template <typename R> fse_status pd_apply(fse_plan p, void* a, hipStream_t st) {
     const int N0 = p->N[0], NL = p->last();
     HIPCHK(L::strided(N0, false, 0, a, a, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, a, a, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
-    HIPCHK(L::line(NL, 1, a, (int)p->lines_last(), p->pd, kin_index(p), p->tw[NL], nullptr, st));
+    HIPCHK(L::line(NL, 1, a, (int)p->lines_last(), p->pd, kin_index(p), p->tw[NL], nullptr, st, p->sched[0]));
     if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, a, a, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
     HIPCHK(L::strided(N0, true, 0, a, a, 1, p->C0, p->tw[N0], nullptr, st));
     return FSE_OK;
@@ -936,6 +1064,9 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
     else p->kernel.kind = FSE_K_NONE;
     p->nl = (p->kernel.kind != FSE_K_NONE) && (lambda != 0.0);
     p->C0 = (int)(p->n / N[0]);
+    // default schedule: plain radix schedules; the mirrored kinetic visit
+    // order in 3D FP64 (measured faster there, slower for the complex64 table)
+    p->sched[2] = (d == 3 && precision == FSE_C128) ? 1 : 0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     auto bail = [&](fse_status e) {
         destroy(p);
@@ -1206,7 +1337,8 @@ fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxi
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite and > 0");
     if (maxit < 1) return fail(FSE_ERR_ARG, "maxit must be >= 1");
     if (plan->U && plan->Omega != 0.0)
-        return fail(FSE_ERR_UNSUPPORTED, "a grid potential set by fse_set_potential needs Omega = 0 in the ground-state step");
+        return fail(FSE_ERR_UNSUPPORTED,
+                    "a grid potential set by fse_set_potential needs Omega = 0 in the ground-state step");
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? gs_step_impl<double>(plan, psi, dt, tol, maxit, stats, st)
                                   : gs_step_impl<float>(plan, psi, dt, tol, maxit, stats, st);
@@ -1234,6 +1366,70 @@ fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* str
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 1, out_dev, st)
                                   : reduce_impl<float>(plan, psi, 1, out_dev, st);
+}
+
+fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::string key = tune_key(plan);
+    if (key.empty()) return fail(FSE_ERR_HIP, "no current device");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it == g_tune_cache.end() && cache_path) {
+        FILE* f = std::fopen(cache_path, "r");
+        if (f) {
+            char line[1024];
+            while (std::fgets(line, sizeof(line), f)) {
+                char* tab = std::strrchr(line, '\t');
+                if (!tab) continue;
+                *tab = '\0';
+                int a = -1, b = -1, c = -1;
+                if (key == line && std::sscanf(tab + 1, "%d %d %d", &a, &b, &c) == 3 && a >= 0 && a <= 1 &&
+                    b >= 0 && b <= 1 && c >= 0 && c <= 1)
+                    g_tune_cache[key] = {a, b, c};
+            }
+            std::fclose(f);
+        }
+        it = g_tune_cache.find(key);
+    }
+    if (it != g_tune_cache.end()) {
+        for (int k = 0; k < 3; ++k) plan->sched[k] = it->second[k];
+        return FSE_OK;
+    }
+    fse_status s = plan->prec == FSE_C128 ? tune_measure<double>(plan, st) : tune_measure<float>(plan, st);
+    if (s != FSE_OK) return s;
+    g_tune_cache[key] = {plan->sched[0], plan->sched[1], plan->sched[2]};
+    if (cache_path) {
+        FILE* f = std::fopen(cache_path, "a");
+        if (!f) return fail(FSE_ERR_ARG, "cannot append to the tuning cache %s", cache_path);
+        std::fprintf(f, "%s\t%d %d %d\n", key.c_str(), plan->sched[0], plan->sched[1], plan->sched[2]);
+        std::fclose(f);
+    }
+    return FSE_OK;
+}
+
+fse_status fse_plan_get_schedule(fse_plan plan, int* sched, double* tuned_ms) {
+    g_err.clear();
+    if (!plan || !sched) return fail(FSE_ERR_ARG, "plan and sched must not be NULL");
+    for (int k = 0; k < 3; ++k) sched[k] = plan->sched[k];
+    if (tuned_ms)
+        for (int k = 0; k < 8; ++k) tuned_ms[k] = plan->tune_ms[k];
+    return FSE_OK;
+}
+
+fse_status fse_plan_set_schedule(fse_plan plan, const int* sched) {
+    g_err.clear();
+    if (!plan || !sched) return fail(FSE_ERR_ARG, "plan and sched must not be NULL");
+    for (int k = 0; k < 3; ++k)
+        if (sched[k] != 0 && sched[k] != 1) return fail(FSE_ERR_ARG, "schedule entries are 0 or 1");
+    if (sched[0] == 1 && !kin_has_alt(plan))
+        return fail(FSE_ERR_UNSUPPORTED, "line length %d has no alternative radix schedule", plan->last());
+    if (sched[1] == 1 && !conv_has_alt(plan))
+        return fail(FSE_ERR_UNSUPPORTED, "the convolution of this plan has no alternative radix schedule");
+    if (sched[2] == 1 && plan->d != 3) return fail(FSE_ERR_UNSUPPORTED, "the mirrored visit order is 3D only");
+    for (int k = 0; k < 3; ++k) plan->sched[k] = sched[k];
+    return FSE_OK;
 }
 
 fse_status fse_set_potential(fse_plan plan, const void* U) {

@@ -62,10 +62,31 @@ constexpr int floor_pow2(int x) {
     return p;
 }
 
-template <typename R, int N, bool CONV> struct LineCfg {
+// Radix schedules of the line transforms: V = 0 the plain one (Radix<M>),
+// V = 1 an alternative for the lengths where one is worth timing (fewer,
+// fuller threads per line, or the reverse); the plan's autotuner picks one
+// per pass.  Lengths without an alternative use the plain schedule for both.
+template <int M> struct AltRadix {
+    static constexpr bool has = false;
+    using L = void;
+};
+template <> struct AltRadix<256> {
+    static constexpr bool has = true;
+    using L = RList<8, 8, 4>;
+};
+template <> struct AltRadix<512> {
+    static constexpr bool has = true;
+    using L = RList<16, 8, 4>;
+};
+template <int M, int V> struct LineFwdOf { using L = FwdPlan<M>; };
+template <int M> struct LineFwdOf<M, 1> { using L = typename AltRadix<M>::L; };
+template <int M, int V> using LineFwd = typename LineFwdOf<M, V>::L;
+template <int M, int V> using LineInv = typename Rev<LineFwd<M, V>>::L;
+
+template <typename R, int N, bool CONV, int V = 0> struct LineCfg {
     using T = typename CT<R>::T;
     static constexpr int P = (sizeof(R) == 8) ? (N + (N >> PadShift<N>::value)) : pitch_lines<N>(N);
-    static constexpr int TPL0 = N / Head<FwdPlan<N>>::value;
+    static constexpr int TPL0 = N / Head<LineFwd<N, V>>::value;
     static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 > 64 ? 64 : TPL0);
     static constexpr int SUB = CONV ? 2 : 1;  // LDS sub-lines (and thread groups) per data line
     static constexpr int BUDGET = 40960 / (P * (int)sizeof(T) * SUB);
@@ -264,16 +285,16 @@ __device__ __forceinline__ long mult_row(int gl, const LineIdx& li) {
     return (long)(k0 * li.T1 + k1) * li.T2;
 }
 
-template <typename R, int N, int MODE>
+template <typename R, int N, int MODE, int V = 0>
 __device__ __forceinline__ void lines_body(
     typename CT<R>::T* data, int nlines, const void* mult, LineIdx li,
     const typename CT<R>::T* twN, const typename CT<R>::T* tw2, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
-    using C = LineCfg<R, N, MODE == 0>;
+    using C = LineCfg<R, N, MODE == 0, V>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB, SUB = C::SUB;
     constexpr bool WS = (64 % (TPL * SUB)) == 0;  // a data line's threads share one wavefront
-    using FF = Fft<T, N, false, TPL, FwdPlan<N>, WS, 2>;
-    using FI = Fft<T, N, true, TPL, InvPlan<N>, WS, 2>;
+    using FF = Fft<T, N, false, TPL, LineFwd<N, V>, WS, 2>;
+    using FI = Fft<T, N, true, TPL, LineInv<N, V>, WS, 2>;
     const int jt = threadIdx.x % TPL;
     const int sl = threadIdx.x / TPL;  // sub-line
     const int dl = sl / SUB, h = sl % SUB;
@@ -283,7 +304,7 @@ __device__ __forceinline__ void lines_body(
     T* line = lds + sl * P;
     T* g = data + (long)gl * N;
     if constexpr (MODE == 3) {
-        using FP = Fft<T, N, true, TPL, FwdPlan<N>, WS, 2>;
+        using FP = Fft<T, N, true, TPL, LineFwd<N, V>, WS, 2>;
         typename FP::In v;
         typename FP::Out u;
         for_pos<N, TPL, FP::R0>(jt, [&](int b, int r, int e) { v[b][r] = g[e]; });
@@ -342,12 +363,13 @@ __device__ __forceinline__ void lines_body(
     }
 }
 
-template <typename R, int N, int MODE>
-__global__ __launch_bounds__((LineCfg<R, N, MODE == 0>::NTH)) void k_lines(
+template <typename R, int N, int MODE, int V = 0>
+__global__ __launch_bounds__((LineCfg<R, N, MODE == 0, V>::NTH)) void k_lines(
     typename CT<R>::T* data, int nlines, const void* mult, LineIdx li,
     const typename CT<R>::T* twN, const typename CT<R>::T* tw2) {
-    __shared__ typename CT<R>::T lds[LineCfg<R, N, (MODE) == 0>::LPB * LineCfg<R, N, (MODE) == 0>::SUB * LineCfg<R, N, (MODE) == 0>::P];
-    lines_body<R, N, MODE>(data, nlines, mult, li, twN, tw2, blockIdx.x, blockIdx.y, lds);
+    using C = LineCfg<R, N, MODE == 0, V>;
+    __shared__ typename CT<R>::T lds[C::LPB * C::SUB * C::P];
+    lines_body<R, N, MODE, V>(data, nlines, mult, li, twN, tw2, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -395,17 +417,17 @@ __global__ __launch_bounds__((LineCfg<R, N, false>::NTH)) void k_lines_deriv(con
 // registers between the forward and the inverse, and only the first N points
 // are stored.
 // ---------------------------------------------------------------------------
-template <typename R, int M>
+template <typename R, int M, int V = 0>
 __device__ __forceinline__ void conv_full_body(
     typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
     const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
-    using C = LineCfg<R, M, false>;
+    using C = LineCfg<R, M, false, V>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
     constexpr int N = M / 2;
     constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
-    using FF = Fft<T, M, false, TPL, FwdPlan<M>, WS, 2>;
-    using FI = Fft<T, M, true, TPL, InvPlan<M>, WS, 2>;
+    using FF = Fft<T, M, false, TPL, LineFwd<M, V>, WS, 2>;
+    using FI = Fft<T, M, true, TPL, LineInv<M, V>, WS, 2>;
     const int jt = threadIdx.x % TPL;
     const int dl = threadIdx.x / TPL;
     const int gv = bx * LPB + dl;
@@ -432,12 +454,12 @@ __device__ __forceinline__ void conv_full_body(
     });
 }
 
-template <typename R, int M>
-__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_full(
+template <typename R, int M, int V = 0>
+__global__ __launch_bounds__((LineCfg<R, M, false, V>::NTH)) void k_conv_full(
     typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
     const typename CT<R>::T* twM) {
-    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LPB * LineCfg<R, M, false>::P];
-    conv_full_body<R, M>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds);
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false, V>::LPB * LineCfg<R, M, false, V>::P];
+    conv_full_body<R, M, V>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,9 +20,10 @@ template <typename R> struct Launch {
     static hipError_t strided(int N, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* twN,
                               const void* tw2N, hipStream_t st);
     // Contiguous line pass on lines of N points; mode 0 padded conv (real multiplier over 2N frequencies),
-    // 1 kinetic (complex table), 2 fwd, 3 inv.
+    // 1 kinetic (complex table), 2 fwd, 3 inv.  var 1 selects the alternative radix schedule (AltRadix) of
+    // the conv and kinetic transforms where the length has one, else the plain schedule is used.
     static hipError_t line(int N, int mode, void* data, int nlines, const void* mult, LineIdx li, const void* twN,
-                           const void* tw2N, hipStream_t st);
+                           const void* tw2N, hipStream_t st, int var = 0);
     // Axis-0 density + padded real-to-complex FFT; src 0 pending state, 1 physical psi, 2 real density.
     static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
                           hipStream_t st);
@@ -83,6 +84,9 @@ hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, 
 hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st);
 
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
+
+// Whether the line transform of length n has an alternative radix schedule (AltRadix).
+bool line_has_alt(int n);
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);

@@ -27,6 +27,18 @@ hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, 
     return hipGetLastError();
 }
 
+bool line_has_alt(int n) {
+    switch (n) {
+#define ALT_CASE(NN) \
+    case NN:         \
+        return AltRadix<NN>::has;
+        FSE_N_SIZES(ALT_CASE)
+#undef ALT_CASE
+        default:
+            return false;
+    }
+}
+
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
     const long g = (n16 + 1023) / 1024;  // 1024 elements per workgroup
     if (g > 0x7fffffffL) return hipErrorInvalidValue;

@@ -26,7 +26,8 @@ KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_
 
 EXPORTS = [
     "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
-    "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_set_potential", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
+    "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_plan_tune", "fse_plan_get_schedule", "fse_plan_set_schedule",
+    "fse_set_potential", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
@@ -81,6 +82,9 @@ def lib():
         "fse_step": (st, [vp, vp, i, d, vp]),
         "fse_step4": (st, [vp, vp, i, d, vp]),
         "fse_set_potential": (st, [vp, vp]),
+        "fse_plan_tune": (st, [vp, ctypes.c_char_p, vp]),
+        "fse_plan_get_schedule": (st, [vp, ip, dp]),
+        "fse_plan_set_schedule": (st, [vp, ip]),
         "fse_step_adjoint": (st, [vp, vp, i, d, vp, vp, vp]),
         "fse_apply_Lz": (st, [vp, vp, vp, vp]),
         "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
@@ -216,6 +220,22 @@ class Plan:
     def _check_real(self, a, what):
         if a.dtype != self.rdtype or tuple(a.shape) != self.N or not a.is_contiguous() or not a.is_cuda:
             raise ValueError(f"{what} must be a contiguous {self.rdtype} device tensor of shape {self.N}")
+
+    def tune(self, cache_path: Optional[str] = None, stream=None) -> dict:
+        """Time the plan's schedule alternatives and keep the fastest (fse_plan_tune)."""
+        _check(lib().fse_plan_tune(self._h, None if cache_path is None else cache_path.encode(), _stream(stream)))
+        return self.schedule()
+
+    def schedule(self) -> dict:
+        """{"schedule": [kinetic radix, convolution radix, kinetic order],
+        "tuned_ms": ms per step of schedule {k, c, o} at index k + 2c + 4o (-1: not timed)}"""
+        sc = (ctypes.c_int * 3)()
+        ms = (ctypes.c_double * 8)()
+        _check(lib().fse_plan_get_schedule(self._h, sc, ms))
+        return {"schedule": [int(x) for x in sc], "tuned_ms": [float(x) for x in ms]}
+
+    def set_schedule(self, sched):
+        _check(lib().fse_plan_set_schedule(self._h, _iarr(sched)))
 
     def set_potential(self, U=None):
         """Grid potential U(x~) added to the step's phase and the energy (fse_set_potential);
