@@ -39,7 +39,7 @@ def _vol(N, L):
 
 def _theta(prob, psi1, t, dt):
     rho = np.abs(psi1) ** 2
-    th = dt * prob.beta * rho + prob.lam * dt * prob.potential(rho)
+    th = dt * prob.beta * rho + prob.lam * dt * prob.potential(rho, t, dt)
     th = th + trap_integral(prob.N, prob.L, prob.gamma, prob.Omega, t, dt)
     if prob.U is not None:
         th = th + dt * prob.U
@@ -54,7 +54,7 @@ def step_adjoint(prob, psi, t, dt, g_next):
     psi2 = psi1 * np.exp(-1j * th)
     g2 = kinetic(g_next, N, L, s, -0.5 * dt, m)
     q = np.imag(np.conj(g2) * psi2)
-    r = dt * prob.beta * q + prob.lam * dt * prob.potential(q)
+    r = dt * prob.beta * q + prob.lam * dt * prob.potential(q, t, dt)
     g1 = g2 * np.exp(1j * th) + 2.0 * r * psi1
     return kinetic(g1, N, L, s, -0.5 * dt, m), dt * q
 

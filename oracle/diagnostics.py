@@ -74,7 +74,7 @@ def energy_parts(prob, psi, t=0.0):
         W = W + prob.U
     epot = vol * float(np.sum(W * rho))
     eint = 0.5 * prob.beta * vol * float(np.sum(rho ** 2))
-    enon = 0.5 * prob.lam * vol * float(np.sum(prob.potential(rho) * rho))
+    enon = 0.5 * prob.lam * vol * float(np.sum(prob.potential(rho, t) * rho))
     erot = -prob.Omega * angular_momentum(psi, N, L)
     return ekin, epot, eint, enon, erot, ekin + epot + eint + enon + erot
 

@@ -22,6 +22,18 @@ the readings below, which the paper leaves open:
   truncated 1/(4 pi |x|) kernel.  This is the kernel's own symbol in eq.
   Kernel; the displayed reformulation at the end of Section 2 carries a sign
   and factor slip.
+* Dipole axes with off-diagonal products n_i n_j (a tilted axis, or any
+  axis that turns in the rotating frame): the multiplier is c0 + Khat_C
+  kappa^T M kappa with a symmetric M; its odd terms kappa_i kappa_j (i != j)
+  are taken as zero at Nyquist indices, where kappa and -kappa share an
+  index, so that the multiplier stays even under kappa -> -kappa on the grid
+  and the potential of a real density is real.
+* An axis that turns in the rotating Lagrangian coordinates, m(t) = A^{-1}(t) n
+  (eq. Kernel_Rot), enters a nonlinear sub-step over [t, t+tau] through the
+  time average M = (1/tau) int m m^T ds (the sub-step integrates the
+  potential over time with the density frozen); in closed form each
+  harmonic cos/sin(a + b s) averages to its value at the midpoint times
+  sinc(b tau / 2).
 * 2D dipole along n = (n_perp, n3): Phi = -(3/2)(d_{n_perp n_perp} - n3^2
   Lap_perp)(1/(2 pi |x|)) * rho (eq. Kernel), i.e. the multiplier
   (3/2)[(n_perp.kappa)^2 - n3^2 |kappa|^2] Khat_C with Khat_C the symbol of
@@ -160,22 +172,72 @@ def coulomb_symbol(N, L, mu=1.0, c=1.0, delta=None, ht=0.14, g_method="auto"):
     return K + C0 - C2 * k2
 
 
+def dipole_average(axis, Omega=0.0, t=0.0, tau=0.0):
+    """M = (1/tau) int_t^{t+tau} m(s) m(s)^T ds with m(s) = A(s)^{-1} n (eq. Kernel_Rot);
+    tau = 0 gives m(t) m(t)^T.  A(s) turns (x, y) by the angle Omega s, so A^{-1} n
+    is n_perp turned by +Omega s and n3 unchanged."""
+    n1, n2, n3 = (float(a) for a in axis)
+    r = math.hypot(n1, n2)
+    phi0 = math.atan2(n2, n1) if r > 0.0 else 0.0
+
+    def sinc(x):
+        return 1.0 if x == 0.0 else math.sin(x) / x
+
+    def avg_cos(k):  # mean of cos(k (phi0 + Omega s)) over [t, t + tau]
+        return math.cos(k * (phi0 + Omega * (t + 0.5 * tau))) * sinc(0.5 * k * Omega * tau)
+
+    def avg_sin(k):
+        return math.sin(k * (phi0 + Omega * (t + 0.5 * tau))) * sinc(0.5 * k * Omega * tau)
+    M = np.zeros((3, 3))
+    M[0, 0] = r * r * (0.5 + 0.5 * avg_cos(2))
+    M[1, 1] = r * r * (0.5 - 0.5 * avg_cos(2))
+    M[0, 1] = M[1, 0] = r * r * 0.5 * avg_sin(2)
+    M[0, 2] = M[2, 0] = n3 * r * avg_cos(1)
+    M[1, 2] = M[2, 1] = n3 * r * avg_sin(1)
+    M[2, 2] = n3 * n3
+    return M
+
+
+def dipole_form_symbol(N, L, kernel, M, delta=None, ht=0.14, KC=None):
+    """Dipolar multiplier for an axis second-moment matrix M (M = n n^T for a fixed axis):
+    3D  -1 + 3 Khat_C kappa^T M kappa,                 Khat_C for 1/(4 pi |x|);
+    2D  (3/2) Khat_C (kappa^T M_perp kappa - M_33 |kappa|^2),  Khat_C for 1/(2 pi |x|).
+    Odd terms (i != j) use kappa = 0 at Nyquist indices."""
+    d = len(N)
+    if KC is None:
+        KC = coulomb_symbol(N, L, mu=1.0, c=1.0 / ((4.0 if d == 3 else 2.0) * math.pi), delta=delta, ht=ht)
+    kap = padded_frequencies(N, L)
+    kx = []
+    for j in range(d):
+        k = kap[j].copy()
+        k[int(N[j])] = 0.0  # the Nyquist index of the 2N_j-point padded axis
+        kx.append(k)
+
+    def b(v, j):
+        shape = [1] * d
+        shape[j] = -1
+        return v.reshape(shape)
+    Q = np.zeros(KC.shape)
+    for i in range(d):
+        Q = Q + M[i, i] * b(kap[i], i) ** 2
+        for j in range(i + 1, d):
+            Q = Q + 2.0 * M[i, j] * b(kx[i], i) * b(kx[j], j)
+    if d == 3:
+        return -1.0 + 3.0 * KC * Q
+    k2 = sum(b(kap[i], i) ** 2 for i in range(2))
+    return 1.5 * KC * (Q - M[2, 2] * k2)
+
+
 def ddi3_symbol(N, L, delta=None, ht=0.14, axis=(0.0, 0.0, 1.0)):
     """3D dipolar multiplier -1 + 3 (n.kappa)^2 Khat_C, Khat_C for 1/(4 pi |x|)."""
-    KC = coulomb_symbol(N, L, mu=1.0, c=1.0 / (4.0 * math.pi), delta=delta, ht=ht)
-    kap = padded_frequencies(N, L)
-    nk = (axis[0] * kap[0][:, None, None] + axis[1] * kap[1][None, :, None]
-          + axis[2] * kap[2][None, None, :])
-    return -1.0 + 3.0 * nk ** 2 * KC
+    n = np.asarray(axis, dtype=np.float64)
+    return dipole_form_symbol(N, L, "ddi3", np.outer(n, n), delta=delta, ht=ht)
 
 
 def ddi2_symbol(N, L, delta=None, ht=0.14, axis=(0.0, 0.0, 1.0)):
     """2D dipolar multiplier (3/2)[(n_perp.kappa)^2 - n3^2 |kappa|^2] Khat_C, Khat_C for 1/(2 pi |x|)."""
-    KC = coulomb_symbol(N, L, mu=1.0, c=1.0 / (2.0 * math.pi), delta=delta, ht=ht)
-    kap = padded_frequencies(N, L)
-    k0, k1 = kap[0][:, None], kap[1][None, :]
-    nk = axis[0] * k0 + axis[1] * k1
-    return 1.5 * (nk ** 2 - axis[2] ** 2 * (k0 ** 2 + k1 ** 2)) * KC
+    n = np.asarray(axis, dtype=np.float64)
+    return dipole_form_symbol(N, L, "ddi2", np.outer(n, n), delta=delta, ht=ht)
 
 
 def symbol(N, L, kernel, mu=1.0, c=1.0, delta=None, axis=(0.0, 0.0, 1.0)):

@@ -10,8 +10,10 @@ Oracle (test infrastructure only).  Follows Section 4.2 of the paper:
   by exp(-i tau (|mu|^2 + m^2)^s / 2).
 * Nonlinear sub-step (eqs. 2stepA/B): the density is constant in time, so
   the solution is phi * exp(-i[tau beta rho + lam * K~ * rho + P]) with
-  K~ = tau * U for a Coulomb kernel or a dipole along z (the rotating axis
-  m(t) = A^{-1} n equals n then; any fixed axis without rotation), and P = int V(A(s) x~) ds (eq. int_poten).
+  K~ = int U ds: tau * U for a Coulomb kernel, a dipole along z (the
+  rotating axis m(t) = A^{-1} n equals n then) or any axis without
+  rotation; for an axis that turns, the multiplier with the time average of
+  m m^T over the sub-step (eq. Kernel_Rot), and P = int V(A(s) x~) ds (eq. int_poten).
 * TS2-GauSum (eqs. tssp1-tssp3): half linear step, full nonlinear step,
   half linear step.
 * Fourth order: the paper notes that TS2 extends to higher-order splitting
@@ -40,8 +42,8 @@ Readings of the paper's text:
 
 Parity: pinned by the exact free-evolution identity, the s = 1 free Gaussian
 closed form, quadrature of P, unitarity (mass), reversibility, second-order
-convergence, the s = 1 centre-of-mass ODE and conservation of <Lz>
-(tests/oracle).
+convergence, the s = 1 centre-of-mass ODE and conservation of <Lz>, and for a turning dipole axis the
+second-order conservation of the rotating-frame energy (tests/oracle).
 """
 from __future__ import annotations
 
@@ -130,11 +132,12 @@ class Problem:
         # optional real potential U(x~) on the computational grid, added to the
         # nonlinear phase as dt * U (static in the rotating Lagrangian coordinates)
         self.U = None
-        if kernel in ("ddi2", "ddi3") and self.Omega != 0.0 and (self.axis[0] != 0.0 or self.axis[1] != 0.0):
-            # in the rotating Lagrangian frame the axis m(t) = A^{-1}(t) n turns
-            # unless n is the rotation axis (eq. Kernel_Rot)
-            raise NotImplementedError("a rotating dipole axis m(t) is not implemented")
+        # in the rotating Lagrangian coordinates the dipole axis m(t) = A^{-1}(t) n
+        # turns unless n is the rotation axis (eq. Kernel_Rot)
+        self.turning_axis = (kernel in ("ddi2", "ddi3") and self.Omega != 0.0
+                             and (self.axis[0] != 0.0 or self.axis[1] != 0.0))
         self._K = None
+        self._KC = None
 
     @classmethod
     def from_params(cls, p):
@@ -152,16 +155,28 @@ class Problem:
                                     delta=self.delta, axis=self.axis)
         return self._K
 
-    def potential(self, rho):
-        """Untimed nonlocal potential Phi[rho] = U * rho (zero if there is no kernel)."""
+    def K_at(self, t=0.0, tau=0.0):
+        """Multiplier of the rotating-frame kernel over [t, t+tau] (its time average;
+        tau = 0: at the instant t).  Equal to K unless the dipole axis turns."""
+        if not self.turning_axis:
+            return self.K
+        if self._KC is None:
+            c = 1.0 / ((4.0 if self.d == 3 else 2.0) * math.pi)
+            self._KC = gausum.coulomb_symbol(self.N, self.L, mu=1.0, c=c, delta=self.delta)
+        M = gausum.dipole_average(self.axis, self.Omega, t, tau)
+        return gausum.dipole_form_symbol(self.N, self.L, self.kernel, M, KC=self._KC)
+
+    def potential(self, rho, t=0.0, tau=0.0):
+        """Nonlocal potential Phi[rho] = U * rho (zero if there is no kernel), in the rotating
+        coordinates at time t (averaged over [t, t+tau]); t = 0 is also the frame of H psi."""
         if self.kernel == "none" or self.lam == 0.0:
             return np.zeros(self.N)
-        return gausum.convolve(rho, self.K)
+        return gausum.convolve(rho, self.K_at(t, tau))
 
     def nonlinear(self, phi, t, tau):
         """Nonlinear sub-step over [t, t+tau] (eqs. 2stepA, 2stepB, solu_step2)."""
         rho = np.abs(phi) ** 2
-        theta = tau * self.beta * rho + self.lam * tau * self.potential(rho)
+        theta = tau * self.beta * rho + self.lam * tau * self.potential(rho, t, tau)
         theta = theta + trap_integral(self.N, self.L, self.gamma, self.Omega, t, tau)
         if self.U is not None:
             theta = theta + tau * self.U

@@ -244,3 +244,41 @@ def test_near_field_constants_against_direct_radial_quadrature():
     assert abs(C0 - Sd * i0) < 1e-9 * abs(C0)
     assert abs(C2 - Sd * i2 / (2 * d)) < 1e-8 * abs(C2)
     assert C0 > 1e-6  # the zeroth-order term is far above round-off: it cannot be dropped
+
+
+@pytest.mark.parametrize("t,tau", [(0.3, 0.05), (1.7, -0.08), (0.0, 0.0), (2.0, 1.3)])
+def test_dipole_time_average_by_quadrature(t, tau):
+    # M = (1/tau) int m m^T ds with m(s) = A(s)^{-1} n, against Gauss-Legendre in s
+    n = np.array([0.48, -0.36, 0.8])
+    Om = 0.7
+    M = gausum.dipole_average(n, Om, t, tau)
+
+    def m(s):
+        c, si = math.cos(Om * s), math.sin(Om * s)
+        A = np.array([[c, si, 0.0], [-si, c, 0.0], [0.0, 0.0, 1.0]])
+        return np.linalg.solve(A, n)
+    if tau == 0.0:
+        ref = np.outer(m(t), m(t))
+    else:
+        x, w = np.polynomial.legendre.leggauss(40)
+        ss = t + 0.5 * tau * (x + 1.0)
+        ref = sum(wi * np.outer(m(si), m(si)) for wi, si in zip(w, ss)) * 0.5
+    assert np.max(np.abs(M - ref)) < 1e-14
+    assert abs(np.trace(M) - 1.0) < 1e-14
+
+
+def test_tilted_dipole_symbol_is_even_and_matches_its_axis_products():
+    # a tilted axis: multiplier even under kappa -> -kappa on the padded grid
+    # (odd products vanish at Nyquist indices) and, away from them, equal to
+    # -1 + 3 (n.kappa)^2 Khat_C
+    N, L = (16, 12, 10), (4.0, 3.0, 3.0)
+    n = np.array([0.48, -0.36, 0.8])
+    K = gausum.ddi3_symbol(N, L, axis=tuple(n))
+    neg = K[np.ix_(*[(-np.arange(2 * m)) % (2 * m) for m in N])]
+    assert np.max(np.abs(K - neg)) == 0.0
+    KC = gausum.coulomb_symbol(N, L, mu=1.0, c=1.0 / (4.0 * math.pi))
+    kap = gausum.padded_frequencies(N, L)
+    nk = n[0] * kap[0][:, None, None] + n[1] * kap[1][None, :, None] + n[2] * kap[2][None, None, :]
+    full = -1.0 + 3.0 * nk ** 2 * KC
+    inner = np.ix_(*[np.r_[0:m, m + 1:2 * m] for m in N])
+    assert np.max(np.abs(K[inner] - full[inner])) < 1e-13 * np.max(np.abs(full))

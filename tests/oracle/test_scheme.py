@@ -237,3 +237,31 @@ def test_fourth_order_free_evolution_is_exact():
     p, _ = pr.run4(psi0, 5, 0.03)
     q = scheme.kinetic(psi0, N, L, 0.7, 0.15)
     assert np.linalg.norm(p - q) / np.linalg.norm(q) < 1e-13
+
+
+def _turning_dipole_drift(sign, nsteps):
+    # 3D dipole along a tilted axis with rotation: in the rotating Lagrangian
+    # coordinates the axis turns, m(t) = A^{-1}(t) n; the rotating-frame energy
+    # (its instantaneous kernel at time t) is conserved by the equation.
+    from oracle import gausum
+    orig = gausum.dipole_average
+    gausum.dipole_average = lambda axis, Omega=0.0, t=0.0, tau=0.0: orig(axis, sign * Omega, t, tau)
+    try:
+        N, L = (24, 24, 24), (5.0, 5.0, 5.0)
+        pr = scheme.Problem(3, N, L, 0.9, 0.5, (1.0, 1.0, 1.2), 20.0, 20.0, kernel="ddi3", axis=(0.6, 0.0, 0.8))
+        X = np.meshgrid(*scheme.axes(N, L), indexing="ij")
+        psi = W.normalize(np.exp(-X[0] ** 2 / 1.2 - X[1] ** 2 / 0.7 - X[2] ** 2) * (1 + 0.2 * X[0] + 0.3j * X[1]),
+                          pr.h)
+        E0 = dg.energy_parts(pr, psi, 0.0)[5]
+        psi, t = pr.run(psi, nsteps, 1.0 / nsteps)
+        return dg.energy_parts(pr, psi, t)[5] - E0
+    finally:
+        gausum.dipole_average = orig
+
+
+def test_turning_dipole_axis_conserves_the_rotating_frame_energy():
+    # second-order drift (2.6e-3, 6.6e-4 over t = 1 at 50, 100 steps); the axis
+    # turned the wrong way (m = A n) drifts by 1.7e-2 and does not converge
+    d50, d100 = _turning_dipole_drift(1, 50), _turning_dipole_drift(1, 100)
+    assert abs(d100) < 1e-3 and 3.5 < d50 / d100 < 4.5
+    assert abs(_turning_dipole_drift(-1, 100)) > 10 * abs(d100)
