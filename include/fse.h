@@ -67,11 +67,15 @@ typedef enum { FSE_C128 = 0, FSE_C64 = 1 } fse_precision;
  *   FSE_K_DDI2    -- d = 2 dipole-dipole kernel
  *                    -(3/2)(d_{n_perp n_perp} - n3^2 Lap_perp)(1/(2 pi |x|)),
  *                    n = (n_perp, n3) a unit vector.
- * The multiplier is stored for non-negative frequencies, so it must be even
- * in each: a 3D axis is a coordinate axis, a 2D axis has n_perp along x or y
- * (any n3); otherwise FSE_ERR_UNSUPPORTED.  With Omega != 0 the axis must be
- * (0, 0, +-1): any other axis turns in the rotating Lagrangian frame
- * (eq. Kernel_Rot), which is not implemented. */
+ * Any unit axis.  A coordinate axis (3D), or an in-plane part along x or y
+ * (2D), gives a multiplier even in every frequency, stored whole.  A tilted
+ * axis (products n_i n_j in the symbol), or with Omega != 0 any axis off z,
+ * which turns in the rotating Lagrangian coordinates as m(t) = A^{-1}(t) n
+ * (eq. Kernel_Rot), is applied as c0 + Khat_C kappa^T M kappa inside the
+ * padded convolution, M the time average of m m^T over each nonlinear
+ * sub-step (M = n n^T for H psi and the ground state, whose frame has the
+ * axis n); its odd products are zero at Nyquist indices.  Such an axis needs
+ * the contiguous axis N[d-1] <= 256 and is not taken by the batch. */
 typedef enum { FSE_K_NONE = 0, FSE_K_COULOMB = 1, FSE_K_DDI3 = 2, FSE_K_DDI2 = 3 } fse_kernel_kind;
 
 typedef struct {
@@ -255,12 +259,14 @@ fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxi
  * non-negative frequency octant, out[(k0*(N1+1)+k1)*(N2+1)+k2] for d = 3
  * (out[k0*(N1+1)+k1] for d = 2), kappa_j = pi k_j / (2 L_j), k_j = 0..N_j.
  * The caller owns `out` (host memory, prod(N_j+1) doubles).  This is the
- * table the plan uploads; it needs no GPU. */
+ * table the plan uploads; it needs no GPU.  A tilted dipole axis has no such
+ * table (its multiplier is not even in each frequency): FSE_ERR_UNSUPPORTED. */
 fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fse_kernel* kernel,
                                   double* out);
 
 /* Copies the plan's multiplier (as fse_gausum_symbol_host lays it out) to
- * host memory.  FSE_ERR_STATE if the plan has no kernel. */
+ * host memory; for a tilted or turning dipole axis, its Coulomb part Khat_C.
+ * FSE_ERR_STATE if the plan has no kernel. */
 fse_status fse_get_symbol(fse_plan plan, double* host_out);
 
 /* ---------------------------------------------------------------------------

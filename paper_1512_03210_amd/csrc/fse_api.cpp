@@ -104,6 +104,10 @@ struct fse_plan_s {
     // the convolution line transforms, [2] kinetic visit order (1 mirrored,
     // 3D only); defaults set at creation, changed by fse_plan_tune/set_schedule
     int sched[3] = {0, 0, 0};
+    // dipole with products n_i n_j or an axis that turns in the rotating frame:
+    // khat holds the Coulomb-part symbol and each convolution gets a QForm
+    bool qf = false;
+    double khat_scale = 1.0;  // 1 / prod(2 N_j), carried by khat
     double tune_ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // ms per step of each schedule, last fse_plan_tune
     size_t adj_bytes = 0;
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
@@ -140,6 +144,17 @@ fse_status dev_alloc(fse_plan p, void** ptr, size_t bytes) {
     return FSE_OK;
 }
 
+// Whether a dipolar kernel needs the quadratic-form multiplier: an axis with a
+// product n_i n_j that enters the symbol (its multiplier is not even in each
+// frequency alone), or an axis that turns in the rotating frame (Omega != 0,
+// n_perp != 0).
+bool dipole_needs_form(const fse_kernel* k, double Omega) {
+    if (!k || (k->kind != FSE_K_DDI3 && k->kind != FSE_K_DDI2)) return false;
+    const double* n = k->n;
+    const int nz = (n[0] != 0.0) + (n[1] != 0.0) + (k->kind == FSE_K_DDI3 && n[2] != 0.0);
+    return nz > 1 || (Omega != 0.0 && (n[0] != 0.0 || n[1] != 0.0));
+}
+
 fse_status check_args(int d, const int* N, const double* L, double s, double Omega, const double* gamma, double beta,
                       double lambda, const fse_kernel* kernel, int precision) {
     if (d != 2 && d != 3) return fail(FSE_ERR_ARG, "d must be 2 or 3 (got %d)", d);
@@ -172,17 +187,11 @@ fse_status check_args(int d, const int* N, const double* L, double s, double Ome
                 return fail(FSE_ERR_ARG, "dipole axis must be finite");
             const double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
             if (std::fabs(nn - 1.0) > 1e-12) return fail(FSE_ERR_ARG, "dipole axis must be a unit vector");
-            // The multiplier is stored for non-negative frequencies only, so it
-            // must be even in each of them: no cross term n_i n_j kappa_i kappa_j.
-            const int nz = (n[0] != 0.0) + (n[1] != 0.0) + (three && n[2] != 0.0);
-            if (nz > 1)
-                return fail(FSE_ERR_UNSUPPORTED, three
-                                                     ? "the 3D dipole axis must be a coordinate axis"
-                                                     : "the in-plane part of the 2D dipole axis must lie along x or y");
-            // With rotation the axis seen in the rotating Lagrangian frame turns
-            // unless it is the rotation axis z.
-            if (Omega != 0.0 && (n[0] != 0.0 || n[1] != 0.0))
-                return fail(FSE_ERR_UNSUPPORTED, "with Omega != 0 the dipole axis must be (0, 0, +-1)");
+            // A tilted or turning axis applies its quadratic form inside the
+            // one-pass padded convolution, which needs a padded length 2N <= 512.
+            if (dipole_needs_form(kernel, Omega) && 2 * N[d - 1] > 512)
+                return fail(FSE_ERR_UNSUPPORTED,
+                            "a tilted or turning dipole axis needs N[%d] <= 256 (padded convolution in one pass)", d - 1);
         } else if (kernel->kind != FSE_K_NONE) {
             return fail(FSE_ERR_ARG, "unknown kernel kind %d", kernel->kind);
         }
@@ -380,24 +389,80 @@ fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
     return a;
 }
 
+// The dipolar multiplier of a qf plan over [t, t+tau] in the rotating
+// Lagrangian coordinates (tau = 0: at the instant t; t = 0 is also the frame of
+// H psi and of the ground state, where the axis is n): the axis
+// m(s) = A(s)^{-1} n is n_perp turned by +Omega s, and the time average of
+// m m^T has, for each harmonic cos/sin(a + b s), its midpoint value times
+// sinc(b tau / 2) (eq. Kernel_Rot).
+fse::QForm qform(const fse_plan p, double t, double tau) {
+    const double* n = p->kernel.n;
+    const double r = std::hypot(n[0], n[1]);
+    const double phi0 = (r > 0.0) ? std::atan2(n[1], n[0]) : 0.0;
+    const double W = p->Omega;
+    auto sinc = [](double x) { return (x == 0.0) ? 1.0 : std::sin(x) / x; };
+    auto mc = [&](double k) { return std::cos(k * (phi0 + W * (t + 0.5 * tau))) * sinc(0.5 * k * W * tau); };
+    auto ms = [&](double k) { return std::sin(k * (phi0 + W * (t + 0.5 * tau))) * sinc(0.5 * k * W * tau); };
+    const double M00 = r * r * (0.5 + 0.5 * mc(2.0)), M11 = r * r * (0.5 - 0.5 * mc(2.0));
+    const double M01 = r * r * 0.5 * ms(2.0), M02 = n[2] * r * mc(1.0), M12 = n[2] * r * ms(1.0);
+    const double M22 = n[2] * n[2];
+    fse::QForm q{};
+    q.dk0 = kPi / (2.0 * p->L[0]);
+    q.n0 = p->N[0];
+    if (p->d == 3) {
+        // -1 + 3 Khat_C kappa^T M kappa; the line axis is axis 2
+        q.dk1 = kPi / (2.0 * p->L[1]);
+        q.dk2 = kPi / (2.0 * p->L[2]);
+        q.n1 = p->N[1];
+        q.c0 = -p->khat_scale;
+        q.m00 = 3.0 * M00;
+        q.m11 = 3.0 * M11;
+        q.m22 = 3.0 * M22;
+        q.m01 = 3.0 * M01;
+        q.m02 = 3.0 * M02;
+        q.m12 = 3.0 * M12;
+    } else {
+        // (3/2) Khat_C (kappa^T M_perp kappa - M22 |kappa|^2); the line axis is axis 1
+        q.dk1 = 0.0;
+        q.dk2 = kPi / (2.0 * p->L[1]);
+        q.n1 = 0;
+        q.c0 = 0.0;
+        q.m00 = 1.5 * (M00 - M22);
+        q.m22 = 1.5 * (M11 - M22);
+        q.m02 = 1.5 * M01;
+    }
+    return q;
+}
+
+// Padded convolution along the contiguous axis with the plan's multiplier; a
+// qf plan uses the quadratic form over [t, t+tau].
+template <typename R> hipError_t conv_line(fse_plan p, double t, double tau, hipStream_t st) {
+    using L = fse::Launch<R>;
+    const int NL = p->last();
+    void* X = (p->d == 3) ? p->X2 : p->X1;
+    const int nl = (p->d == 3) ? (p->N[0] + 1) * 2 * p->N[1] : p->N[0] + 1;
+    if (p->qf) return L::conv_qf(NL, X, nl, p->khat, conv_index(p), p->tw[2 * NL], qform(p, t, tau), st);
+    return L::line(NL, 0, X, nl, p->khat, conv_index(p), p->tw[NL], p->tw[2 * NL], st, p->sched[1]);
+}
+
 // Zero-padded GauSum convolution of the density held in X1 (after r2c), result back in X1.
-template <typename R> fse_status conv_passes(fse_plan p, hipStream_t st) {
+template <typename R> fse_status conv_passes(fse_plan p, double t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     if (p->d == 3) {
         const int N1 = p->N[1], N2 = p->N[2];
         HIPCHK(L::strided(N1, false, 1, p->X1, p->X2, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
-        HIPCHK(L::line(N2, 0, p->X2, (p->N[0] + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2], st,
-                       p->sched[1]));
+        HIPCHK(conv_line<R>(p, t, tau, st));
         HIPCHK(L::strided(N1, true, 2, p->X2, p->X1, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
     } else {
-        const int N1 = p->N[1];
-        HIPCHK(L::line(N1, 0, p->X1, p->N[0] + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st, p->sched[1]));
+        HIPCHK(conv_line<R>(p, t, tau, st));
     }
     return FSE_OK;
 }
 
 // Phi[rho] into a real array; src 1: rho = |psi|^2, 2: rho given.
-template <typename R> fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, hipStream_t st) {
+// (t, tau: the time and averaging interval of a turning dipole axis, see qform)
+template <typename R>
+fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, double t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     if (!p->nl) {
         HIPCHK(hipMemsetAsync(Phi, 0, (size_t)p->n * p->rsize, st));
@@ -405,7 +470,7 @@ template <typename R> fse_status potential_impl(fse_plan p, const void* src, int
     }
     const int N0 = p->N[0];
     HIPCHK(L::r2c(N0, srckind, src, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
-    fse_status s = conv_passes<R>(p, st);
+    fse_status s = conv_passes<R>(p, t, tau, st);
     if (s != FSE_OK) return s;
     fse::PhaseArgs pa = phase_args(p, p->t, 0.0);
     HIPCHK(L::c2r_phase(N0, 2, p->X1, nullptr, Phi, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
@@ -467,15 +532,11 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                 if (p->d == 3) {
                     PLAUNCH(p, FSE_PASS_PAD_FWD, st,
                             L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
-                    PLAUNCH(p, FSE_PASS_CONV, st,
-                            L::line(N2, 0, p->X2, (N0 + 1) * 2 * N1, p->khat, conv_index(p), p->tw[N2], p->tw[2 * N2],
-                                    st, p->sched[1]));
+                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, tj - tau, tau, st));
                     PLAUNCH(p, FSE_PASS_CROP_INV, st,
                             L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
                 } else {
-                    PLAUNCH(p, FSE_PASS_CONV, st,
-                            L::line(N1, 0, p->X1, N0 + 1, p->khat, conv_index(p), p->tw[N1], p->tw[2 * N1], st,
-                                    p->sched[1]));
+                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, tj - tau, tau, st));
                 }
                 PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
                         L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
@@ -519,7 +580,7 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     if (kind == 1) {
         const bool use_phi = p->nl;
         if (use_phi) {
-            s = potential_impl<R>(p, psi, 1, Phi, st);
+            s = potential_impl<R>(p, psi, 1, Phi, p->t, 0.0, st);
             if (s != FSE_OK) return s;
         }
         const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
@@ -609,7 +670,7 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     // forward: psi1 and theta of every step
     if ((s = kin_full<R>(p, psi0, S(0), kp_h, st)) != FSE_OK) return s;
     for (int k = 0; k < nsteps; ++k) {
-        if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, st)) != FSE_OK) return s;
+        if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, p->t + k * dt, dt, st)) != FSE_OK) return s;
         const fse::PhaseArgs pa = phase_args(p, p->t + k * dt, dt);
         void* next = (k + 1 < nsteps) ? S(k + 1) : nullptr;
         HIPCHK(L::adj_theta(S(k), p->nl ? Phi : nullptr, p->U, TH(k), next, p->n, gg, pa, st));
@@ -619,7 +680,7 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     if ((s = kin_full<R>(p, g, g, km_h, st)) != FSE_OK) return s;
     for (int k = nsteps - 1; k >= 0; --k) {
         HIPCHK(L::adj_q(g, S(k), TH(k), q, gU, p->n, dt, st));
-        if (p->nl && (s = potential_impl<R>(p, q, 2, Phi, st)) != FSE_OK) return s;
+        if (p->nl && (s = potential_impl<R>(p, q, 2, Phi, p->t + k * dt, dt, st)) != FSE_OK) return s;
         HIPCHK(L::adj_g1(g, S(k), TH(k), q, p->nl ? Phi : nullptr, p->n, p->beta * dt, p->lambda * dt, st));
         if ((s = kin_full<R>(p, g, g, (k > 0) ? km_f : km_h, st)) != FSE_OK) return s;
     }
@@ -777,7 +838,7 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
     void* B = base + (size_t)p->n * p->csize;
     void* Phi = base + (size_t)p->n * 2 * p->csize;
     if (p->nl) {
-        s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, st);
+        s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, 0.0, 0.0, st);
         if (s != FSE_OK) return s;
     }
     // kinetic part: H = (1/2)(-Lap+m^2)^s psi through the strided forward passes
@@ -923,7 +984,7 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     const double c0 = 1.0 / dt;
     // frozen W^n = V + beta rho^n + lambda Phi^n
     if (p->nl) {
-        if ((s = potential_impl<R>(p, psi, 1, b.Phi, st)) != FSE_OK) return s;
+        if ((s = potential_impl<R>(p, psi, 1, b.Phi, 0.0, 0.0, st)) != FSE_OK) return s;
     }
     HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, p->U, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
                         (p->d == 3) ? p->gamma[2] : 0.0, st));
@@ -1063,6 +1124,7 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
     if (kernel) p->kernel = *kernel;
     else p->kernel.kind = FSE_K_NONE;
     p->nl = (p->kernel.kind != FSE_K_NONE) && (lambda != 0.0);
+    p->qf = p->nl && dipole_needs_form(&p->kernel, Omega);
     p->C0 = (int)(p->n / N[0]);
     // default schedule: plain radix schedules; the mirrored kinetic visit
     // order in 3D FP64 (measured faster there, slower for the complex64 table)
@@ -1086,12 +1148,18 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
             // same grid and kernel: share the donor's multiplier (not owned here)
             p->khat_host = donor->khat_host;
             p->khat = donor->khat;
+        } else if (p->qf) {
+            // the Coulomb part of the dipole; the quadratic form is applied per convolution
+            const double c = 1.0 / ((d == 3 ? 4.0 : 2.0) * kPi);
+            p->khat_host = fse::gausum_symbol(d, N, L, FSE_K_COULOMB, 1.0, c, p->kernel.delta, p->kernel.ht,
+                                              p->kernel.n);
         } else {
             p->khat_host = fse::gausum_symbol(d, N, L, p->kernel.kind, p->kernel.mu, p->kernel.prefactor,
                                               p->kernel.delta, p->kernel.ht, p->kernel.n);
         }
         double scale = 1.0;
         for (int j = 0; j < d; ++j) scale /= (2.0 * N[j]);
+        p->khat_scale = scale;
         const size_t nk = p->khat_host.size();
         if (p->khat) {
             // shared multiplier: nothing to upload
@@ -1256,6 +1324,8 @@ fse_status fse_gausum_symbol_host(int d, const int* N, const double* L, const fs
     const double gam[3] = {0, 0, 0};
     fse_status st = check_args(d, N, L, 1.0, 0.0, gam, 0.0, 1.0, kernel, FSE_C128);
     if (st != FSE_OK) return st;
+    if (dipole_needs_form(kernel, 0.0))
+        return fail(FSE_ERR_UNSUPPORTED, "a tilted dipole axis has no multiplier even in each frequency");
     std::vector<double> k = fse::gausum_symbol(d, N, L, kernel->kind, kernel->mu, kernel->prefactor, kernel->delta,
                                                kernel->ht, kernel->n);
     std::memcpy(out, k.data(), k.size() * sizeof(double));
@@ -1348,8 +1418,8 @@ fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, voi
     g_err.clear();
     if (!plan || !psi || !Phi) return fail(FSE_ERR_ARG, "plan, psi and Phi must not be NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    return plan->prec == FSE_C128 ? potential_impl<double>(plan, psi, 1, Phi, st)
-                                  : potential_impl<float>(plan, psi, 1, Phi, st);
+    return plan->prec == FSE_C128 ? potential_impl<double>(plan, psi, 1, Phi, plan->t, 0.0, st)
+                                  : potential_impl<float>(plan, psi, 1, Phi, plan->t, 0.0, st);
 }
 
 fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* stream) {
@@ -1492,6 +1562,8 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
         }
         if (!std::isfinite(q.dt) || q.dt == 0.0) return fail(FSE_ERR_ARG, "instance %d: dt must be finite, non-zero", i);
         if (!(q.m >= 0.0) || !std::isfinite(q.m)) return fail(FSE_ERR_ARG, "instance %d: m must be finite, >= 0", i);
+        if (q.lambda != 0.0 && dipole_needs_form(&q.kernel, q.Omega))
+            return fail(FSE_ERR_UNSUPPORTED, "instance %d: the batch does not take tilted or turning dipole axes", i);
     }
     fse_batch b = new fse_batch_s();
     b->count = count;

@@ -417,10 +417,10 @@ __global__ __launch_bounds__((LineCfg<R, N, false>::NTH)) void k_lines_deriv(con
 // registers between the forward and the inverse, and only the first N points
 // are stored.
 // ---------------------------------------------------------------------------
-template <typename R, int M, int V = 0>
+template <typename R, int M, int V = 0, bool QF = false>
 __device__ __forceinline__ void conv_full_body(
     typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
-    const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds) {
+    const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds, const QForm* qf = nullptr) {
     using T = typename CT<R>::T;
     using C = LineCfg<R, M, false, V>;
     constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
@@ -441,7 +441,23 @@ __device__ __forceinline__ void conv_full_body(
     for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (e < N) ? g[e] : T{0, 0}; });
     const long row = mult_row(gl, li);
     R kq[FF::BK][FF::RK];
-    for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
+    if constexpr (QF) {
+        // row frequencies (signed; odd products vanish at Nyquist indices)
+        const int k0 = gl / li.D1, k1r = gl % li.D1;
+        const int k1 = (k1r <= qf->n1) ? k1r : k1r - li.D1;
+        const double a0 = k0 * qf->dk0, a1 = k1 * qf->dk1;
+        const double x0 = (k0 == qf->n0) ? 0.0 : a0, x1 = (k1r == qf->n1) ? 0.0 : a1;
+        const double base = qf->m00 * a0 * a0 + qf->m11 * a1 * a1 + 2.0 * qf->m01 * x0 * x1;
+        const double lin = 2.0 * (qf->m02 * x0 + qf->m12 * x1);
+        for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) {
+            const int k2 = (p <= M / 2) ? p : p - M;
+            const double a2 = k2 * qf->dk2, x2 = (p == M / 2) ? 0.0 : a2;
+            const double Q = base + qf->m22 * a2 * a2 + lin * x2;
+            kq[b][r] = R(qf->c0 + (double)mult[row + min(p, M - p)] * Q);
+        });
+    } else {
+        for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
+    }
     FF::run(v, u, line, jt, twM);
     for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int) {
         u[b][r] = T{u[b][r].x * kq[b][r], u[b][r].y * kq[b][r]};
@@ -452,6 +468,15 @@ __device__ __forceinline__ void conv_full_body(
     for_pos<M, TPL, FI::RK>(jt, [&](int b, int r, int e) {
         if (valid && e < N) g[e] = w[b][r];
     });
+}
+
+// The padded convolution with the quadratic-form dipolar multiplier (QForm).
+template <typename R, int M>
+__global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_conv_qf(
+    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
+    const typename CT<R>::T* twM, QForm q) {
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LPB * LineCfg<R, M, false>::P];
+    conv_full_body<R, M, 0, true>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds, &q);
 }
 
 template <typename R, int M, int V = 0>

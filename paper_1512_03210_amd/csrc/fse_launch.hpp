@@ -25,6 +25,10 @@ template <typename R> struct Launch {
     static hipError_t line(int N, int mode, void* data, int nlines, const void* mult, LineIdx li, const void* twN,
                            const void* tw2N, hipStream_t st, int var = 0);
     // Axis-0 density + padded real-to-complex FFT; src 0 pending state, 1 physical psi, 2 real density.
+    // Padded convolution along the contiguous axis (length N, padded 2N <= 512) with the
+    // quadratic-form dipolar multiplier q over the Coulomb-part table.
+    static hipError_t conv_qf(int N, void* data, int nlines, const void* mult, LineIdx li, const void* tw2N,
+                              const QForm& q, hipStream_t st);
     static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
                           hipStream_t st);
     // Axis-0 complex-to-real + nonlinear phase; mode 0 full, 1 phase only, 2 potential output only.

@@ -29,6 +29,21 @@ struct PhaseArgs {
     double udt;                      // dt, the factor of U in the phase
 };
 
+// Dipolar multiplier as a quadratic form (an axis with products n_i n_j, or
+// one that turns in the rotating frame):
+//   K(kappa) = c0 + Kc(kappa) * sum_ij m_ij kappa_i kappa_j,
+// Kc the Coulomb-part symbol held in the multiplier table (which carries the
+// FFT scale; c0 carries it too).  kappa_j = k_j dk_j with signed indices;
+// index 0 is the row's axis-0 frequency (0..n0), index 1 the row's axis-1
+// frequency (3D, padded length 2 n1), index 2 the line's frequency.  The odd
+// products (i != j) take kappa = 0 at Nyquist indices (k0 = n0, k1 = n1, and
+// the middle of the line), which keeps K even on the grid.
+struct QForm {
+    double c0, m00, m11, m22, m01, m02, m12;
+    double dk0, dk1, dk2;
+    int n0, n1;
+};
+
 // Grid geometry for the elementwise kernels and reductions.
 struct GridGeom {
     int d, N0, N1, N2;

@@ -56,29 +56,34 @@ def test_plan_check_codes(args, code):
 def test_plan_check_3d_and_unsupported_axis():
     k = fse.make_kernel("ddi3", axis=(0.0, 0.0, 1.0))
     assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k) == 0
-    k2 = fse.make_kernel("ddi3", axis=(1.0, 0.0, 0.0))
-    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k2) == -2
+    k2 = fse.make_kernel("ddi3", axis=(1.0, 0.0, 0.0))  # turns in the rotating frame: quadratic form
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k2) == 0
     assert fse.plan_check(3, (512, 32, 32), (6.0,) * 3, 0.8, 0.7, (1, 1, 2), 200, 50, k) == -1
 
 
 def test_plan_check_dipole_axes():
-    # coordinate axes pass without rotation; an axis whose multiplier has a
-    # cross term (odd in a frequency) is unsupported; with rotation only z
+    # any unit axis; tilted or turning axes need the one-pass convolution
     ok3 = [((1.0, 0.0, 0.0), 0.0), ((0.0, 1.0, 0.0), 0.0), ((0.0, 0.0, -1.0), 0.7)]
     for axis, Om in ok3:
         k = fse.make_kernel("ddi3", axis=axis)
         assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, Om, (1, 1, 2), 200, 50, k) == 0, axis
-    k = fse.make_kernel("ddi3", axis=(0.6, 0.8, 0.0))
-    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.0, (1, 1, 2), 200, 50, k) == -2
+    k = fse.make_kernel("ddi3", axis=(0.6, 0.8, 0.0))  # tilted: quadratic form
+    assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.0, (1, 1, 2), 200, 50, k) == 0
+    with pytest.raises(fse.FseError):  # no even table for a tilted axis
+        fse.gausum_symbol_host(3, (32, 32, 32), (6.0,) * 3, k)
     ok2 = [((0.0, 0.0, 1.0), 0.5), ((0.6, 0.0, 0.8), 0.0), ((0.0, 1.0, 0.0), 0.0), ((1.0, 0.0, 0.0), 0.0)]
     for axis, Om in ok2:
         k = fse.make_kernel("ddi2", axis=axis)
         assert fse.plan_check(2, (64, 48), (8.0, 6.0), 0.8, Om, (1, 1), 20, 5, k) == 0, axis
-    bad2 = [((0.36, 0.48, 0.8), 0.0, -2), ((0.6, 0.0, 0.8), 0.5, -2), ((0.6, 0.0, 0.0), 0.0, -1),
-            ((float("nan"), 0.0, 1.0), 0.0, -1)]
-    for axis, Om, want in bad2:
+    cases2 = [((0.36, 0.48, 0.8), 0.0, 0), ((0.6, 0.0, 0.8), 0.5, 0), ((0.6, 0.0, 0.0), 0.0, -1),
+              ((float("nan"), 0.0, 1.0), 0.0, -1)]
+    for axis, Om, want in cases2:
         k = fse.make_kernel("ddi2", axis=axis)
         assert fse.plan_check(2, (64, 48), (8.0, 6.0), 0.8, Om, (1, 1), 20, 5, k) == want, axis
+    # the quadratic form runs in the one-pass padded convolution: contiguous axis <= 256
+    k = fse.make_kernel("ddi2", axis=(0.6, 0.0, 0.8))
+    assert fse.plan_check(2, (64, 384), (8.0, 8.0), 0.8, 0.5, (1, 1), 20, 5, k) == -2
+    assert fse.plan_check(2, (64, 384), (8.0, 8.0), 0.8, 0.0, (1, 1), 20, 5, k) == 0  # fixed, even: stored whole
     k = fse.make_kernel("ddi2")
     assert fse.plan_check(3, (32, 32, 32), (6.0,) * 3, 0.8, 0.0, (1, 1, 2), 200, 50, k) == -1
     k = fse.make_kernel("ddi3")
