@@ -265,3 +265,17 @@ def test_turning_dipole_axis_conserves_the_rotating_frame_energy():
     d50, d100 = _turning_dipole_drift(1, 50), _turning_dipole_drift(1, 100)
     assert abs(d100) < 1e-3 and 3.5 < d50 / d100 < 4.5
     assert abs(_turning_dipole_drift(-1, 100)) > 10 * abs(d100)
+
+
+def test_plane_wave_phase_with_mass_term():
+    # free evolution (no trap, no interaction) of a grid plane wave exp(i k.x):
+    # exp(-i T (|k|^2 + m^2)^s / 2) (eq. SFSE with the mass term)
+    N, L = (32, 24), (4.0, 3.0)
+    s, m = 0.7, 1.3
+    pr = scheme.Problem(2, N, L, s, 0.0, (0.0, 0.0), 0.0, 0.0, kernel="none", m=m)
+    X = np.meshgrid(*scheme.axes(N, L), indexing="ij")
+    k = (3 * math.pi / L[0], -2 * math.pi / L[1])
+    psi0 = np.exp(1j * (k[0] * X[0] + k[1] * X[1]))
+    psi, t = pr.run(psi0, 7, 0.11)
+    om = (k[0] ** 2 + k[1] ** 2 + m * m) ** s
+    assert np.max(np.abs(psi - psi0 * np.exp(-0.5j * t * om))) < 1e-13

@@ -36,6 +36,8 @@ def _params(name):
                           beta=50.0, lam=-5.0, kernel="ddi3", dt=0.02, name="ddi3d"),
         "ddi2rot": W.Params(d=2, N=(32, 48), L=(7.0, 8.0), s=0.8, Omega=0.5, gamma=(1.0, 1.1), beta=40.0, lam=-6.0,
                             kernel="ddi2", dt=0.05, name="ddi2rot"),
+        "mass2d": W.Params(d=2, N=(32, 32), L=(6.0, 6.0), s=0.6, Omega=0.4, gamma=(1.0, 1.0), beta=30.0, lam=2.0,
+                           kernel="coulomb", coef=c2, m=0.8, dt=0.05, name="mass2d"),
         "local2d": W.Params(d=2, N=(48, 48), L=(8.0, 8.0), s=0.5, Omega=0.0, gamma=(1.0, 1.0), beta=100.0, lam=0.0,
                             kernel="none", dt=0.1, name="local2d"),
     }
@@ -59,7 +61,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("name", ["rot2d", "ddi3d", "local2d", "ddi2rot"])
+@pytest.mark.parametrize("name", ["rot2d", "ddi3d", "local2d", "ddi2rot", "mass2d"])
 @pytest.mark.parametrize("prec,tol,gate", [(fse.C128, 1e-12, 1e-10), (fse.C64, 1e-6, 1e-5)])
 def test_one_step_against_oracle(name, prec, tol, gate):
     p = _params(name)

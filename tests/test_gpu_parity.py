@@ -85,6 +85,11 @@ def P(name, **kw):
         # 3D dipole along y, no rotation
         ddi3y=W.Params(d=3, N=(24, 32, 16), L=(5.0, 6.0, 4.0), s=0.9, Omega=0.0, gamma=(1.0, 1.2, 1.5),
                        beta=100.0, lam=30.0, kernel="ddi3", axis=(0.0, 1.0, 0.0), dt=5e-4, name="ddi3y"),
+        # the mass term of (-Lap + m^2)^s (eq. SFSE), 2D rotating Coulomb and 3D local
+        mass2d=W.Params(d=2, N=(48, 64), L=(6.0, 7.0), s=0.6, Omega=0.5, gamma=(1.0, 1.1), beta=40.0, lam=2.0,
+                        kernel="coulomb", m=0.7, dt=1e-3, name="mass2d"),
+        mass3d=W.Params(d=3, N=(24, 16, 32), L=(5.0, 4.0, 6.0), s=1.3, Omega=0.3, gamma=(1.0, 1.2, 0.8), beta=20.0,
+                        lam=0.0, kernel="none", m=1.5, dt=1e-3, name="mass3d"),
         # radix-3 lengths in every pass
         rad3_3d=W.Params(d=3, N=(48, 96, 24), L=(6.0, 8.0, 4.0), s=0.6, Omega=0.4, gamma=(1.0, 0.9, 1.3),
                          beta=100.0, lam=2.0, kernel="coulomb", dt=1e-3, name="rad3_3d"),
@@ -99,7 +104,7 @@ def _psi0(p, seed=0):
 
 
 CASES = ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "local3d", "big2d", "big2d_t", "rad3_3d", "ddi2z",
-         "ddi2xz", "ddi3y"]
+         "ddi2xz", "ddi3y", "mass2d", "mass3d"]
 
 
 @pytest.mark.parametrize("name", CASES)
@@ -132,7 +137,7 @@ def test_one_step_c64(name):
     assert err < 1e-5
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "ddi2z", "ddi2xz"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "ddi2z", "ddi2xz", "mass2d"])
 def test_many_steps_fsal_against_plain_oracle(name):
     # merged half steps inside one call vs the oracle's plain scheme; the
     # anisotropic rotating cases exercise the time-dependent trap integral.
@@ -185,7 +190,8 @@ def test_symbol_of_plan_matches_oracle():
     assert np.max(np.abs(K - Ko)) < 1e-11 * np.max(np.abs(Ko))
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local3d", "ddi2z", "ddi2xz", "ddi3y"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local3d", "ddi2z", "ddi2xz", "ddi3y",
+                                  "mass2d", "mass3d"])
 @pytest.mark.parametrize("prec", [fse.C128, fse.C64])
 def test_diagnostics(name, prec):
     p = P(name)
@@ -206,7 +212,7 @@ def test_diagnostics(name, prec):
     assert abs(lz - dg.angular_momentum(xin, p.N, p.L)) < tol
 
 
-@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "ddi2z", "ddi2xz"])
+@pytest.mark.parametrize("name", ["plain2d", "aniso2d", "coul3d", "ddi3d", "local2d", "ddi2z", "ddi2xz", "mass2d"])
 @pytest.mark.parametrize("frozen", [False, True])
 def test_apply_H(name, frozen):
     p = P(name)
