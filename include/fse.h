@@ -109,6 +109,19 @@ fse_status fse_plan_destroy(fse_plan plan);
 /* Device bytes held by the plan (multiplier, twiddles, workspace). */
 fse_status fse_workspace_size(fse_plan plan, size_t* bytes);
 
+/* Bytes of the step's scratch (the padded transform intermediates X1 and, in
+ * 3D, X2; 0 without a nonlocal term) that fse_set_workspace can take from the
+ * caller. */
+fse_status fse_scratch_size(fse_plan plan, size_t* bytes);
+
+/* Use a caller-owned device buffer (e.g. torch-allocated) of at least
+ * fse_scratch_size bytes, 256-byte aligned, as the step's scratch; the plan
+ * frees its own (synchronising the device).  The contents are not kept across
+ * calls, so the caller may reuse the memory between calls on the plan's
+ * stream, but must keep it allocated while calls run.  dev_ptr = NULL returns
+ * to plan-owned scratch.  FSE_ERR_ARG if too small or misaligned. */
+fse_status fse_set_workspace(fse_plan plan, void* dev_ptr, size_t bytes);
+
 fse_status fse_set_time(fse_plan plan, double t);
 fse_status fse_get_time(fse_plan plan, double* t);
 

@@ -95,6 +95,7 @@ struct fse_plan_s {
     std::vector<double> khat_host;
     void* X1 = nullptr;
     void* X2 = nullptr;
+    bool ext_ws = false;  // X1 and X2 live in a caller's buffer (fse_set_workspace)
     void* kin[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double kin_tau[7] = {NAN, NAN, NAN, NAN, NAN, NAN, NAN};
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
@@ -1345,6 +1346,51 @@ fse_status fse_plan_destroy(fse_plan plan) {
     (void)hipDeviceSynchronize();
     destroy(plan);
     return FSE_OK;
+}
+
+// Scratch of the step: X1 and X2 (3D), each rounded up to 256 bytes.
+size_t scratch_parts(const fse_plan p, size_t* x1b, size_t* x2b) {
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    *x1b = p->nl ? up((size_t)(p->N[0] + 1) * p->C0 * p->csize) : 0;
+    *x2b = (p->nl && p->d == 3) ? up((size_t)(p->N[0] + 1) * 2 * p->N[1] * p->N[2] * p->csize) : 0;
+    return *x1b + *x2b;
+}
+
+fse_status fse_scratch_size(fse_plan plan, size_t* bytes) {
+    g_err.clear();
+    if (!plan || !bytes) return fail(FSE_ERR_ARG, "plan and bytes must not be NULL");
+    size_t a, b;
+    *bytes = scratch_parts(plan, &a, &b);
+    return FSE_OK;
+}
+
+fse_status fse_set_workspace(fse_plan plan, void* dev_ptr, size_t bytes) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    size_t x1b, x2b;
+    const size_t need = scratch_parts(plan, &x1b, &x2b);
+    if (need == 0) return FSE_OK;  // no nonlocal term: the step has no scratch
+    if (dev_ptr && bytes < need)
+        return fail(FSE_ERR_ARG, "workspace of %zu bytes is smaller than the %zu the plan needs", bytes, need);
+    if (dev_ptr && (reinterpret_cast<uintptr_t>(dev_ptr) % 256) != 0)
+        return fail(FSE_ERR_ARG, "workspace must be 256-byte aligned");
+    // release the current scratch (the plan's own memory, or forget the caller's)
+    if (!plan->ext_ws) {
+        dev_free(plan, plan->X1, x1b ? (size_t)(plan->N[0] + 1) * plan->C0 * plan->csize : 0);
+        if (plan->X2) dev_free(plan, plan->X2, (size_t)(plan->N[0] + 1) * 2 * plan->N[1] * plan->N[2] * plan->csize);
+    }
+    plan->X1 = plan->X2 = nullptr;
+    plan->ext_ws = false;
+    if (dev_ptr) {
+        plan->X1 = dev_ptr;
+        if (x2b) plan->X2 = static_cast<char*>(dev_ptr) + x1b;
+        plan->ext_ws = true;
+        return FSE_OK;
+    }
+    fse_status st = dev_alloc(plan, &plan->X1, (size_t)(plan->N[0] + 1) * plan->C0 * plan->csize);
+    if (st == FSE_OK && plan->d == 3)
+        st = dev_alloc(plan, &plan->X2, (size_t)(plan->N[0] + 1) * 2 * plan->N[1] * plan->N[2] * plan->csize);
+    return st;
 }
 
 fse_status fse_workspace_size(fse_plan plan, size_t* bytes) {

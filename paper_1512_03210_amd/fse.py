@@ -25,7 +25,8 @@ K_NONE, K_COULOMB, K_DDI3, K_DDI2 = 0, 1, 2, 3
 KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_DDI2}
 
 EXPORTS = [
-    "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size",
+    "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size", "fse_scratch_size",
+    "fse_set_workspace",
     "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_plan_tune", "fse_plan_get_schedule", "fse_plan_set_schedule",
     "fse_set_potential", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
@@ -77,6 +78,8 @@ def lib():
         "fse_plan_create": (st, [ctypes.POINTER(vp), i, ip, dp, d, d, dp, d, d, kp, i, d, vp]),
         "fse_plan_destroy": (st, [vp]),
         "fse_workspace_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "fse_scratch_size": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "fse_set_workspace": (st, [vp, vp, ctypes.c_size_t]),
         "fse_set_time": (st, [vp, d]),
         "fse_get_time": (st, [vp, dp]),
         "fse_step": (st, [vp, vp, i, d, vp]),
@@ -192,6 +195,7 @@ class Plan:
         self.rdtype = torch.float64 if precision == C128 else torch.float32
         self._h = ctypes.c_void_p()
         self._U = None
+        self._ws = None
         _check(lib().fse_plan_create(ctypes.byref(self._h), self.d, _iarr(self.N), _darr(self.L), s, Omega,
                                      _darr(gamma), beta, lam,
                                      ctypes.byref(kernel) if kernel is not None else None,
@@ -279,6 +283,22 @@ class Plan:
         b = ctypes.c_size_t()
         _check(lib().fse_workspace_size(self._h, ctypes.byref(b)))
         return b.value
+
+    def scratch_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        _check(lib().fse_scratch_size(self._h, ctypes.byref(b)))
+        return b.value
+
+    def set_workspace(self, buf=None):
+        """Take the step's scratch from a device tensor of at least scratch_bytes() bytes
+        (fse_set_workspace); the plan holds a reference to it.  None returns to plan-owned scratch."""
+        if buf is None:
+            _check(lib().fse_set_workspace(self._h, None, 0))
+        else:
+            if not buf.is_cuda or not buf.is_contiguous():
+                raise ValueError("workspace must be a contiguous device tensor")
+            _check(lib().fse_set_workspace(self._h, _ptr(buf), buf.numel() * buf.element_size()))
+        self._ws = buf
 
     def step(self, psi, nsteps: int, dt: float, stream=None, order: int = 2):
         """nsteps steps in place: TS2-GauSum (order 2, fse_step) or its fourth-order
