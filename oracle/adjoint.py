@@ -40,7 +40,7 @@ def _vol(N, L):
 def _theta(prob, psi1, t, dt):
     rho = np.abs(psi1) ** 2
     th = dt * prob.beta * rho + prob.lam * dt * prob.potential(rho, t, dt)
-    th = th + trap_integral(prob.N, prob.L, prob.gamma, prob.Omega, t, dt)
+    th = th + trap_integral(prob.N, prob.L, prob.gamma, prob.Omega, t, dt, prob.lattice)
     if prob.U is not None:
         th = th + dt * prob.U
     return th

@@ -69,7 +69,7 @@ def energy_parts(prob, psi, t=0.0):
     ph = np.fft.fftn(psi)
     ekin = 0.5 * vol / n * float(np.sum(om * np.abs(ph) ** 2))
     rho = np.abs(psi) ** 2
-    W = trap(N, L, prob.gamma, prob.Omega, t)
+    W = trap(N, L, prob.gamma, prob.Omega, t, getattr(prob, "lattice", None))
     if getattr(prob, "U", None) is not None:
         W = W + prob.U
     epot = vol * float(np.sum(W * rho))
@@ -111,7 +111,7 @@ def apply_H(prob, psi, rho_frozen=None):
     om = kinetic_symbol(N, L, prob.s, prob.m)
     kin = np.fft.ifftn(0.5 * om * np.fft.fftn(psi))
     rho = np.abs(psi) ** 2 if rho_frozen is None else rho_frozen
-    V = trap(N, L, prob.gamma, 0.0, 0.0)
+    V = trap(N, L, prob.gamma, 0.0, 0.0, getattr(prob, "lattice", None))
     if getattr(prob, "U", None) is not None:
         if prob.Omega != 0.0:
             # U is static in the rotating Lagrangian coordinates, which turn

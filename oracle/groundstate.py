@@ -37,7 +37,7 @@ import math
 import numpy as np
 from scipy.sparse.linalg import LinearOperator, bicgstab
 
-from .scheme import _bcast, axes, freqs, kinetic_symbol
+from .scheme import _bcast, axes, freqs, kinetic_symbol, lattice_potential
 
 
 def _norm(phi, N, L):
@@ -90,6 +90,8 @@ class GroundState:
         """W^n = V + beta rho^n + lam Phi^n of the time level phi^n."""
         rho = np.abs(phi_n) ** 2
         V = self.V
+        if getattr(self.prob, "lattice", None) is not None:
+            V = V + lattice_potential(self.X, self.prob.lattice)  # the frame of eq. SFSE
         if getattr(self.prob, "U", None) is not None:
             if self.prob.Omega != 0.0:
                 raise NotImplementedError("an external potential needs Omega = 0 in the ground-state step")

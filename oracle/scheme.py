@@ -16,6 +16,12 @@ Oracle (test infrastructure only).  Follows Section 4.2 of the paper:
   m m^T over the sub-step (eq. Kernel_Rot), and P = int V(A(s) x~) ds (eq. int_poten).
 * TS2-GauSum (eqs. tssp1-tssp3): half linear step, full nonlinear step,
   half linear step.
+* A non-harmonic part of V: an optical lattice V_L = sum_j v_j sin^2(k_j x_j)
+  in the frame of eq. SFSE (the form of the paper's second ground-state
+  example).  Its time integral over a sub-step in rotating coordinates has no
+  closed form; the paper leaves P to be computed numerically for a general V.
+  Here: Gauss-Legendre quadrature in s with 32 nodes (Omega = 0: exactly
+  tau V_L).
 * Fourth order: the paper notes that TS2 extends to higher-order splitting
   (end of Section 4.2) without giving a scheme.  Reading: the symmetric
   triple-jump composition of Yoshida (1990), TS2 steps of lengths w1 dt,
@@ -85,8 +91,33 @@ def kinetic(psi, N, L, s, tau, m=0.0):
     return np.fft.ifftn(np.exp(-1j * tau * 0.5 * om) * np.fft.fftn(psi))
 
 
-def trap(N, L, gamma, Omega, t):
-    """W(x~, t) = V(A(t) x~) on the grid (rotating frame, eq. FSE1_Rot)."""
+def lattice_potential(X, lattice):
+    """V_L = sum_j v_j sin^2(k_j x_j) at frame coordinates X (lattice = (v, k), per axis)."""
+    v, k = lattice
+    return sum(v[j] * np.sin(k[j] * X[j]) ** 2 for j in range(len(X)))
+
+
+def _lab(X, Omega, t):
+    th = Omega * t
+    c, s_ = math.cos(th), math.sin(th)
+    lab = list(X)
+    lab[0] = c * X[0] + s_ * X[1]
+    lab[1] = -s_ * X[0] + c * X[1]
+    return lab
+
+
+def lattice_integral(N, L, Omega, lattice, t, tau, nodes=32):
+    """int_t^{t+tau} V_L(A(s) x~) ds by Gauss-Legendre in s."""
+    X = np.meshgrid(*axes(N, L), indexing="ij")
+    xg, wg = np.polynomial.legendre.leggauss(nodes)
+    out = np.zeros(X[0].shape)
+    for xi, wi in zip(xg, wg):
+        out = out + 0.5 * tau * wi * lattice_potential(_lab(X, Omega, t + 0.5 * tau * (xi + 1.0)), lattice)
+    return out
+
+
+def trap(N, L, gamma, Omega, t, lattice=None):
+    """W(x~, t) = V(A(t) x~) on the grid (rotating frame, eq. FSE1_Rot), lattice included."""
     d = len(N)
     X = np.meshgrid(*axes(N, L), indexing="ij")
     th = Omega * t
@@ -96,11 +127,14 @@ def trap(N, L, gamma, Omega, t):
     V = 0.5 * (gamma[0] ** 2 * x ** 2 + gamma[1] ** 2 * y ** 2)
     if d == 3:
         V = V + 0.5 * gamma[2] ** 2 * X[2] ** 2
+    if lattice is not None:
+        V = V + lattice_potential(_lab(X, Omega, t), lattice)
     return V
 
 
-def trap_integral(N, L, gamma, Omega, t, tau):
-    """P(x~; t, t+tau) = int_t^{t+tau} V(A(s) x~) ds, closed form (eq. int_poten)."""
+def trap_integral(N, L, gamma, Omega, t, tau, lattice=None):
+    """P(x~; t, t+tau) = int_t^{t+tau} V(A(s) x~) ds: closed form for the harmonic trap
+    (eq. int_poten), quadrature for a lattice."""
     d = len(N)
     X = np.meshgrid(*axes(N, L), indexing="ij")
     gx2, gy2 = gamma[0] ** 2, gamma[1] ** 2
@@ -115,6 +149,8 @@ def trap_integral(N, L, gamma, Omega, t, tau):
     P = P + (gx2 - gy2) / 4.0 * ((X[0] ** 2 - X[1] ** 2) * sc_int + 2.0 * X[0] * X[1] * ss_int)
     if d == 3:
         P = P + tau * 0.5 * gamma[2] ** 2 * X[2] ** 2
+    if lattice is not None:
+        P = P + lattice_integral(N, L, Omega, lattice, t, tau)
     return P
 
 
@@ -138,6 +174,8 @@ class Problem:
                              and (self.axis[0] != 0.0 or self.axis[1] != 0.0))
         self._K = None
         self._KC = None
+        # optional optical lattice (v, k) per axis, in the frame of eq. SFSE
+        self.lattice = None
 
     @classmethod
     def from_params(cls, p):
@@ -177,7 +215,7 @@ class Problem:
         """Nonlinear sub-step over [t, t+tau] (eqs. 2stepA, 2stepB, solu_step2)."""
         rho = np.abs(phi) ** 2
         theta = tau * self.beta * rho + self.lam * tau * self.potential(rho, t, tau)
-        theta = theta + trap_integral(self.N, self.L, self.gamma, self.Omega, t, tau)
+        theta = theta + trap_integral(self.N, self.L, self.gamma, self.Omega, t, tau, self.lattice)
         if self.U is not None:
             theta = theta + tau * self.U
         return phi * np.exp(-1j * theta)

@@ -279,3 +279,43 @@ def test_plane_wave_phase_with_mass_term():
     psi, t = pr.run(psi0, 7, 0.11)
     om = (k[0] ** 2 + k[1] ** 2 + m * m) ** s
     assert np.max(np.abs(psi - psi0 * np.exp(-0.5j * t * om))) < 1e-13
+
+
+def test_lattice_time_integral_against_adaptive_quadrature():
+    # int_t^{t+tau} V_L(A(s) x~) ds on the grid against scipy's adaptive quad at sample points
+    N, L = (16, 12), (4.0, 3.0)
+    lat = ((10.0, 7.0, 0.0), (math.pi, 1.3, 0.0))
+    Om, t, tau = 0.8, 0.9, 0.3
+    P = scheme.lattice_integral(N, L, Om, lat, t, tau)
+    ax = scheme.axes(N, L)
+    for i, j in [(0, 0), (3, 7), (11, 2), (15, 11)]:
+        x, y = ax[0][i], ax[1][j]
+
+        def f(s):
+            c, sn = math.cos(Om * s), math.sin(Om * s)
+            return 10.0 * math.sin(math.pi * (c * x + sn * y)) ** 2 + 7.0 * math.sin(1.3 * (-sn * x + c * y)) ** 2
+        ref, _ = integrate.quad(f, t, t + tau, epsabs=1e-14, epsrel=1e-14)
+        assert abs(P[i, j] - ref) < 1e-13 * max(1.0, abs(ref))
+    # without rotation: exactly tau V_L
+    P0 = scheme.lattice_integral(N, L, 0.0, lat, t, tau)
+    X = np.meshgrid(*ax, indexing="ij")
+    assert np.max(np.abs(P0 - tau * scheme.lattice_potential(X, lat))) < 1e-13
+
+
+def _lattice_drift(nsteps):
+    N, L = (48, 48), (6.0, 6.0)
+    pr = scheme.Problem(2, N, L, 0.9, 0.5, (1.0, 1.0), 10.0, 0.0, kernel="none")
+    pr.lattice = ((2.0, 2.0, 0.0), (0.5 * math.pi, 0.5 * math.pi, 0.0))
+    X = np.meshgrid(*scheme.axes(N, L), indexing="ij")
+    psi = W.normalize(np.exp(-(X[0] - 0.5) ** 2 / 1.2 - X[1] ** 2 / 0.8) * (1 + 0.3j * X[1]) + 0j, pr.h)
+    E0 = dg.energy_parts(pr, psi, 0.0)[5]
+    psi, t = pr.run(psi, nsteps, 1.0 / nsteps)
+    return dg.energy_parts(pr, psi, t)[5] - E0
+
+
+def test_rotating_lattice_conserves_the_rotating_frame_energy():
+    # the lattice is static in the frame of eq. SFSE, where the Hamiltonian does
+    # not depend on time; in rotating coordinates it turns, and the energy with
+    # W(x~, t) = V(A(t) x~) is conserved up to the splitting error (order 2)
+    d50, d100 = _lattice_drift(50), _lattice_drift(100)
+    assert abs(d100) < 1e-3 and 3.5 < d50 / d100 < 4.5
