@@ -170,6 +170,16 @@ fse_status fse_plan_get_schedule(fse_plan plan, int* sched, double* tuned_ms);
  * the plan's lengths do not have, or a mirrored order in 2D. */
 fse_status fse_plan_set_schedule(fse_plan plan, const int* sched);
 
+/* Optical lattice added to the harmonic trap: V_L = sum_j v[j] sin^2(k[j] x_j)
+ * over the d axes, defined in the frame of eq. SFSE (the form of the paper's
+ * second ground-state example).  With Omega != 0 it turns in the rotating
+ * Lagrangian coordinates of the step, and each nonlinear sub-step integrates
+ * it over time by 8-node Gauss-Legendre quadrature (the trap integral P of a
+ * non-harmonic V has no closed form); the energy takes its value at the plan's
+ * time, H psi and the ground state take it in the frame of eq. SFSE.  v = NULL
+ * removes it.  The first call allocates one real array of N points. */
+fse_status fse_set_lattice(fse_plan plan, const double* v, const double* k);
+
 /* Optional real potential U(x~) on the plan's grid, added to the nonlinear
  * phase of fse_step and fse_step4 as dt * U and to the potential energy of
  * fse_energy (eq. SFSE with V + U; U is static in the rotating Lagrangian

@@ -96,6 +96,10 @@ struct fse_plan_s {
     void* X1 = nullptr;
     void* X2 = nullptr;
     bool ext_ws = false;  // X1 and X2 live in a caller's buffer (fse_set_workspace)
+    // optional optical lattice (fse_set_lattice) and a real n-array for its phase / values
+    bool lat = false;
+    double lat_v[3] = {0, 0, 0}, lat_k[3] = {0, 0, 0};
+    void* lat_buf = nullptr;
     void* kin[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
     double kin_tau[7] = {NAN, NAN, NAN, NAN, NAN, NAN, NAN};
     void* diag = nullptr;  // 2 n complex + n real, allocated on first use
@@ -446,6 +450,51 @@ template <typename R> hipError_t conv_line(fse_plan p, double t, double tau, hip
     return L::line(NL, 0, X, nl, p->khat, conv_index(p), p->tw[NL], p->tw[2 * NL], st, p->sched[1]);
 }
 
+// Lattice arguments: its time integral over [t, t+tau] in rotating coordinates
+// (8-node Gauss-Legendre in time; the trap integral P of a non-harmonic V has
+// no closed form), plus tau U; or its value at the instant t (tau = 0), plus U.
+fse::LatArgs lat_args(const fse_plan p, double t, double tau) {
+    fse::LatArgs la{};
+    for (int j = 0; j < 3; ++j) {
+        la.v[j] = p->lat_v[j];
+        la.k[j] = p->lat_k[j];
+    }
+    if (tau == 0.0) {
+        la.nq = 1;
+        la.c[0] = std::cos(p->Omega * t);
+        la.s[0] = std::sin(p->Omega * t);
+        la.w[0] = 1.0;
+        la.uf = 1.0;
+        return la;
+    }
+    std::vector<double> x, w;
+    fse::gauss_legendre(8, x, w);
+    la.nq = 8;
+    for (int q = 0; q < 8; ++q) {
+        const double sq = t + 0.5 * tau * (x[q] + 1.0);
+        la.c[q] = std::cos(p->Omega * sq);
+        la.s[q] = std::sin(p->Omega * sq);
+        la.w[q] = 0.5 * tau * w[q];
+    }
+    la.uf = tau;
+    return la;
+}
+
+// The potential array the pointwise kernels add: the grid potential U, or with a
+// lattice the lattice in the frame at time t (frame = true: the frame of
+// eq. SFSE, for H psi and the ground state) plus U, written to lat_buf.
+template <typename R> const void* extra_potential(fse_plan p, double t, bool frame, hipStream_t st, hipError_t* e) {
+    *e = hipSuccess;
+    if (!p->lat) return p->U;
+    fse::LatArgs la = lat_args(p, frame ? 0.0 : t, 0.0);
+    if (frame) {
+        la.c[0] = 1.0;
+        la.s[0] = 0.0;
+    }
+    *e = fse::Launch<R>::lattice(p->lat_buf, p->U, p->n, geom(p), la, st);
+    return p->lat_buf;
+}
+
 // Zero-padded GauSum convolution of the density held in X1 (after r2c), result back in X1.
 template <typename R> fse_status conv_passes(fse_plan p, double t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
@@ -526,7 +575,13 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
         double tj = p->t + k * dt;
         for (int j = 0; j < nw; ++j) {
             const double tau = w[j] * dt;
-            const fse::PhaseArgs pa = phase_args(p, tj, tau);
+            fse::PhaseArgs pa = phase_args(p, tj, tau);
+            if (p->lat) {
+                // the sub-step's lattice integral (and tau U) as the phase's grid potential
+                HIPCHK(L::lattice(p->lat_buf, p->U, p->n, geom(p), lat_args(p, tj, tau), st));
+                pa.U = p->lat_buf;
+                pa.udt = 1.0;
+            }
             tj += tau;
             if (p->nl) {
                 PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
@@ -587,7 +642,10 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
         const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
         const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
         const double th = 2.0 * p->Omega * p->t;
-        HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, p->U, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
+        hipError_t ee;
+        const void* Ux = extra_potential<R>(p, p->t, false, st, &ee);
+        HIPCHK(ee);
+        HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, Ux, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
                             (gx2 - gy2) / 4.0 * std::cos(th), (gx2 - gy2) / 4.0 * std::sin(th), p->partials, 0,
                             kRedBlocks, st));
     } else {
@@ -672,9 +730,15 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     if ((s = kin_full<R>(p, psi0, S(0), kp_h, st)) != FSE_OK) return s;
     for (int k = 0; k < nsteps; ++k) {
         if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, p->t + k * dt, dt, st)) != FSE_OK) return s;
-        const fse::PhaseArgs pa = phase_args(p, p->t + k * dt, dt);
+        fse::PhaseArgs pa = phase_args(p, p->t + k * dt, dt);
+        const void* Ux = p->U;
+        if (p->lat) {
+            HIPCHK(L::lattice(p->lat_buf, p->U, p->n, gg, lat_args(p, p->t + k * dt, dt), st));
+            Ux = p->lat_buf;
+            pa.udt = 1.0;
+        }
         void* next = (k + 1 < nsteps) ? S(k + 1) : nullptr;
-        HIPCHK(L::adj_theta(S(k), p->nl ? Phi : nullptr, p->U, TH(k), next, p->n, gg, pa, st));
+        HIPCHK(L::adj_theta(S(k), p->nl ? Phi : nullptr, Ux, TH(k), next, p->n, gg, pa, st));
         if (next && (s = kin_full<R>(p, next, next, kp_f, st)) != FSE_OK) return s;
     }
     // reverse
@@ -864,7 +928,10 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
         HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
         HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, p->Omega, 0, 0, 0, 0, 0, st));
     }
-    HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, p->U, p->n, g, 2, p->Omega, p->beta, p->lambda,
+    hipError_t ee;
+    const void* Ux = extra_potential<R>(p, 0.0, true, st, &ee);
+    HIPCHK(ee);
+    HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, Ux, p->n, g, 2, p->Omega, p->beta, p->lambda,
                       p->gamma[0], p->gamma[1], (p->d == 3) ? p->gamma[2] : 0.0, st));
     return FSE_OK;
 }
@@ -987,7 +1054,10 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     if (p->nl) {
         if ((s = potential_impl<R>(p, psi, 1, b.Phi, 0.0, 0.0, st)) != FSE_OK) return s;
     }
-    HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, p->U, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
+    hipError_t ee;
+    const void* Ux = extra_potential<R>(p, 0.0, true, st, &ee);
+    HIPCHK(ee);
+    HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, Ux, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
                         (p->d == 3) ? p->gamma[2] : 0.0, st));
     if ((s = pd_table<R>(p, c0, st)) != FSE_OK) return s;
     // right-hand side P_Delta psi/dt, held in sv until r is formed
@@ -1545,6 +1615,28 @@ fse_status fse_plan_set_schedule(fse_plan plan, const int* sched) {
         return fail(FSE_ERR_UNSUPPORTED, "the convolution of this plan has no alternative radix schedule");
     if (sched[2] == 1 && plan->d != 3) return fail(FSE_ERR_UNSUPPORTED, "the mirrored visit order is 3D only");
     for (int k = 0; k < 3; ++k) plan->sched[k] = sched[k];
+    return FSE_OK;
+}
+
+fse_status fse_set_lattice(fse_plan plan, const double* v, const double* k) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    if (!v) {
+        plan->lat = false;
+        return FSE_OK;
+    }
+    if (!k) return fail(FSE_ERR_ARG, "k must not be NULL when v is given");
+    for (int j = 0; j < plan->d; ++j)
+        if (!std::isfinite(v[j]) || !std::isfinite(k[j])) return fail(FSE_ERR_ARG, "lattice v and k must be finite");
+    if (!plan->lat_buf) {
+        fse_status s = dev_alloc(plan, &plan->lat_buf, (size_t)plan->n * plan->rsize);
+        if (s != FSE_OK) return s;
+    }
+    for (int j = 0; j < 3; ++j) {
+        plan->lat_v[j] = (j < plan->d) ? v[j] : 0.0;
+        plan->lat_k[j] = (j < plan->d) ? k[j] : 0.0;
+    }
+    plan->lat = true;
     return FSE_OK;
 }
 

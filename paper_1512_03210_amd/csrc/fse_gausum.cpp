@@ -38,40 +38,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
-// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n.
-void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
-    x.assign(n, 0.0);
-    w.assign(n, 0.0);
-    for (int i = 0; i < (n + 1) / 2; ++i) {
-        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
-        double dp = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double p0 = 1.0, p1 = z;
-            for (int k = 2; k <= n; ++k) {
-                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            // p1 = P_n(z), p0 = P_{n-1}(z)
-            dp = n * (z * p1 - p0) / (z * z - 1.0);
-            const double dz = p1 / dp;
-            z -= dz;
-            if (std::fabs(dz) < 1e-17) break;
-        }
-        {
-            double p0 = 1.0, p1 = z;
-            for (int k = 2; k <= n; ++k) {
-                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
-                p0 = p1;
-                p1 = p2;
-            }
-            dp = n * (z * p1 - p0) / (z * z - 1.0);
-        }
-        x[i] = -z;
-        x[n - 1 - i] = z;
-        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
-    }
-}
 
 // Series for the lower incomplete gamma function scaled as
 // gamma(a, x) / x^a = e^{-x} sum_k x^k / (a (a+1) ... (a+k)).
@@ -109,6 +75,41 @@ template <typename F> void parallel_for(int n, F f) {
 }
 
 }  // namespace
+
+// Gauss-Legendre nodes and weights on [-1, 1] by Newton's method on P_n.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            // p1 = P_n(z), p0 = P_{n-1}(z)
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-17) break;
+        }
+        {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
 
 void sinc_gaussian_sum(double mu, double c, int d, double Lmax, double delta, double ht, std::vector<double>& w,
                        std::vector<double>& tau) {

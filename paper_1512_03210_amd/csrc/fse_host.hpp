@@ -15,6 +15,9 @@ void gauss_factor_table(const std::vector<double>& tau, double D, int K, std::ve
 void near_field(int d, double mu, double c, double delta, const std::vector<double>& w, const std::vector<double>& tau,
                 double& C0, double& C2);
 
+// Gauss-Legendre nodes and weights on [-1, 1].
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
 // Multiplier on the non-negative octant, (N_j + 1) values per axis, row-major.
 // kind: 1 Coulomb c/|x|^mu, 2 3D dipole, 3 2D dipole, along the unit axis n
 // (kinds 2 and 3; the multiplier must be even in every frequency, so n has no

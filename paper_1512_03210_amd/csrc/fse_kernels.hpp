@@ -1093,6 +1093,25 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
     }
 }
 
+// Lattice potential or its time integral (LatArgs), plus uf U when U is given; FP64 inside.
+template <typename R>
+__global__ void k_lattice(R* __restrict__ out, const R* __restrict__ U, long n, GridGeom g, LatArgs la) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        int i0, i1, i2;
+        decode(i, g, i0, i1, i2);
+        const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy, z = (g.d == 3) ? g.z0 + i2 * g.hz : 0.0;
+        const double sz = (la.v[2] != 0.0) ? sin(la.k[2] * z) : 0.0;
+        double acc = 0.0;
+        for (int q = 0; q < la.nq; ++q) {
+            const double xr = la.c[q] * x + la.s[q] * y, yr = -la.s[q] * x + la.c[q] * y;
+            const double sx = sin(la.k[0] * xr), sy = sin(la.k[1] * yr);
+            acc += la.w[q] * (la.v[0] * sx * sx + la.v[1] * sy * sy + la.v[2] * sz * sz);
+        }
+        if (U) acc += la.uf * (double)U[i];
+        out[i] = R(acc);
+    }
+}
+
 // Plain streaming copy (HBM bandwidth calibration): 16-byte vectors, each
 // thread loads four elements 256 apart, then stores them; one pass, no loop.
 static __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src, long n) {

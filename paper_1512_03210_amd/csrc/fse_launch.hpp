@@ -62,6 +62,8 @@ template <typename R> struct Launch {
     // Ground-state step (kernels in fse_gs.hpp).
     static hipError_t gs_frozen(const void* psi, const void* Phi, const void* U, void* W, long n, const GridGeom& g,
                                 double beta, double lam, double g0, double g1, double g2, hipStream_t st);
+    // Lattice potential / its time integral into out (k_lattice).
+    static hipError_t lattice(void* out, const void* U, long n, const GridGeom& g, const LatArgs& la, hipStream_t st);
     // Adjoint of the split step (kernels in fse_adjoint.hpp).
     static hipError_t adj_theta(const void* psi1, const void* Phi, const void* U, void* theta, void* psi2, long n,
                                 const GridGeom& g, const PhaseArgs& pa, hipStream_t st);

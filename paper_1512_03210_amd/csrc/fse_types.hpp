@@ -44,6 +44,18 @@ struct QForm {
     int n0, n1;
 };
 
+// Optical lattice V_L = sum_j v_j sin^2(k_j x_j), defined in the frame of
+// eq. SFSE, evaluated along the rotating frame: out = sum_q w_q V_L(A_q x~)
+// + uf U, A_q turning (x, y) by the angle with cosine c[q] and sine s[q] (z is
+// not turned).  One node with w = 1 gives V_L at one instant; Gauss-Legendre
+// nodes over [t, t+tau] (weights times tau/2) give its time integral.
+struct LatArgs {
+    double v[3], k[3];
+    double c[8], s[8], w[8];
+    int nq;
+    double uf;
+};
+
 // Grid geometry for the elementwise kernels and reductions.
 struct GridGeom {
     int d, N0, N1, N2;

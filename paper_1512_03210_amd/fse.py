@@ -28,7 +28,7 @@ EXPORTS = [
     "fse_plan_check", "fse_plan_create", "fse_plan_destroy", "fse_workspace_size", "fse_scratch_size",
     "fse_set_workspace",
     "fse_set_time", "fse_get_time", "fse_step", "fse_step4", "fse_plan_tune", "fse_plan_get_schedule", "fse_plan_set_schedule",
-    "fse_set_potential", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
+    "fse_set_potential", "fse_set_lattice", "fse_step_adjoint", "fse_apply_Lz", "fse_apply_H", "fse_nonlocal_potential",
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
@@ -85,6 +85,7 @@ def lib():
         "fse_step": (st, [vp, vp, i, d, vp]),
         "fse_step4": (st, [vp, vp, i, d, vp]),
         "fse_set_potential": (st, [vp, vp]),
+        "fse_set_lattice": (st, [vp, dp, dp]),
         "fse_plan_tune": (st, [vp, ctypes.c_char_p, vp]),
         "fse_plan_get_schedule": (st, [vp, ip, dp]),
         "fse_plan_set_schedule": (st, [vp, ip]),
@@ -240,6 +241,13 @@ class Plan:
 
     def set_schedule(self, sched):
         _check(lib().fse_plan_set_schedule(self._h, _iarr(sched)))
+
+    def set_lattice(self, v=None, k=None):
+        """Optical lattice sum_j v[j] sin^2(k[j] x_j) added to the trap (fse_set_lattice); None removes it."""
+        if v is None:
+            _check(lib().fse_set_lattice(self._h, None, None))
+        else:
+            _check(lib().fse_set_lattice(self._h, _darr(v), _darr(k)))
 
     def set_potential(self, U=None):
         """Grid potential U(x~) added to the step's phase and the energy (fse_set_potential);
