@@ -213,9 +213,10 @@ def run_batch(steps, warmup=5):
     }
 
 
-def run_case(p, prec, steps, warmup=5):
+def run_case(p, prec, steps, warmup=5, keep=None):
     """Throughput of one fse_step call of `steps` steps of a named case, and the
-    drift of its invariants (mass, energy, <Lz>) over those steps."""
+    drift of its invariants (mass, energy, <Lz>) over those steps.  With keep (a
+    dict), the final state and scalars are stored there for comparison."""
     import numpy as np
     import torch
 
@@ -240,6 +241,8 @@ def run_case(p, prec, steps, warmup=5):
     torch.cuda.synchronize()
     ms = e_0.elapsed_time(e_1)
     m1, e1, l1 = plan.mass(x).item(), plan.energy(x)[5].item(), plan.angular_momentum(x).item()
+    if keep is not None:
+        keep.update(state=x.to(torch.complex128), mass=m1, energy=e1, lz=l1)
     del plan, x
     torch.cuda.empty_cache()
     return {
@@ -583,9 +586,18 @@ def main():
         for name, steps in (("dipole3d_128", 1000), ("plain2d", 100)):
             q = W.preset(name)
             print(f"[bench] case {q.name}: {steps} steps", file=sys.stderr, flush=True)
-            cases[q.name] = {"c128": run_case(q, fse.C128, steps)}
+            ref, low = {}, {}
+            cases[q.name] = {"c128": run_case(q, fse.C128, steps, keep=ref)}
             if not args.no_c64:
-                cases[q.name]["c64"] = run_case(q, fse.C64, steps)
+                cases[q.name]["c64"] = run_case(q, fse.C64, steps, keep=low)
+                # complex64 against the FP64 run of the same case (which the tests hold to the oracle)
+                d = torch.linalg.vector_norm(low["state"] - ref["state"]) / torch.linalg.vector_norm(ref["state"])
+                cases[q.name]["c64"]["error_vs_c128"] = {
+                    "state_rel_l2": float(d), "mass_abs": abs(low["mass"] - ref["mass"]),
+                    "energy_rel": abs(low["energy"] - ref["energy"]) / abs(ref["energy"]),
+                    "lz_abs": abs(low["lz"] - ref["lz"])}
+            del ref, low
+            torch.cuda.empty_cache()
     gs = None
     if args.gs_steps > 0:
         q = W.preset("gs3d_256")
