@@ -61,6 +61,15 @@ def pass_bytes(p, csize):
     """Algorithmic HBM bytes per launch of each pass kind (compulsory reads + writes)."""
     rsize = csize // 2
     n = p.npts
+    if p.kernel == "none" or p.lam == 0.0:
+        # no nonlocal term: the phase pass reads and writes the state only
+        kin = 1
+        for Nj in p.N:
+            kin *= Nj // 2 + 1
+        out = {"c2r_phase": 2 * n * csize, "kin": 2 * n * csize + kin * csize, "edge": 2 * n * csize}
+        if p.d == 3:
+            out.update(f1=2 * n * csize, i1=2 * n * csize)
+        return out
     if p.d == 3:
         N0, N1, N2 = p.N
         X1 = (N0 + 1) * N1 * N2
@@ -571,6 +580,16 @@ def main():
             "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
             "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"], "schedule": r32["schedule"],
         }
+    ql = p.replace(lam=0.0, name=p.name + "-local")
+    print(f"[bench] {ql.name}: lambda = 0", file=sys.stderr, flush=True)
+    rl = run_precision(ql, fse.C128, args.steps, args.warmup, args.prof_steps, args.tune)
+    variants["local_c128"] = {
+        "workload": "the same 256^3 step without the nonlocal term (lambda = 0)",
+        "value": rl["value"], "ms_per_step": rl["ms_per_step"], "dtype": "c128",
+        "step_hbm_frac": rl["step_hbm_frac"], "model_bytes_per_point": rl["model_bytes_per_point"],
+        "passes": rl["passes"],
+    }
+    print(f"[bench] local c128 {rl['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     print("[bench] reductions and H psi", file=sys.stderr, flush=True)
     ops = {"c128": run_ops(p, fse.C128)}
     if not args.no_c64:
