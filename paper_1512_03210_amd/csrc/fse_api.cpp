@@ -1011,10 +1011,14 @@ template <typename R> fse_status gs_apply_M(fse_plan p, const GsBuf& b, const vo
         Dx = b.Dx;
         Dy = b.Dy;
     }
-    HIPCHK(L::gs_tf(v, Dx, Dy, b.W, b.A, p->n, g, p->Omega, st));
-    fse_status s = pd_apply<R>(p, b.A, st);
-    if (s != FSE_OK) return s;
-    HIPCHK(L::gs_axpy(v, b.A, out, p->n, 1.0, 0.0, st));
+    // W v - Omega Lz v folded into the forward pass of axis 0, P_Delta's
+    // inner passes, and v + (.) folded into the inverse pass of axis 0
+    const int N0 = p->N[0], NL = p->last();
+    HIPCHK(L::gs_cols(1, N0, v, Dx, Dy, b.W, nullptr, b.A, p->C0, g, p->Omega, p->tw[N0], st));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], false, 0, b.A, b.A, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::line(NL, 1, b.A, (int)p->lines_last(), p->pd, kin_index(p), p->tw[NL], nullptr, st, p->sched[0]));
+    if (p->d == 3) HIPCHK(L::strided(p->N[1], true, 0, b.A, b.A, N0, p->N[2], p->tw[p->N[1]], nullptr, st));
+    HIPCHK(L::gs_cols(2, N0, v, nullptr, nullptr, nullptr, b.A, out, p->C0, g, 0.0, p->tw[N0], st));
     return FSE_OK;
 }
 

@@ -38,27 +38,64 @@ __global__ void k_gs_frozen(const typename CT<R>::T* __restrict__ psi, const R* 
     }
 }
 
-// u = W v - Omega Lz v, with Lz v = -i (x Dy - y Dx): u = W v + i Omega (x Dy - y Dx).
-// Dx, Dy may be null (Omega = 0).
-template <typename R>
-__global__ void k_gs_tf(const typename CT<R>::T* __restrict__ v, const typename CT<R>::T* __restrict__ Dx,
-                        const typename CT<R>::T* __restrict__ Dy, const R* __restrict__ W,
-                        typename CT<R>::T* __restrict__ u, long n, GridGeom g, double Omega) {
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double2 a = gsd::up(v[i]);
-        const double w = (double)W[i];
-        double2 o{w * a.x, w * a.y};
-        if (Dx) {
-            int i0, i1, i2;
-            decode(i, g, i0, i1, i2);
-            const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy;
-            const double2 dx = gsd::up(Dx[i]), dy = gsd::up(Dy[i]);
-            const double qx = x * dy.x - y * dx.x, qy = x * dy.y - y * dx.y;
-            o.x -= Omega * qy;
-            o.y += Omega * qx;
-        }
-        u[i] = gsd::down<R>(o);
+// The first and last passes of the preconditioned operator on the strided
+// axis 0, with the pointwise work folded in (one HBM sweep each instead of two):
+//   OP 1 (forward): A = FFT_0[W v + i Omega (x Dy - y Dx)] (Dx, Dy null when
+//        Omega = 0; W v - Omega Lz v with Lz = -i (x D_y - y D_x)), the value
+//        built in FP64 and rounded to the plan's precision;
+//   OP 2 (inverse): out = v + IFFT_0[A], the sum in FP64 as k_gs_axpy forms it.
+// Column tiles as in the plain column pass; C columns, x from the row index,
+// y from the column (c / N2 in 3D, c in 2D).
+template <typename R, int N, int OP>
+__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_gs_cols(
+    const typename CT<R>::T* __restrict__ v, const typename CT<R>::T* __restrict__ Dx,
+    const typename CT<R>::T* __restrict__ Dy, const R* __restrict__ W, const typename CT<R>::T* A,
+    typename CT<R>::T* out, int C, GridGeom g, double Omega, const typename CT<R>::T* __restrict__ twN) {
+    using T = typename CT<R>::T;
+    using Cf = ColCfg<R, N>;
+    constexpr int Wt = Cf::W, TPL = Cf::TPL;
+    constexpr int P = pitch_cols<N>(N);
+    using F = Fft<T, N, OP == 2, TPL, FwdPlan<N>>;
+    __shared__ T lds[Wt * P];
+    const int l = threadIdx.x % Wt, jt = threadIdx.x / Wt;
+    const int c = blockIdx.x * Wt + l;
+    const bool lv = c < C;
+    T* line = lds + l * P;
+    typename F::In in;
+    typename F::Out u;
+    if constexpr (OP == 1) {
+        const double y = g.y0 + ((g.d == 3) ? (c / g.N2) : c) * g.hy;
+        for_pos<N, TPL, F::R0>(jt, [&](int b, int r, int e) {
+            T a{0, 0};
+            if (lv) {
+                const long i = (long)e * C + c;
+                const double2 vv = gsd::up(v[i]);
+                const double w = (double)W[i];
+                double2 o{w * vv.x, w * vv.y};
+                if (Dx) {
+                    const double x = g.x0 + e * g.hx;
+                    const double2 dx = gsd::up(Dx[i]), dy = gsd::up(Dy[i]);
+                    o.x -= Omega * (x * dy.y - y * dx.y);
+                    o.y += Omega * (x * dy.x - y * dx.x);
+                }
+                a = gsd::down<R>(o);
+            }
+            in[b][r] = a;
+        });
+    } else {
+        for_pos<N, TPL, F::R0>(jt, [&](int b, int r, int e) { in[b][r] = lv ? A[(long)e * C + c] : T{0, 0}; });
     }
+    F::run(in, u, line, jt, twN);
+    for_pos<N, TPL, F::RK>(jt, [&](int b, int r, int e) {
+        if (!lv) return;
+        const long i = (long)e * C + c;
+        if constexpr (OP == 1) {
+            out[i] = u[b][r];
+        } else {
+            const double2 a = gsd::up(v[i]), q = gsd::up(u[b][r]);
+            out[i] = gsd::down<R>(double2{a.x + q.x, a.y + q.y});
+        }
+    });
 }
 
 // out = a + c b (c complex, FP64); out may be a.

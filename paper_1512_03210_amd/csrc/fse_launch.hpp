@@ -71,8 +71,11 @@ template <typename R> struct Launch {
                             double udt, hipStream_t st);
     static hipError_t adj_g1(void* g, const void* psi1, const void* theta, const void* q, const void* Phiq, long n,
                              double bdt, double ldt, hipStream_t st);
-    static hipError_t gs_tf(const void* v, const void* Dx, const void* Dy, const void* W, void* u, long n,
-                            const GridGeom& g, double Omega, hipStream_t st);
+    // First (op 1: pointwise operator + forward FFT of axis 0) and last (op 2: inverse FFT of
+    // axis 0 + v) passes of the preconditioned ground-state operator (k_gs_cols).
+    static hipError_t gs_cols(int op, int N0, const void* v, const void* Dx, const void* Dy, const void* W,
+                              const void* A, void* out, int C, const GridGeom& g, double Omega, const void* twN,
+                              hipStream_t st);
     static hipError_t gs_axpy(const void* a, const void* b, void* out, long n, double cr, double ci, hipStream_t st);
     static hipError_t gs_update_xr(void* x, void* r, const void* p, const void* s, const void* t, long n, double ar,
                                    double ai, double wr, double wi, hipStream_t st);
