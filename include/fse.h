@@ -119,7 +119,10 @@ fse_status fse_scratch_size(fse_plan plan, size_t* bytes);
  * frees its own (synchronising the device).  The contents are not kept across
  * calls, so the caller may reuse the memory between calls on the plan's
  * stream, but must keep it allocated while calls run.  dev_ptr = NULL returns
- * to plan-owned scratch.  FSE_ERR_ARG if too small or misaligned. */
+ * to plan-owned scratch.  FSE_ERR_ARG if too small or misaligned.  If the
+ * plan-owned scratch cannot be allocated again (FSE_ERR_NOMEM), the plan has
+ * none until a later call succeeds, and calls that need it return
+ * FSE_ERR_STATE. */
 fse_status fse_set_workspace(fse_plan plan, void* dev_ptr, size_t bytes);
 
 fse_status fse_set_time(fse_plan plan, double t);

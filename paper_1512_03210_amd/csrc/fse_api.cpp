@@ -495,9 +495,19 @@ template <typename R> const void* extra_potential(fse_plan p, double t, bool fra
     return p->lat_buf;
 }
 
+// Whether the nonlocal scratch (X1, and X2 in 3D) is in place: an allocation
+// that failed in fse_set_workspace leaves the plan without it until a later
+// call succeeds, and no kernel may then be launched on it.
+fse_status scratch_ready(const fse_plan p) {
+    if (p->nl && (!p->X1 || (p->d == 3 && !p->X2)))
+        return fail(FSE_ERR_STATE, "the plan has no scratch (fse_set_workspace failed to allocate it)");
+    return FSE_OK;
+}
+
 // Zero-padded GauSum convolution of the density held in X1 (after r2c), result back in X1.
 template <typename R> fse_status conv_passes(fse_plan p, double t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
+    if (fse_status s = scratch_ready(p); s != FSE_OK) return s;
     if (p->d == 3) {
         const int N1 = p->N[1], N2 = p->N[2];
         HIPCHK(L::strided(N1, false, 1, p->X1, p->X2, p->N[0] + 1, N2, p->tw[N1], p->tw[2 * N1], st));
@@ -519,6 +529,7 @@ fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, d
         return FSE_OK;
     }
     const int N0 = p->N[0];
+    if (fse_status s = scratch_ready(p); s != FSE_OK) return s;
     HIPCHK(L::r2c(N0, srckind, src, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
     fse_status s = conv_passes<R>(p, t, tau, st);
     if (s != FSE_OK) return s;
@@ -540,6 +551,7 @@ fse_status ensure_diag(fse_plan p) {
 template <typename R>
 fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hipStream_t st) {
     using L = fse::Launch<R>;
+    if (fse_status s = scratch_ready(p); s != FSE_OK) return s;
     double w[3] = {1.0, 0.0, 0.0};
     int nw = 1;
     if (order == 4) {
