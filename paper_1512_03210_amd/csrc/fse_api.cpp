@@ -525,7 +525,7 @@ template <typename R>
 fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, double t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     if (!p->nl) {
-        HIPCHK(hipMemsetAsync(Phi, 0, (size_t)p->n * p->rsize, st));
+        HIPCHK(fse::launch_zero(Phi, (size_t)p->n * p->rsize, st));
         return FSE_OK;
     }
     const int N0 = p->N[0];
@@ -662,7 +662,7 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
                             kRedBlocks, st));
     } else {
         // slots 0..4 unused for Lz; keep them defined
-        HIPCHK(hipMemsetAsync(p->partials, 0, sizeof(double) * kRedBlocks * 5, st));
+        HIPCHK(fse::launch_zero(p->partials, sizeof(double) * kRedBlocks * 5, st));
     }
     if (kind == 1) {
         // kinetic energy by Parseval from the spectrum (first pass out of place)
@@ -771,7 +771,7 @@ template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void
     if (s != FSE_OK) return s;
     void* B = static_cast<char*>(p->diag) + (size_t)p->n * p->csize;
     const fse::GridGeom g = geom(p);
-    HIPCHK(hipMemsetAsync(out, 0, (size_t)p->n * p->csize, st));
+    HIPCHK(fse::launch_zero(out, (size_t)p->n * p->csize, st));
     HIPCHK(deriv_axis<R>(p, 1, psi, B, st));
     HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 0, -1.0, 0, 0, 0, 0, 0, st));
     HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
@@ -853,7 +853,7 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     fse_status s = ensure_diag(p);
     if (s != FSE_OK) return s;
     void* A = p->diag;
-    HIPCHK(hipMemsetAsync(A, 0, (size_t)p->n * p->csize, st));
+    HIPCHK(fse::launch_zero(A, (size_t)p->n * p->csize, st));
     const double dt = std::isnan(p->kin_tau[1]) ? 1e-3 : p->kin_tau[1];
     const double t_keep = p->t;
     const bool prof_keep = p->prof;

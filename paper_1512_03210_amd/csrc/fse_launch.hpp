@@ -102,6 +102,9 @@ hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kin
 
 // out[0..6] = lab-frame {N, x_c, y_c, z_c, delta_x, delta_y, delta_z} from
 // the eight moment slots; (c, s) = (cos, sin) of the frame angle.
+// Zero fill of `bytes` (a multiple of 8) at p, as a kernel: unlike a runtime
+// memset it may be recorded into a captured graph like the other passes.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
                                 hipStream_t st);
 

@@ -52,6 +52,19 @@ hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kin
     return hipGetLastError();
 }
 
+__global__ void k_zero8(unsigned long long* __restrict__ p, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0ull;
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+    if (bytes % 8 != 0) return hipErrorInvalidValue;
+    const long n = (long)(bytes / 8);
+    if (n == 0) return hipSuccess;
+    const long blocks = std::min<long>((n + 255) / 256, 4096);
+    k_zero8<<<(unsigned)blocks, 256, 0, st>>>(static_cast<unsigned long long*>(p), n);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
                                 hipStream_t st) {
     k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, out);
