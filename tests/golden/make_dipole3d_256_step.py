@@ -1,0 +1,61 @@
+"""Write dipole3d_256_step1.txt: one TS2-GauSum step (eqs. tssp1-tssp3) of the
+256^3 dipolar workload, computed by the FP64 oracle, at sampled grid points.
+
+The oracle needs minutes for one step at this size (the padded convolution
+runs on a 512^3 box), too long for a test, so the test compares the library's
+step with these stored samples.  This script calls only oracle/ and the seeded
+input generators of workloads/ (no library code).
+
+Samples: 2048 points uniform over the grid and 2048 points where
+|psi0| >= 1e-2 max|psi0| (inside the condensate), from a seeded generator.
+
+Usage (about 8 minutes on one core):
+    python tests/golden/make_dipole3d_256_step.py
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import workloads as W  # noqa: E402
+from oracle import scheme  # noqa: E402
+
+OUT = os.path.join(HERE, "dipole3d_256_step1.txt")
+PRESET, SEED, STEPS, SAMPLE_SEED, NS = "dipole3d_256", 0, 1, 20261203, 2048
+
+
+def sample_indices(psi0):
+    rng = np.random.default_rng(SAMPLE_SEED)
+    n = psi0.size
+    uni = rng.choice(n, NS, replace=False)
+    a = np.abs(psi0).ravel()
+    core = np.flatnonzero(a >= 1e-2 * a.max())
+    cor = rng.choice(core, NS, replace=False)
+    return np.unique(np.concatenate([uni, cor]))
+
+
+def main():
+    p = W.preset(PRESET)
+    psi0 = W.initial_state(p, seed=SEED)
+    ref, _ = scheme.Problem.from_params(p).run(psi0, STEPS, p.dt)
+    idx = sample_indices(psi0)
+    ii = np.unravel_index(idx, p.N)
+    vals = ref.ravel()[idx]
+    with open(OUT, "w") as f:
+        f.write(f"# oracle TS2-GauSum (eqs. tssp1-tssp3), workload {PRESET}, N={p.N}, L={p.L}, s={p.s}, "
+                f"Omega={p.Omega}, beta={p.beta}, lam={p.lam}, kernel={p.kernel}, dt={p.dt}\n")
+        f.write(f"# psi0 = workloads.initial_state(seed={SEED}); steps={STEPS}; t0=0; "
+                f"written by make_dipole3d_256_step.py\n")
+        f.write("# i0 i1 i2 re im\n")
+        for a, b, c, v in zip(ii[0], ii[1], ii[2], vals):
+            f.write(f"{a} {b} {c} {float(v.real)!r} {float(v.imag)!r}\n")
+    print(f"wrote {OUT}: {idx.size} samples")
+
+
+if __name__ == "__main__":
+    main()

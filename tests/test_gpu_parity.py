@@ -6,6 +6,7 @@ printed.  Sizes span several tiles and ragged tails (odd line counts of the
 padded passes, 24-column tiles in complex64).
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -460,6 +461,39 @@ def test_full_size_fsal_split_equals_single_call():
     err = _rel(_host(a), _host(b))
     _note(f"[full] 256^3 4 steps vs 2+2: {err:.3e}")
     assert err < 1e-13
+
+
+GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dipole3d_256_step1.txt")
+
+
+def _golden_samples(path):
+    """(flat indices, complex values, header fields) of a sampled oracle fixture."""
+    rows = np.loadtxt(path, comments="#")
+    N = W.preset("dipole3d_256").N
+    idx = np.ravel_multi_index((rows[:, 0].astype(int), rows[:, 1].astype(int), rows[:, 2].astype(int)), N)
+    return idx, rows[:, 3] + 1j * rows[:, 4]
+
+
+@pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-12), (fse.C64, 1e-5)])
+def test_dipole3d_256_step_against_oracle_samples(prec, tol):
+    """One step of the benchmarked 256^3 dipolar workload, under every pass
+    schedule the tuner can choose, against the oracle's step at 4096 stored
+    points (tests/golden/make_dipole3d_256_step.py writes them)."""
+    p = W.preset("dipole3d_256")
+    idx, ref = _golden_samples(GOLDEN_256)
+    psi0 = W.initial_state(p, seed=0)
+    plan = fse.Plan.from_params(p, prec)
+    it = torch.from_numpy(idx).to("cuda:0")
+    for sched in [(k, c, o) for o in (0, 1) for c in (0, 1) for k in (0, 1)]:
+        plan.set_schedule(sched)
+        plan.time = 0.0
+        x = _dev(psi0, prec)
+        plan.step(x, 1, p.dt)
+        got = _host(x.reshape(-1)[it])
+        err = _rel(got, ref)
+        emax = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+        _note(f"[full] 256^3 step vs oracle samples prec={prec} schedule={sched}: rel {err:.3e}, max {emax:.3e}")
+        assert err < tol and emax < tol
 
 
 def test_dipole3d_128_against_oracle_two_steps():
