@@ -1,5 +1,7 @@
-"""Write dipole3d_256_step1.txt: one TS2-GauSum step (eqs. tssp1-tssp3) of the
-256^3 dipolar workload, computed by the FP64 oracle, at sampled grid points.
+"""Write dipole3d_256_step{1,2}.txt: one or two TS2-GauSum steps (eqs.
+tssp1-tssp3) of the 256^3 dipolar workload, computed by the FP64 oracle, at
+sampled grid points.  Two steps pass through the merged full-step kinetic
+junction that every inner step of a longer call uses.
 
 The oracle needs minutes for one step at this size (the padded convolution
 runs on a 512^3 box), too long for a test, so the test compares the library's
@@ -9,8 +11,8 @@ input generators of workloads/ (no library code).
 Samples: 2048 points uniform over the grid and 2048 points where
 |psi0| >= 1e-2 max|psi0| (inside the condensate), from a seeded generator.
 
-Usage (about 8 minutes on one core):
-    python tests/golden/make_dipole3d_256_step.py
+Usage (about 8 minutes per step on one core):
+    python tests/golden/make_dipole3d_256_step.py [steps]     (steps: 1 or 2, default 1)
 """
 from __future__ import annotations
 
@@ -25,8 +27,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import workloads as W  # noqa: E402
 from oracle import scheme  # noqa: E402
 
-OUT = os.path.join(HERE, "dipole3d_256_step1.txt")
-PRESET, SEED, STEPS, SAMPLE_SEED, NS = "dipole3d_256", 0, 1, 20261203, 2048
+PRESET, SEED, SAMPLE_SEED, NS = "dipole3d_256", 0, 20261203, 2048
 
 
 def sample_indices(psi0):
@@ -39,17 +40,18 @@ def sample_indices(psi0):
     return np.unique(np.concatenate([uni, cor]))
 
 
-def main():
+def main(steps=1):
+    OUT = os.path.join(HERE, f"dipole3d_256_step{steps}.txt")
     p = W.preset(PRESET)
     psi0 = W.initial_state(p, seed=SEED)
-    ref, _ = scheme.Problem.from_params(p).run(psi0, STEPS, p.dt)
+    ref, _ = scheme.Problem.from_params(p).run(psi0, steps, p.dt)
     idx = sample_indices(psi0)
     ii = np.unravel_index(idx, p.N)
     vals = ref.ravel()[idx]
     with open(OUT, "w") as f:
         f.write(f"# oracle TS2-GauSum (eqs. tssp1-tssp3), workload {PRESET}, N={p.N}, L={p.L}, s={p.s}, "
                 f"Omega={p.Omega}, beta={p.beta}, lam={p.lam}, kernel={p.kernel}, dt={p.dt}\n")
-        f.write(f"# psi0 = workloads.initial_state(seed={SEED}); steps={STEPS}; t0=0; "
+        f.write(f"# psi0 = workloads.initial_state(seed={SEED}); steps={steps}; t0=0; "
                 f"written by make_dipole3d_256_step.py\n")
         f.write("# i0 i1 i2 re im\n")
         for a, b, c, v in zip(ii[0], ii[1], ii[2], vals):
@@ -58,4 +60,4 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1)

@@ -1,19 +1,24 @@
 """Stored oracle fixtures under tests/golden/ stay consistent with the workloads they were written for.
 
-dipole3d_256_step1.txt holds the FP64 oracle's TS2-GauSum step (eqs. tssp1-tssp3) of the 256^3 dipolar
-workload at sampled points (tests/golden/make_dipole3d_256_step.py writes it; the GPU parity suite compares
-the library's step there).  If the workload's parameters or initial state change, the fixture must be
-written again: these checks fail first.
+dipole3d_256_step1.txt and dipole3d_256_step2.txt hold one and two of the FP64 oracle's TS2-GauSum steps
+(eqs. tssp1-tssp3) of the 256^3 dipolar workload at sampled points; tests/golden/make_dipole3d_256_step.py
+writes them and the GPU parity suite compares the library's steps there.  If the workload's parameters or
+initial state change, the fixtures must be written again: these checks fail first.
 """
 import os
 import re
 
 import numpy as np
+import pytest
 
 import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-PATH = os.path.join(GOLDEN, "dipole3d_256_step1.txt")
+STEPS = [1, 2]
+
+
+def _path(steps):
+    return os.path.join(GOLDEN, f"dipole3d_256_step{steps}.txt")
 
 
 def _header(path):
@@ -22,26 +27,28 @@ def _header(path):
     return " ".join(lines)
 
 
-def test_fixture_records_the_current_workload():
+@pytest.mark.parametrize("steps", STEPS)
+def test_fixture_records_the_current_workload(steps):
     p = W.preset("dipole3d_256")
-    h = _header(PATH)
+    h = _header(_path(steps))
     for key, val in [("N", p.N), ("L", p.L), ("s", p.s), ("Omega", p.Omega), ("beta", p.beta), ("lam", p.lam),
                      ("kernel", p.kernel), ("dt", p.dt)]:
         assert f"{key}={val}" in h, (key, val, h)
-    assert re.search(r"initial_state\(seed=0\); steps=1; t0=0", h)
+    assert re.search(rf"initial_state\(seed=0\); steps={steps}; t0=0", h)
 
 
-def test_fixture_samples_are_distinct_finite_and_cover_the_condensate():
+@pytest.mark.parametrize("steps", STEPS)
+def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(steps):
     p = W.preset("dipole3d_256")
-    r = np.loadtxt(PATH, comments="#")
+    r = np.loadtxt(_path(steps), comments="#")
     assert r.shape == (4096, 5) or (r.shape[1] == 5 and 4000 <= r.shape[0] <= 4096)
     ijk = r[:, :3].astype(int)
     assert np.all(ijk >= 0) and np.all(ijk < np.array(p.N))
     assert len({tuple(x) for x in ijk}) == r.shape[0]
     v = r[:, 3] + 1j * r[:, 4]
     assert np.all(np.isfinite(v))
-    # the condensate half of the samples carries most of the mass; a step of
-    # size dt changes |psi| there by far less than its size
+    # the condensate half of the samples carries most of the mass; a step or two
+    # of size dt change |psi| there by far less than its size
     psi0 = W.initial_state(p, seed=0)
     a0 = np.abs(psi0[ijk[:, 0], ijk[:, 1], ijk[:, 2]])
     core = a0 >= 1e-2 * np.abs(psi0).max()

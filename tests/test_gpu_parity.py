@@ -463,24 +463,26 @@ def test_full_size_fsal_split_equals_single_call():
     assert err < 1e-13
 
 
-GOLDEN_256 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "dipole3d_256_step1.txt")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def _golden_samples(path):
-    """(flat indices, complex values, header fields) of a sampled oracle fixture."""
+    """(flat indices, complex values) of a sampled oracle fixture of the 256^3 workload."""
     rows = np.loadtxt(path, comments="#")
     N = W.preset("dipole3d_256").N
     idx = np.ravel_multi_index((rows[:, 0].astype(int), rows[:, 1].astype(int), rows[:, 2].astype(int)), N)
     return idx, rows[:, 3] + 1j * rows[:, 4]
 
 
+@pytest.mark.parametrize("steps", [1, 2])
 @pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-12), (fse.C64, 1e-5)])
-def test_dipole3d_256_step_against_oracle_samples(prec, tol):
-    """One step of the benchmarked 256^3 dipolar workload, under every pass
-    schedule the tuner can choose, against the oracle's step at 4096 stored
-    points (tests/golden/make_dipole3d_256_step.py writes them)."""
+def test_dipole3d_256_steps_against_oracle_samples(steps, prec, tol):
+    """One and two steps of the benchmarked 256^3 dipolar workload (two steps
+    pass through the merged full-step kinetic junction of every inner step),
+    under every pass schedule the tuner can choose, against the oracle at 4096
+    stored points (tests/golden/make_dipole3d_256_step.py writes them)."""
     p = W.preset("dipole3d_256")
-    idx, ref = _golden_samples(GOLDEN_256)
+    idx, ref = _golden_samples(os.path.join(GOLDEN, f"dipole3d_256_step{steps}.txt"))
     psi0 = W.initial_state(p, seed=0)
     plan = fse.Plan.from_params(p, prec)
     it = torch.from_numpy(idx).to("cuda:0")
@@ -488,11 +490,12 @@ def test_dipole3d_256_step_against_oracle_samples(prec, tol):
         plan.set_schedule(sched)
         plan.time = 0.0
         x = _dev(psi0, prec)
-        plan.step(x, 1, p.dt)
+        plan.step(x, steps, p.dt)
         got = _host(x.reshape(-1)[it])
         err = _rel(got, ref)
         emax = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        _note(f"[full] 256^3 step vs oracle samples prec={prec} schedule={sched}: rel {err:.3e}, max {emax:.3e}")
+        _note(f"[full] 256^3 {steps} step(s) vs oracle samples prec={prec} schedule={sched}: "
+              f"rel {err:.3e}, max {emax:.3e}")
         assert err < tol and emax < tol
 
 
