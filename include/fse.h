@@ -134,6 +134,25 @@ fse_status fse_get_time(fse_plan plan, double* t);
  * dt may be negative (backward in time); nsteps >= 0.  t += nsteps*dt. */
 fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
+/* Optional numeric guard (failure detection; the paper has none).  With
+ * tol > 0, every fse_step and fse_step4 call ends with an FP64 mass reduction
+ * of its result on the call's stream, compared on the device with the mass
+ * at the first guarded call: a non-finite mass or a relative change above tol
+ * trips the guard.  The outcome reaches the host behind an event: a later
+ * fse_step or fse_step4 call that finds the check completed and tripped
+ * returns FSE_ERR_NUMERIC without launching anything, and so does every such
+ * call after it until fse_set_guard is called again.  fse_set_guard
+ * synchronises the device and resets the reference mass and the flag;
+ * tol <= 0 turns the guard off (the default).  Each guarded call reads the
+ * state once more and copies 24 bytes to pinned host memory (not meant for
+ * graph capture).  FSE_ERR_ARG if tol is not finite. */
+fse_status fse_set_guard(fse_plan plan, double tol);
+
+/* Waits for the last guarded call's check.  *tripped = 1 if the guard has
+ * tripped; masses (nullable, 2 doubles): the reference mass and the mass of
+ * the last completed check (NaN before the first check). */
+fse_status fse_guard_status(fse_plan plan, int* tripped, double* masses);
+
 /* nsteps fourth-order steps of size dt, in place on psi: each step is the
  * symmetric triple-jump composition of TS2-GauSum steps of lengths w1 dt,
  * w0 dt, w1 dt, w1 = 1/(2 - 2^{1/3}), w0 = 1 - 2 w1 < 0 (the paper notes

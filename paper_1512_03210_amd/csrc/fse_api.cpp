@@ -121,6 +121,14 @@ struct fse_plan_s {
     double pd_c0 = NAN;
     void* ks = nullptr;    // kinetic symbol omega/2 / n (layout of the kinetic tables), built on first use
     double* partials = nullptr;
+    // numeric guard (fse_set_guard): guard_dev = {M0 (NaN until the first
+    // check), M of the last check, tripped flag}; guard_host is its pinned
+    // copy, read only once guard_ev has completed
+    double guard_tol = 0.0;
+    double* guard_dev = nullptr;
+    double* guard_host = nullptr;
+    hipEvent_t guard_ev = nullptr;
+    bool guard_pending = false, guard_tripped = false;
     size_t bytes = 0;
     std::vector<void*> allocs;
     // profiling: event pairs recorded around launches, by pass kind
@@ -794,6 +802,35 @@ template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void
 std::mutex g_tune_mu;
 std::map<std::string, std::array<int, 3>> g_tune_cache;
 
+// Numeric guard.  guard_poll: the outcome of the last completed check, without
+// waiting (a check still running is looked at by a later call).  guard_check:
+// after a step call, the mass of the result against the reference, on the
+// stream, and a copy of the outcome to pinned memory behind guard_ev.
+fse_status guard_poll(fse_plan p) {
+    if (p->guard_pending && hipEventQuery(p->guard_ev) == hipSuccess) {
+        p->guard_pending = false;
+        if (p->guard_host[2] != 0.0) p->guard_tripped = true;
+    }
+    if (p->guard_tripped)
+        return fail(FSE_ERR_NUMERIC,
+                    "numeric guard: mass %.17g against %.17g at the first guarded call (relative tolerance %g); "
+                    "fse_set_guard resets it",
+                    p->guard_host[1], p->guard_host[0], p->guard_tol);
+    return FSE_OK;
+}
+
+fse_status guard_check(fse_plan p, const void* psi, hipStream_t st) {
+    if (p->guard_tol <= 0.0) return FSE_OK;
+    fse_status s = (p->prec == FSE_C128) ? reduce_impl<double>(p, psi, 0, p->guard_dev + 1, st)
+                                         : reduce_impl<float>(p, psi, 0, p->guard_dev + 1, st);
+    if (s != FSE_OK) return s;
+    HIPCHK(fse::launch_guard(p->guard_dev, p->guard_tol, st));
+    HIPCHK(hipMemcpyAsync(p->guard_host, p->guard_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(p->guard_ev, st));
+    p->guard_pending = true;
+    return FSE_OK;
+}
+
 std::string tune_key(const fse_plan p) {
     int dev = 0;
     hipDeviceProp_t prop{};
@@ -1174,6 +1211,8 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
 void destroy(fse_plan p) {
     if (!p) return;
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
+    if (p->guard_ev) (void)hipEventDestroy(p->guard_ev);
+    if (p->guard_host) (void)hipHostFree(p->guard_host);
     for (void* a : p->allocs) (void)hipFree(a);
     delete p;
 }
@@ -1498,15 +1537,59 @@ fse_status fse_get_time(fse_plan plan, double* t) {
     return FSE_OK;
 }
 
+fse_status fse_set_guard(fse_plan plan, double tol) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    if (!std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite");
+    if (tol > 0.0 && !plan->guard_dev) {
+        fse_status s = dev_alloc(plan, reinterpret_cast<void**>(&plan->guard_dev), 3 * sizeof(double));
+        if (s != FSE_OK) return s;
+        if (hipHostMalloc(reinterpret_cast<void**>(&plan->guard_host), 3 * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess)
+            return fail(FSE_ERR_NOMEM, "hipHostMalloc for the guard");
+        if (hipEventCreateWithFlags(&plan->guard_ev, hipEventDisableTiming) != hipSuccess)
+            return fail(FSE_ERR_HIP, "hipEventCreate for the guard");
+    }
+    if (plan->guard_dev) {
+        // no check may still be writing the buffers that are reset here
+        if (hipDeviceSynchronize() != hipSuccess) return fail(FSE_ERR_HIP, "hipDeviceSynchronize");
+        const double init[3] = {NAN, NAN, 0.0};
+        if (hipMemcpy(plan->guard_dev, init, sizeof(init), hipMemcpyHostToDevice) != hipSuccess)
+            return fail(FSE_ERR_HIP, "hipMemcpy");
+        std::memcpy(plan->guard_host, init, sizeof(init));
+    }
+    plan->guard_tol = tol > 0.0 ? tol : 0.0;
+    plan->guard_pending = plan->guard_tripped = false;
+    return FSE_OK;
+}
+
+fse_status fse_guard_status(fse_plan plan, int* tripped, double* masses) {
+    g_err.clear();
+    if (!plan || !tripped) return fail(FSE_ERR_ARG, "plan and tripped must not be NULL");
+    if (plan->guard_pending) {
+        if (hipEventSynchronize(plan->guard_ev) != hipSuccess) return fail(FSE_ERR_HIP, "hipEventSynchronize");
+        plan->guard_pending = false;
+        if (plan->guard_host[2] != 0.0) plan->guard_tripped = true;
+    }
+    *tripped = plan->guard_tripped ? 1 : 0;
+    if (masses) {
+        masses[0] = plan->guard_host ? plan->guard_host[0] : NAN;
+        masses[1] = plan->guard_host ? plan->guard_host[1] : NAN;
+    }
+    return FSE_OK;
+}
+
 fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream) {
     g_err.clear();
     if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
     if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
     if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
+    if (fse_status s = guard_poll(plan); s != FSE_OK) return s;
     if (nsteps == 0) return FSE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 2, st)
-                                  : step_impl<float>(plan, psi, nsteps, dt, 2, st);
+    fse_status s = plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 2, st)
+                                          : step_impl<float>(plan, psi, nsteps, dt, 2, st);
+    return s == FSE_OK ? guard_check(plan, psi, st) : s;
 }
 
 fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream) {
@@ -1514,10 +1597,12 @@ fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stre
     if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
     if (nsteps < 0) return fail(FSE_ERR_ARG, "nsteps must be >= 0");
     if (!std::isfinite(dt) || dt == 0.0) return fail(FSE_ERR_ARG, "dt must be finite and non-zero");
+    if (fse_status s = guard_poll(plan); s != FSE_OK) return s;
     if (nsteps == 0) return FSE_OK;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    return plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 4, st)
-                                  : step_impl<float>(plan, psi, nsteps, dt, 4, st);
+    fse_status s = plan->prec == FSE_C128 ? step_impl<double>(plan, psi, nsteps, dt, 4, st)
+                                          : step_impl<float>(plan, psi, nsteps, dt, 4, st);
+    return s == FSE_OK ? guard_check(plan, psi, st) : s;
 }
 
 fse_status fse_apply_H(fse_plan plan, const void* psi, void* Hpsi, const void* rho_frozen, void* stream) {

@@ -105,6 +105,9 @@ hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kin
 // Zero fill of `bytes` (a multiple of 8) at p, as a kernel: unlike a runtime
 // memset it may be recorded into a captured graph like the other passes.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+// Numeric guard: g = {M0, M, flag}.  M0 = M if M0 is NaN (first check); flag
+// = 1 if M or M0 is not finite or |M - M0| > tol |M0| (the flag stays set).
+hipError_t launch_guard(double* g, double tol, hipStream_t st);
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
                                 hipStream_t st);
 

@@ -65,6 +65,20 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
+__global__ void k_guard(double* g, double tol) {
+    if (threadIdx.x == 0) {
+        const double m = g[1];
+        if (isnan(g[0])) g[0] = m;
+        const double m0 = g[0];
+        if (!isfinite(m) || !isfinite(m0) || fabs(m - m0) > tol * fabs(m0)) g[2] = 1.0;
+    }
+}
+
+hipError_t launch_guard(double* g, double tol, hipStream_t st) {
+    k_guard<<<1, 64, 0, st>>>(g, tol);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
                                 hipStream_t st) {
     k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, out);

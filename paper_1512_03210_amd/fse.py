@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("FSE_LIB", os.path.join(_PKG, "libfse.so"))
 FSE_OK = 0
 STATUS = {0: "FSE_OK", -1: "FSE_ERR_ARG", -2: "FSE_ERR_UNSUPPORTED", -3: "FSE_ERR_NOMEM",
           -4: "FSE_ERR_HIP", -5: "FSE_ERR_NUMERIC", -6: "FSE_ERR_STATE"}
+STATUS_CODES = {name: code for code, name in STATUS.items()}
 C128, C64 = 0, 1
 K_NONE, K_COULOMB, K_DDI3, K_DDI2 = 0, 1, 2, 3
 KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_DDI2}
@@ -32,7 +33,7 @@ EXPORTS = [
     "fse_mass", "fse_energy", "fse_angular_momentum", "fse_moments", "fse_gausum_symbol_host",
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
-    "fse_batch_reduce", "fse_batch_times", "fse_gs_step",
+    "fse_batch_reduce", "fse_batch_times", "fse_gs_step", "fse_set_guard", "fse_guard_status",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -84,6 +85,8 @@ def lib():
         "fse_get_time": (st, [vp, dp]),
         "fse_step": (st, [vp, vp, i, d, vp]),
         "fse_step4": (st, [vp, vp, i, d, vp]),
+        "fse_set_guard": (st, [vp, d]),
+        "fse_guard_status": (st, [vp, ip, dp]),
         "fse_set_potential": (st, [vp, vp]),
         "fse_set_lattice": (st, [vp, dp, dp]),
         "fse_plan_tune": (st, [vp, ctypes.c_char_p, vp]),
@@ -286,6 +289,19 @@ class Plan:
     @time.setter
     def time(self, t: float):
         _check(lib().fse_set_time(self._h, float(t)))
+
+    def set_guard(self, tol: float = 0.0):
+        """Numeric guard (fse_set_guard): with tol > 0 every step call ends with a device-side mass check
+        against the mass at the first guarded call; a later step call raises FseError (FSE_ERR_NUMERIC)
+        once a check has failed.  Resets the reference mass and the flag; tol <= 0 turns it off."""
+        _check(lib().fse_set_guard(self._h, float(tol)))
+
+    def guard_status(self):
+        """(tripped, reference mass, mass at the last completed check), waiting for the last check."""
+        t = ctypes.c_int()
+        m = (ctypes.c_double * 2)()
+        _check(lib().fse_guard_status(self._h, ctypes.byref(t), m))
+        return bool(t.value), float(m[0]), float(m[1])
 
     def workspace_bytes(self) -> int:
         b = ctypes.c_size_t()
