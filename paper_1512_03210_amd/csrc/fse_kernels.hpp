@@ -89,10 +89,15 @@ template <typename R, int N, bool CONV, int V = 0> struct LineCfg {
     static constexpr int TPL0 = N / Head<LineFwd<N, V>>::value;
     static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 > 64 ? 64 : TPL0);
     static constexpr int SUB = CONV ? 2 : 1;  // LDS sub-lines (and thread groups) per data line
-    static constexpr int BUDGET = 40960 / (P * (int)sizeof(T) * SUB);
+    // LDS per workgroup aimed at: small workgroups (down to one wavefront)
+    // strand less of the 160 KB per CU than a few large ones (FP64 256^3:
+    // convolution 16 -> 17 lines per CU, kinetic pass 8 -> 9; both ~2.5 %
+    // faster than with a 40 KB budget)
+    static constexpr int BUDGET = 10240 / (P * (int)sizeof(T) * SUB);
     static constexpr int LPB0 = floor_pow2(BUDGET < 1 ? 1 : BUDGET);
     static constexpr int LPB1 = (LPB0 * TPL * SUB > 256) ? 256 / (TPL * SUB) : LPB0;
-    static constexpr int LPB = LPB1 < 1 ? 1 : LPB1;
+    static constexpr int LPBW = (TPL * SUB >= 64) ? 1 : 64 / (TPL * SUB);  // at least one full wavefront
+    static constexpr int LPB = LPB1 < LPBW ? LPBW : LPB1;
     static constexpr int NTH = LPB * TPL * SUB;
 };
 
