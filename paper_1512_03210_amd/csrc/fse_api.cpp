@@ -1541,16 +1541,23 @@ fse_status fse_set_guard(fse_plan plan, double tol) {
     g_err.clear();
     if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
     if (!std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite");
-    if (tol > 0.0 && !plan->guard_dev) {
-        fse_status s = dev_alloc(plan, reinterpret_cast<void**>(&plan->guard_dev), 3 * sizeof(double));
-        if (s != FSE_OK) return s;
-        if (hipHostMalloc(reinterpret_cast<void**>(&plan->guard_host), 3 * sizeof(double), hipHostMallocDefault) !=
-            hipSuccess)
+    if (tol > 0.0) {  // each resource on its own, so that a call after a failed one completes the set
+        if (!plan->guard_dev) {
+            fse_status s = dev_alloc(plan, reinterpret_cast<void**>(&plan->guard_dev), 3 * sizeof(double));
+            if (s != FSE_OK) return s;
+        }
+        if (!plan->guard_host &&
+            hipHostMalloc(reinterpret_cast<void**>(&plan->guard_host), 3 * sizeof(double), hipHostMallocDefault) !=
+                hipSuccess) {
+            plan->guard_host = nullptr;
             return fail(FSE_ERR_NOMEM, "hipHostMalloc for the guard");
-        if (hipEventCreateWithFlags(&plan->guard_ev, hipEventDisableTiming) != hipSuccess)
+        }
+        if (!plan->guard_ev && hipEventCreateWithFlags(&plan->guard_ev, hipEventDisableTiming) != hipSuccess) {
+            plan->guard_ev = nullptr;
             return fail(FSE_ERR_HIP, "hipEventCreate for the guard");
+        }
     }
-    if (plan->guard_dev) {
+    if (plan->guard_dev && plan->guard_host) {
         // no check may still be writing the buffers that are reset here
         if (hipDeviceSynchronize() != hipSuccess) return fail(FSE_ERR_HIP, "hipDeviceSynchronize");
         const double init[3] = {NAN, NAN, 0.0};
