@@ -1,0 +1,43 @@
+"""Checkpoint files round-trip exactly (host side; no GPU needed)."""
+import dataclasses
+import os
+
+import pytest
+
+import workloads as W
+
+torch = pytest.importorskip("torch")
+
+from paper_1512_03210_amd import checkpoint, fse  # noqa: E402
+
+
+@pytest.mark.parametrize("prec,dtype", [(fse.C128, torch.complex128), (fse.C64, torch.complex64)])
+def test_save_load_round_trip_is_exact(tmp_path, prec, dtype):
+    p = W.preset("plain2d")
+    psi = torch.from_numpy(W.harmonic_vortex_2d(p.N, p.L, seed=4)).to(dtype)
+    prefix = os.path.join(tmp_path, "ck")
+    checkpoint.save(prefix, p, psi, 0.125, prec)
+    pd, back, t, pr = checkpoint.load(prefix, device="cpu")
+    assert back.dtype == dtype and torch.equal(back, psi)
+    assert t == 0.125 and pr == prec
+    want = {k: list(v) if isinstance(v, tuple) else v for k, v in dataclasses.asdict(p).items()}
+    assert pd == want
+
+
+def test_save_rejects_a_state_of_the_wrong_precision(tmp_path):
+    p = W.preset("plain2d")
+    psi = torch.zeros(p.N, dtype=torch.complex64)
+    with pytest.raises(ValueError):
+        checkpoint.save(os.path.join(tmp_path, "ck"), p, psi, 0.0, fse.C128)
+
+
+def test_load_checks_the_stored_shape(tmp_path):
+    p = W.preset("plain2d")
+    prefix = os.path.join(tmp_path, "ck")
+    checkpoint.save(prefix, p, torch.zeros(p.N, dtype=torch.complex128), 0.0, fse.C128)
+    import json
+    meta = json.load(open(prefix + ".json"))
+    meta["shape"] = [1, 2]
+    json.dump(meta, open(prefix + ".json", "w"))
+    with pytest.raises(ValueError):
+        checkpoint.load(prefix, device="cpu")
