@@ -1,7 +1,9 @@
 """Write dipole3d_256_step{1,2}.txt: one or two TS2-GauSum steps (eqs.
 tssp1-tssp3) of the 256^3 dipolar workload, computed by the FP64 oracle, at
 sampled grid points.  Two steps pass through the merged full-step kinetic
-junction that every inner step of a longer call uses.
+junction that every inner step of a longer call uses.  With order 4,
+dipole3d_256_order4_step1.txt: one fourth-order step (the symmetric
+triple-jump composition of TS2 steps of lengths w1 dt, w0 dt, w1 dt).
 
 The oracle needs minutes for one step at this size (the padded convolution
 runs on a 512^3 box), too long for a test, so the test compares the library's
@@ -12,7 +14,7 @@ Samples: 2048 points uniform over the grid and 2048 points where
 |psi0| >= 1e-2 max|psi0| (inside the condensate), from a seeded generator.
 
 Usage (about 8 minutes per step on one core):
-    python tests/golden/make_dipole3d_256_step.py [steps]     (steps: 1 or 2, default 1)
+    python tests/golden/make_dipole3d_256_step.py [steps] [order]     (steps 1 or 2, order 2 or 4; default 1 2)
 """
 from __future__ import annotations
 
@@ -40,18 +42,20 @@ def sample_indices(psi0):
     return np.unique(np.concatenate([uni, cor]))
 
 
-def main(steps=1):
-    OUT = os.path.join(HERE, f"dipole3d_256_step{steps}.txt")
+def main(steps=1, order=2):
+    name = f"dipole3d_256_step{steps}.txt" if order == 2 else f"dipole3d_256_order{order}_step{steps}.txt"
+    OUT = os.path.join(HERE, name)
     p = W.preset(PRESET)
     psi0 = W.initial_state(p, seed=SEED)
-    ref, _ = scheme.Problem.from_params(p).run(psi0, steps, p.dt)
+    prob = scheme.Problem.from_params(p)
+    ref, _ = prob.run(psi0, steps, p.dt) if order == 2 else prob.run4(psi0, steps, p.dt)
     idx = sample_indices(psi0)
     ii = np.unravel_index(idx, p.N)
     vals = ref.ravel()[idx]
     with open(OUT, "w") as f:
         f.write(f"# oracle TS2-GauSum (eqs. tssp1-tssp3), workload {PRESET}, N={p.N}, L={p.L}, s={p.s}, "
                 f"Omega={p.Omega}, beta={p.beta}, lam={p.lam}, kernel={p.kernel}, dt={p.dt}\n")
-        f.write(f"# psi0 = workloads.initial_state(seed={SEED}); steps={steps}; t0=0; "
+        f.write(f"# psi0 = workloads.initial_state(seed={SEED}); steps={steps}; order={order}; t0=0; "
                 f"written by make_dipole3d_256_step.py\n")
         f.write("# i0 i1 i2 re im\n")
         for a, b, c, v in zip(ii[0], ii[1], ii[2], vals):
@@ -60,4 +64,4 @@ def main(steps=1):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, int(sys.argv[2]) if len(sys.argv) > 2 else 2)

@@ -1,8 +1,9 @@
 """Stored oracle fixtures under tests/golden/ stay consistent with the workloads they were written for.
 
 dipole3d_256_step1.txt and dipole3d_256_step2.txt hold one and two of the FP64 oracle's TS2-GauSum steps
-(eqs. tssp1-tssp3) of the 256^3 dipolar workload at sampled points; tests/golden/make_dipole3d_256_step.py
-writes them and the GPU parity suite compares the library's steps there.  If the workload's parameters or
+(eqs. tssp1-tssp3) of the 256^3 dipolar workload at sampled points, dipole3d_256_order4_step1.txt one
+fourth-order step; tests/golden/make_dipole3d_256_step.py writes them and the GPU parity suite compares the
+library's steps there.  If the workload's parameters or
 initial state change, the fixtures must be written again: these checks fail first.
 """
 import os
@@ -14,11 +15,13 @@ import pytest
 import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-STEPS = [1, 2]
+# (file, steps, order)
+FIXTURES = [("dipole3d_256_step1.txt", 1, 2), ("dipole3d_256_step2.txt", 2, 2),
+            ("dipole3d_256_order4_step1.txt", 1, 4)]
 
 
-def _path(steps):
-    return os.path.join(GOLDEN, f"dipole3d_256_step{steps}.txt")
+def _path(name):
+    return os.path.join(GOLDEN, name)
 
 
 def _header(path):
@@ -27,20 +30,21 @@ def _header(path):
     return " ".join(lines)
 
 
-@pytest.mark.parametrize("steps", STEPS)
-def test_fixture_records_the_current_workload(steps):
+@pytest.mark.parametrize("name,steps,order", FIXTURES)
+def test_fixture_records_the_current_workload(name, steps, order):
     p = W.preset("dipole3d_256")
-    h = _header(_path(steps))
+    h = _header(_path(name))
     for key, val in [("N", p.N), ("L", p.L), ("s", p.s), ("Omega", p.Omega), ("beta", p.beta), ("lam", p.lam),
                      ("kernel", p.kernel), ("dt", p.dt)]:
         assert f"{key}={val}" in h, (key, val, h)
-    assert re.search(rf"initial_state\(seed=0\); steps={steps}; t0=0", h)
+    order_field = rf" order={order};" if order != 2 else r"( order=2;)?"
+    assert re.search(rf"initial_state\(seed=0\); steps={steps};{order_field} t0=0", h)
 
 
-@pytest.mark.parametrize("steps", STEPS)
-def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(steps):
+@pytest.mark.parametrize("name,steps,order", FIXTURES)
+def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(name, steps, order):
     p = W.preset("dipole3d_256")
-    r = np.loadtxt(_path(steps), comments="#")
+    r = np.loadtxt(_path(name), comments="#")
     assert r.shape == (4096, 5) or (r.shape[1] == 5 and 4000 <= r.shape[0] <= 4096)
     ijk = r[:, :3].astype(int)
     assert np.all(ijk >= 0) and np.all(ijk < np.array(p.N))

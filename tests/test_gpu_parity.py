@@ -474,15 +474,17 @@ def _golden_samples(path):
     return idx, rows[:, 3] + 1j * rows[:, 4]
 
 
-@pytest.mark.parametrize("steps", [1, 2])
+@pytest.mark.parametrize("name,steps,order", [("dipole3d_256_step1.txt", 1, 2), ("dipole3d_256_step2.txt", 2, 2),
+                                              ("dipole3d_256_order4_step1.txt", 1, 4)])
 @pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-12), (fse.C64, 1e-5)])
-def test_dipole3d_256_steps_against_oracle_samples(steps, prec, tol):
-    """One and two steps of the benchmarked 256^3 dipolar workload (two steps
-    pass through the merged full-step kinetic junction of every inner step),
-    under every pass schedule the tuner can choose, against the oracle at 4096
-    stored points (tests/golden/make_dipole3d_256_step.py writes them)."""
+def test_dipole3d_256_steps_against_oracle_samples(name, steps, order, prec, tol):
+    """One and two TS2 steps and one fourth-order step of the benchmarked
+    256^3 dipolar workload (two steps pass through the merged full-step
+    kinetic junction of every inner step), under every pass schedule the
+    tuner can choose, against the oracle at 4096 stored points
+    (tests/golden/make_dipole3d_256_step.py writes them)."""
     p = W.preset("dipole3d_256")
-    idx, ref = _golden_samples(os.path.join(GOLDEN, f"dipole3d_256_step{steps}.txt"))
+    idx, ref = _golden_samples(os.path.join(GOLDEN, name))
     psi0 = W.initial_state(p, seed=0)
     plan = fse.Plan.from_params(p, prec)
     it = torch.from_numpy(idx).to("cuda:0")
@@ -490,11 +492,11 @@ def test_dipole3d_256_steps_against_oracle_samples(steps, prec, tol):
         plan.set_schedule(sched)
         plan.time = 0.0
         x = _dev(psi0, prec)
-        plan.step(x, steps, p.dt)
+        plan.step(x, steps, p.dt, order=order)
         got = _host(x.reshape(-1)[it])
         err = _rel(got, ref)
         emax = float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
-        _note(f"[full] 256^3 {steps} step(s) vs oracle samples prec={prec} schedule={sched}: "
+        _note(f"[full] 256^3 {steps} step(s) of order {order} vs oracle samples prec={prec} schedule={sched}: "
               f"rel {err:.3e}, max {emax:.3e}")
         assert err < tol and emax < tol
 
