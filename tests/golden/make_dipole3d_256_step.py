@@ -3,7 +3,9 @@ tssp1-tssp3) of the 256^3 dipolar workload, computed by the FP64 oracle, at
 sampled grid points.  Two steps pass through the merged full-step kinetic
 junction that every inner step of a longer call uses.  With order 4,
 dipole3d_256_order4_step1.txt: one fourth-order step (the symmetric
-triple-jump composition of TS2 steps of lengths w1 dt, w0 dt, w1 dt).
+triple-jump composition of TS2 steps of lengths w1 dt, w0 dt, w1 dt).  With
+"local", dipole3d_256_local_step{n}.txt: the same workload with lam = 0 (no
+nonlocal term).
 
 The oracle needs minutes for one step at this size (the padded convolution
 runs on a 512^3 box), too long for a test, so the test compares the library's
@@ -14,7 +16,7 @@ Samples: 2048 points uniform over the grid and 2048 points where
 |psi0| >= 1e-2 max|psi0| (inside the condensate), from a seeded generator.
 
 Usage (about 8 minutes per step on one core):
-    python tests/golden/make_dipole3d_256_step.py [steps] [order]     (steps 1 or 2, order 2 or 4; default 1 2)
+    python tests/golden/make_dipole3d_256_step.py [steps] [order] [local]   (steps 1 or 2, order 2 or 4; default 1 2)
 """
 from __future__ import annotations
 
@@ -42,10 +44,12 @@ def sample_indices(psi0):
     return np.unique(np.concatenate([uni, cor]))
 
 
-def main(steps=1, order=2):
-    name = f"dipole3d_256_step{steps}.txt" if order == 2 else f"dipole3d_256_order{order}_step{steps}.txt"
-    OUT = os.path.join(HERE, name)
+def main(steps=1, order=2, local=False):
+    tag = "_local" if local else ("" if order == 2 else f"_order{order}")
+    OUT = os.path.join(HERE, f"dipole3d_256{tag}_step{steps}.txt")
     p = W.preset(PRESET)
+    if local:
+        p = p.replace(lam=0.0)
     psi0 = W.initial_state(p, seed=SEED)
     prob = scheme.Problem.from_params(p)
     ref, _ = prob.run(psi0, steps, p.dt) if order == 2 else prob.run4(psi0, steps, p.dt)
@@ -64,4 +68,5 @@ def main(steps=1, order=2):
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, int(sys.argv[2]) if len(sys.argv) > 2 else 2)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, int(sys.argv[2]) if len(sys.argv) > 2 else 2,
+         len(sys.argv) > 3 and sys.argv[3] == "local")

@@ -2,7 +2,8 @@
 
 dipole3d_256_step1.txt and dipole3d_256_step2.txt hold one and two of the FP64 oracle's TS2-GauSum steps
 (eqs. tssp1-tssp3) of the 256^3 dipolar workload at sampled points, dipole3d_256_order4_step1.txt one
-fourth-order step; tests/golden/make_dipole3d_256_step.py writes them and the GPU parity suite compares the
+fourth-order step, dipole3d_256_local_step{1,2}.txt the same workload with lam = 0;
+tests/golden/make_dipole3d_256_step.py writes them and the GPU parity suite compares the
 library's steps there.  If the workload's parameters or
 initial state change, the fixtures must be written again: these checks fail first.
 """
@@ -15,9 +16,15 @@ import pytest
 import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-# (file, steps, order)
-FIXTURES = [("dipole3d_256_step1.txt", 1, 2), ("dipole3d_256_step2.txt", 2, 2),
-            ("dipole3d_256_order4_step1.txt", 1, 4)]
+# (file, steps, order, local)
+FIXTURES = [("dipole3d_256_step1.txt", 1, 2, False), ("dipole3d_256_step2.txt", 2, 2, False),
+            ("dipole3d_256_order4_step1.txt", 1, 4, False), ("dipole3d_256_local_step1.txt", 1, 2, True),
+            ("dipole3d_256_local_step2.txt", 2, 2, True)]
+
+
+def _workload(local):
+    p = W.preset("dipole3d_256")
+    return p.replace(lam=0.0) if local else p
 
 
 def _path(name):
@@ -30,9 +37,9 @@ def _header(path):
     return " ".join(lines)
 
 
-@pytest.mark.parametrize("name,steps,order", FIXTURES)
-def test_fixture_records_the_current_workload(name, steps, order):
-    p = W.preset("dipole3d_256")
+@pytest.mark.parametrize("name,steps,order,local", FIXTURES)
+def test_fixture_records_the_current_workload(name, steps, order, local):
+    p = _workload(local)
     h = _header(_path(name))
     for key, val in [("N", p.N), ("L", p.L), ("s", p.s), ("Omega", p.Omega), ("beta", p.beta), ("lam", p.lam),
                      ("kernel", p.kernel), ("dt", p.dt)]:
@@ -41,9 +48,9 @@ def test_fixture_records_the_current_workload(name, steps, order):
     assert re.search(rf"initial_state\(seed=0\); steps={steps};{order_field} t0=0", h)
 
 
-@pytest.mark.parametrize("name,steps,order", FIXTURES)
-def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(name, steps, order):
-    p = W.preset("dipole3d_256")
+@pytest.mark.parametrize("name,steps,order,local", FIXTURES)
+def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(name, steps, order, local):
+    p = _workload(local)
     r = np.loadtxt(_path(name), comments="#")
     assert r.shape == (4096, 5) or (r.shape[1] == 5 and 4000 <= r.shape[0] <= 4096)
     ijk = r[:, :3].astype(int)

@@ -474,21 +474,27 @@ def _golden_samples(path):
     return idx, rows[:, 3] + 1j * rows[:, 4]
 
 
-@pytest.mark.parametrize("name,steps,order", [("dipole3d_256_step1.txt", 1, 2), ("dipole3d_256_step2.txt", 2, 2),
-                                              ("dipole3d_256_order4_step1.txt", 1, 4)])
+@pytest.mark.parametrize("name,steps,order,local", [
+    ("dipole3d_256_step1.txt", 1, 2, False), ("dipole3d_256_step2.txt", 2, 2, False),
+    ("dipole3d_256_order4_step1.txt", 1, 4, False), ("dipole3d_256_local_step1.txt", 1, 2, True),
+    ("dipole3d_256_local_step2.txt", 2, 2, True)])
 @pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-12), (fse.C64, 1e-5)])
-def test_dipole3d_256_steps_against_oracle_samples(name, steps, order, prec, tol):
+def test_dipole3d_256_steps_against_oracle_samples(name, steps, order, local, prec, tol):
     """One and two TS2 steps and one fourth-order step of the benchmarked
-    256^3 dipolar workload (two steps pass through the merged full-step
-    kinetic junction of every inner step), under every pass schedule the
-    tuner can choose, against the oracle at 4096 stored points
-    (tests/golden/make_dipole3d_256_step.py writes them)."""
+    256^3 dipolar workload, and one and two steps of it without the nonlocal
+    term (two steps pass through the merged full-step kinetic junction of
+    every inner step), under every pass schedule the tuner can choose, against
+    the oracle at 4096 stored points (tests/golden/make_dipole3d_256_step.py
+    writes them)."""
     p = W.preset("dipole3d_256")
+    if local:
+        p = p.replace(lam=0.0)
     idx, ref = _golden_samples(os.path.join(GOLDEN, name))
     psi0 = W.initial_state(p, seed=0)
     plan = fse.Plan.from_params(p, prec)
     it = torch.from_numpy(idx).to("cuda:0")
-    for sched in [(k, c, o) for o in (0, 1) for c in (0, 1) for k in (0, 1)]:
+    convs = (0,) if local else (0, 1)  # without a convolution there is no convolution schedule
+    for sched in [(k, c, o) for o in (0, 1) for c in convs for k in (0, 1)]:
         plan.set_schedule(sched)
         plan.time = 0.0
         x = _dev(psi0, prec)
