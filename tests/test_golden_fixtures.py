@@ -66,3 +66,20 @@ def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(name, step
     assert core.sum() >= 2048
     rel = np.linalg.norm(np.abs(v[core]) - a0[core]) / np.linalg.norm(a0[core])
     assert rel < 0.05
+
+
+def test_batch_fixture_covers_one_instance_of_each_size():
+    path = _path("batch_sweep_step5.txt")
+    h = _header(path)
+    assert "steps=5, t0=0" in h and "instances (0, 17, 38, 63)" in h
+    r = np.loadtxt(path, comments="#")
+    params = W.batch_sweep()
+    ks = sorted(set(r[:, 0].astype(int)))
+    assert ks == [0, 17, 38, 63]
+    assert sorted({params[k].N for k in ks}) == [(128, 128), (256, 256), (384, 384), (512, 512)]
+    for k in ks:
+        rk = r[r[:, 0] == k]
+        ij = rk[:, 1:3].astype(int)
+        assert np.all(ij >= 0) and np.all(ij < np.array(params[k].N))
+        assert len({tuple(x) for x in ij}) == rk.shape[0] >= 900
+        assert np.all(np.isfinite(rk[:, 3:5]))

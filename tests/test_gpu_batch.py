@@ -1,4 +1,5 @@
 """GPU parity of the batched 2D sweep (graph-captured, one branch per grid size)."""
+import os
 import sys
 
 import numpy as np
@@ -120,10 +121,26 @@ def test_batch_invalid():
         fse.Batch(bad, fse.C64)
 
 
-def test_full_sweep_sampled_against_fp64_single_plans():
-    # The benchmarked sweep: 64 instances, 16 each of 128^2, 256^2, 384^2, 512^2.
+def _sweep_samples():
+    """{instance: (flat indices, oracle values)} of tests/golden/batch_sweep_step5.txt (five oracle steps;
+    tests/golden/make_batch_sweep_samples.py writes it)."""
+    rows = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch_sweep_step5.txt"),
+                      comments="#")
+    params = W.batch_sweep()
+    out = {}
+    for k in np.unique(rows[:, 0]).astype(int):
+        r = rows[rows[:, 0] == k]
+        idx = np.ravel_multi_index((r[:, 1].astype(int), r[:, 2].astype(int)), params[k].N)
+        out[k] = (idx, r[:, 3] + 1j * r[:, 4])
+    return out
+
+
+def test_full_sweep_sampled_against_fp64_single_plans_and_the_oracle():
+    # The benchmarked sweep: 64 instances, 16 each of 128^2, 256^2, 384^2, 512^2; one instance of every
+    # size against the FP64 single plan (whole state) and both against stored oracle samples.
     params = W.batch_sweep()
     states = [W.vortex_lattice_2d(p.N, p.L, seed=k) for k, p in enumerate(params)]
+    samples = _sweep_samples()
     b = fse.Batch(params, fse.C64)
     x = b.pack(states)
     b.step(x, 5)
@@ -136,8 +153,12 @@ def test_full_sweep_sampled_against_fp64_single_plans():
         plan.step(y, 5, p.dt)
         ref = y.cpu().numpy()
         err = float(np.linalg.norm(got[k] - ref) / np.linalg.norm(ref))
-        _note(f"[sweep] instance {k} N={p.N} s={p.s:.3f} Omega={p.Omega:.3f}: c64 vs c128 {err:.3e}")
-        assert err < 1e-5
+        idx, orc = samples[k]
+        e128 = float(np.linalg.norm(ref.ravel()[idx] - orc) / np.linalg.norm(orc))
+        e64 = float(np.linalg.norm(got[k].ravel()[idx] - orc) / np.linalg.norm(orc))
+        _note(f"[sweep] instance {k} N={p.N} s={p.s:.3f} Omega={p.Omega:.3f}: c64 vs c128 {err:.3e}; "
+              f"oracle samples: c128 {e128:.3e}, batch c64 {e64:.3e}")
+        assert err < 1e-5 and e128 < 1e-12 and e64 < 1e-5
     assert np.max(np.abs(red[:, 0] - 1.0)) < 1e-5
 
 
