@@ -83,3 +83,17 @@ def test_batch_fixture_covers_one_instance_of_each_size():
         assert np.all(ij >= 0) and np.all(ij < np.array(params[k].N))
         assert len({tuple(x) for x in ij}) == rk.shape[0] >= 900
         assert np.all(np.isfinite(rk[:, 3:5]))
+
+
+def test_groundstate_fixture_records_the_current_workload():
+    p = W.preset("gs3d_256")
+    path = _path("groundstate3d_256_step1.txt")
+    h = _header(path)
+    for key, val in [("N", p.N), ("L", p.L), ("s", p.s), ("Omega", p.Omega), ("beta", p.beta), ("lam", p.lam),
+                     ("kernel", p.kernel), ("dt", p.dt)]:
+        assert f"{key}={val}" in h, (key, val, h)
+    r = np.loadtxt(path, comments="#")
+    ijk = r[:, :3].astype(int)
+    assert np.all(ijk >= 0) and np.all(ijk < np.array(p.N))
+    assert len({tuple(x) for x in ijk}) == r.shape[0] >= 4000
+    assert np.all(np.isfinite(r[:, 3:5]))

@@ -169,3 +169,24 @@ def test_optical_lattice_ground_state_steps(prec, gate):
     _note(f"[gs] optical lattice prec={prec}: 5 steps rel L2 {err:.3e}, E {E[0]:.6f} -> {E[-1]:.6f}")
     assert err < gate
     assert np.all(np.diff(E) <= 1e-6)
+
+
+@pytest.mark.parametrize("prec,tol,gate", [(fse.C128, 1e-12, 1e-10), (fse.C64, 1e-6, 1e-5)])
+def test_full_size_step_against_oracle_samples(prec, tol, gate):
+    """One step of the benchmarked 256^3 ground-state case from the initial guess
+    against the oracle's step (BiCGStab to 1e-12) at 4096 stored points
+    (tests/golden/make_groundstate3d_256_samples.py writes them)."""
+    import os
+    p = W.preset("gs3d_256")
+    rows = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                   "groundstate3d_256_step1.txt"), comments="#")
+    idx = np.ravel_multi_index((rows[:, 0].astype(int), rows[:, 1].astype(int), rows[:, 2].astype(int)), p.N)
+    ref = rows[:, 3] + 1j * rows[:, 4]
+    plan = fse.Plan.from_params(p, prec)
+    x = _dev(_psi0(p), prec)
+    st = plan.gs_step(x, p.dt, tol=tol, maxit=500)
+    got = x.reshape(-1)[torch.from_numpy(idx).to("cuda:0")].cpu().numpy().astype(np.complex128)
+    err = _rel(got, ref)
+    _note(f"[gs] 256^3 prec={prec}: samples rel {err:.3e}; GPU {st['iterations']} its res {st['residual']:.1e}")
+    assert st["converged"] and st["residual"] <= tol
+    assert err < gate
