@@ -97,3 +97,19 @@ def test_groundstate_fixture_records_the_current_workload():
     assert np.all(ijk >= 0) and np.all(ijk < np.array(p.N))
     assert len({tuple(x) for x in ijk}) == r.shape[0] >= 4000
     assert np.all(np.isfinite(r[:, 3:5]))
+
+
+def test_adjoint_fixture_records_the_current_workload():
+    p = W.preset("adjoint3d_96")
+    path = _path("adjoint3d_96_grad.txt")
+    h = _header(path)
+    for key, val in [("N", p.N), ("L", p.L), ("s", p.s), ("Omega", p.Omega), ("beta", p.beta), ("lam", p.lam),
+                     ("kernel", p.kernel), ("dt", p.dt)]:
+        assert f"{key}={val}" in h, (key, val, h)
+    assert "adjoint of 200 TS2-GauSum steps" in h
+    r = np.loadtxt(path, comments="#")
+    assert r.shape[1] == 6 and r.shape[0] >= 4000
+    ijk = r[:, :3].astype(int)
+    assert np.all(ijk >= 0) and np.all(ijk < np.array(p.N))
+    assert len({tuple(x) for x in ijk}) == r.shape[0]
+    assert np.all(np.isfinite(r[:, 3:6]))

@@ -261,3 +261,36 @@ def test_full_size_differentiation_case():
     assert e_psi < 1e-3 and e_v < 1e-3
     # the one-step complex64 bound is 1e-5; 200 steps accumulate to 2.4e-5 (measured)
     assert abs(L64 - L128) < 1e-4 * abs(L128)
+
+
+@pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-9), (fse.C64, 5e-4)])
+def test_full_size_differentiation_case_against_oracle_samples(prec, tol):
+    """The benchmarked 96^3 differentiation case (200 steps, U = |x|^2/2, loss
+    |<psi_t, psi(T)>|^2 + 0.1 <Lz>): dL/dpsi0 and dL/dU from fse_step_adjoint
+    against the oracle's at 4096 stored points (tests/golden/make_adjoint3d_96_samples.py
+    writes them); dL/dpsi(T) is the oracle's loss gradient at the library's own final state."""
+    import os
+    p = W.preset("adjoint3d_96")
+    rows = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint3d_96_grad.txt"),
+                      comments="#")
+    idx = np.ravel_multi_index((rows[:, 0].astype(int), rows[:, 1].astype(int), rows[:, 2].astype(int)), p.N)
+    g_ref, u_ref = rows[:, 3] + 1j * rows[:, 4], rows[:, 5]
+    cd, rd = (np.complex128, np.float64) if prec == fse.C128 else (np.complex64, np.float32)
+    psi0 = W.anisotropic_gaussian(p.N, p.L, (1.0, 1.0, 1.0), seed=0)
+    V = W.harmonic_potential(p.N, p.L, (1.0, 1.0, 1.0))
+    tgt = W.adjoint_target(p.N, p.L, seed=1)
+    plan = fse.Plan.from_params(p, prec)
+    Ud = _dev(V, rd)
+    plan.set_potential(Ud)
+    x = _dev(psi0, cd)
+    plan.step(x, 200, p.dt)
+    _, gT = adj.loss_and_grad(x.cpu().numpy().astype(np.complex128), tgt, p.N, p.L)
+    plan.time = 0.0
+    g = _dev(gT, cd)
+    gU = torch.zeros(p.N, dtype=torch.float64 if prec == fse.C128 else torch.float32, device="cuda:0")
+    plan.step_adjoint(_dev(psi0, cd), 200, p.dt, g, gU)
+    it = torch.from_numpy(idx).to("cuda:0")
+    e1 = _rel(g.reshape(-1)[it].cpu().numpy().astype(np.complex128), g_ref)
+    e2 = _rel(gU.reshape(-1)[it].cpu().numpy().astype(np.float64), u_ref)
+    _note(f"[adjoint] 96^3 x 200 steps prec={prec}: dL/dpsi0 {e1:.3e}, dL/dU {e2:.3e} at the stored points")
+    assert e1 < tol and e2 < tol
