@@ -55,16 +55,14 @@ def load(prefix: str, device: str = "cuda:0"):
     return meta["params"], psi.to(device), float(meta["t"]), _PREC_BACK[meta["precision"]]
 
 
-def resume(prefix: str, params_type=None, device: str = "cuda:0"):
-    """(plan, psi, params) ready to continue: the plan is built from the stored parameters (params_type(**dict)
-    when given, e.g. a dataclass with tuple fields) and its time set to the stored t."""
+def resume(prefix: str, params_type, device: str = "cuda:0"):
+    """(plan, psi, params) ready to continue: params = params_type(**stored fields, lists as tuples), the type
+    the checkpoint was written from (it may derive further values, such as the kernel prefactor, from its
+    fields), the plan built from it and its time set to the stored t."""
     pd, psi, t, prec = load(prefix, device)
-    if params_type is not None:
-        fields = {f.name for f in dataclasses.fields(params_type)} if dataclasses.is_dataclass(params_type) else None
-        kw = {k: tuple(v) if isinstance(v, list) else v for k, v in pd.items() if fields is None or k in fields}
-        params = params_type(**kw)
-    else:
-        params = pd
+    fields = {f.name for f in dataclasses.fields(params_type)} if dataclasses.is_dataclass(params_type) else None
+    kw = {k: tuple(v) if isinstance(v, list) else v for k, v in pd.items() if fields is None or k in fields}
+    params = params_type(**kw)
     plan = fse.Plan.from_params(params, prec)
     plan.time = t
     return plan, psi, params

@@ -46,6 +46,10 @@ def test_resume_equals_an_uninterrupted_run(tmp_path, prec, tol):
     assert abs(plan2.time - plan.time) < 1e-15
     err = float(torch.linalg.vector_norm(c - a) / torch.linalg.vector_norm(a))
     assert err < tol
+    # a second resume from the same files repeats the continuation bit for bit
+    plan3, c3, _ = checkpoint.resume(prefix, W.Params)
+    plan3.step(c3, 5, p.dt)
+    assert torch.equal(c3, c)
 
 
 def test_logged_run_writes_one_line_per_chunk(tmp_path):
