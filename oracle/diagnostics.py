@@ -30,6 +30,7 @@ from __future__ import annotations
 import numpy as np
 
 from .scheme import axes, freqs, kinetic_symbol, trap, _bcast
+from . import _fft
 
 
 def _vol(N, L):
@@ -42,7 +43,7 @@ def mass(psi, N, L):
 
 def derivative(psi, N, L, axis):
     mu = freqs(N, L)[axis]
-    return np.fft.ifftn(1j * _bcast(mu, axis, len(N)) * np.fft.fftn(psi))
+    return _fft.ifftn(1j * _bcast(mu, axis, len(N)) * _fft.fftn(psi))
 
 
 def apply_Lz(psi, N, L):
@@ -66,7 +67,7 @@ def energy_parts(prob, psi, t=0.0):
     vol = _vol(N, L)
     n = float(np.prod(N))
     om = kinetic_symbol(N, L, prob.s, prob.m)
-    ph = np.fft.fftn(psi)
+    ph = _fft.fftn(psi)
     ekin = 0.5 * vol / n * float(np.sum(om * np.abs(ph) ** 2))
     rho = np.abs(psi) ** 2
     W = trap(N, L, prob.gamma, prob.Omega, t, getattr(prob, "lattice", None))
@@ -109,7 +110,7 @@ def apply_H(prob, psi, rho_frozen=None):
     """H psi = (1/2)(-Lap+m^2)^s psi + (V + beta rho + lam Phi[rho]) psi - Omega Lz psi (lab frame)."""
     N, L = prob.N, prob.L
     om = kinetic_symbol(N, L, prob.s, prob.m)
-    kin = np.fft.ifftn(0.5 * om * np.fft.fftn(psi))
+    kin = _fft.ifftn(0.5 * om * _fft.fftn(psi))
     rho = np.abs(psi) ** 2 if rho_frozen is None else rho_frozen
     V = trap(N, L, prob.gamma, 0.0, 0.0, getattr(prob, "lattice", None))
     if getattr(prob, "U", None) is not None:

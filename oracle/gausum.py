@@ -52,6 +52,8 @@ import math
 import numpy as np
 from scipy import special
 
+from . import _fft
+
 
 SURFACE = {2: 2.0 * math.pi, 3: 4.0 * math.pi}  # |S^{d-1}|
 
@@ -260,7 +262,7 @@ def convolve(rho, K):
     M = K.shape
     pad = np.zeros(M)
     pad[tuple(slice(0, n) for n in N)] = rho
-    out = np.fft.ifftn(K * np.fft.fftn(pad))
+    out = _fft.ifftn(K * _fft.fftn(pad))
     return np.real(out[tuple(slice(0, n) for n in N)])
 
 
@@ -273,4 +275,4 @@ def potential(rho, N, L, kernel, mu=1.0, c=1.0, delta=None, K=None, axis=(0.0, 0
 
 def real_space_kernel(K):
     """k = ifftn(K): the discrete kernel whose circular convolution the FFT path applies."""
-    return np.real(np.fft.ifftn(K))
+    return np.real(_fft.ifftn(K))

@@ -15,7 +15,9 @@ Oracle (test infrastructure only).  Follows Section 3.2 of the paper:
   space) and A_TF = V + beta rho^n + lam Phi^n - Omega Lz,
       (I + P_Delta A_TF) phi1 = P_Delta phi^n / dt,
   solved by BiCGStab.
-* Stopping rule of the paper's experiments: ||phi^n - phi^{n+1}||_inf <= eps0 dt.
+* Stopping rule of the paper's experiments: ||phi^n - phi^{n+1}||_inf <= eps0 dt
+  (run, run_to); run_to also stops on an energy change |E^{n+1} - E^n| below a
+  tolerance, E of eq. energy in the frame of eq. SFSE.
 * Initial guess (eq. ini_guess): ((1-Omega) phi_ho + Omega phi_ho^v), normalised.
 
 Readings where the paper is silent:
@@ -38,6 +40,7 @@ import numpy as np
 from scipy.sparse.linalg import LinearOperator, bicgstab
 
 from .scheme import _bcast, axes, freqs, kinetic_symbol, lattice_potential
+from . import _fft, diagnostics
 
 
 def _norm(phi, N, L):
@@ -77,13 +80,13 @@ class GroundState:
     # -- operators ------------------------------------------------------------
     def P_delta(self, v):
         """[I/dt + (1/2)(-Lap+m^2)^s]^{-1} v, diagonal in Fourier space."""
-        return np.fft.ifftn(np.fft.fftn(v) / (1.0 / self.dt + 0.5 * self.omega))
+        return _fft.ifftn(_fft.fftn(v) / (1.0 / self.dt + 0.5 * self.omega))
 
     def Lz(self, v):
         """-i (x d_y - y d_x) v with Fourier derivatives."""
-        vh = np.fft.fftn(v)
-        dx = np.fft.ifftn(1j * self.mu[0] * vh)
-        dy = np.fft.ifftn(1j * self.mu[1] * vh)
+        vh = _fft.fftn(v)
+        dx = _fft.ifftn(1j * self.mu[0] * vh)
+        dy = _fft.ifftn(1j * self.mu[1] * vh)
         return -1j * (self.X[0] * dy - self.X[1] * dx)
 
     def frozen(self, phi_n):
@@ -146,3 +149,23 @@ class GroundState:
             if stats[2] <= eps0 * self.dt:
                 return phi, n, stats
         return phi, int(max_steps), stats
+
+    def energy(self, phi):
+        """The functional the flow decreases: E(phi) of eq. energy in the frame of eq. SFSE (V unrotated, -Omega Lz)."""
+        return diagnostics.energy_parts(self.prob, phi, 0.0)[5]
+
+    def run_to(self, phi0, eps_diff=None, eps_energy=None, max_steps=100000, rtol=1e-12):
+        """Iterate until a stopping rule holds after a step: the paper's ||phi^n - phi^{n+1}||_inf <= eps_diff dt
+        (Section 3.3), or an energy change |E(phi^{n+1}) - E(phi^n)| <= eps_energy (None: rule not used), or
+        max_steps.  Returns (phi, steps, rule, energies): rule 1 (difference), 2 (energy) or 0 (neither, after
+        max_steps; the difference rule is tested first), energies = [E(phi0), E(phi^1), ...]."""
+        phi = phi0
+        energies = [self.energy(phi)]
+        for n in range(1, int(max_steps) + 1):
+            phi, stats = self.step(phi, rtol)
+            energies.append(self.energy(phi))
+            if eps_diff is not None and stats[2] <= eps_diff * self.dt:
+                return phi, n, 1, energies
+            if eps_energy is not None and abs(energies[-1] - energies[-2]) <= eps_energy:
+                return phi, n, 2, energies
+        return phi, int(max_steps), 0, energies

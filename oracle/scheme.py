@@ -58,6 +58,7 @@ import math
 import numpy as np
 
 from . import gausum
+from . import _fft
 
 
 def axes(N, L):
@@ -88,7 +89,7 @@ def kinetic_symbol(N, L, s, m=0.0):
 def kinetic(psi, N, L, s, tau, m=0.0):
     """Linear sub-step over time tau (eq. 1step, exact in Fourier space)."""
     om = kinetic_symbol(N, L, s, m)
-    return np.fft.ifftn(np.exp(-1j * tau * 0.5 * om) * np.fft.fftn(psi))
+    return _fft.ifftn(np.exp(-1j * tau * 0.5 * om) * _fft.fftn(psi))
 
 
 def lattice_potential(X, lattice):

@@ -93,3 +93,21 @@ def test_fractional_nonlinear_energy_decreases_and_stationarity():
     mu = float(np.real(_overlap(phi, H, p.N, p.L)))
     res = np.linalg.norm(H - mu * phi) / np.linalg.norm(mu * phi)
     assert res < 1e-8
+
+
+def test_run_to_stopping_rules():
+    # The loop with the paper's difference rule stops where run() stops; with the
+    # energy-change rule it stops once |E^{n+1} - E^n| <= eps, here at the s = 1
+    # harmonic ground state (energy 1 exactly), the energies decreasing on the way.
+    p = _prob((32, 32), (8.0, 8.0), 1.0, 0.3, 0.0, 0.0)
+    g = gs.GroundState(p, dt=1.0)
+    phi0 = gs.initial_guess(p.N, p.L, 0.3)
+    a, na, _ = g.run(phi0, eps0=1e-10)
+    b, nb, rule, en = g.run_to(phi0, eps_diff=1e-10)
+    assert (nb, rule) == (na, 1) and np.array_equal(a, b)
+    assert len(en) == nb + 1 and abs(en[-1] - dg.energy_parts(p, b)[5]) == 0.0
+    c, nc, rule, en = g.run_to(phi0, eps_energy=1e-14)
+    assert rule == 2 and abs(en[-1] - en[-2]) <= 1e-14 and nc < 200
+    assert abs(en[-1] - 1.0) < 1e-10 and np.all(np.diff(en) <= 1e-15)
+    _, nd, rule, en = g.run_to(phi0, eps_energy=1e-14, max_steps=3)
+    assert (nd, rule, len(en)) == (3, 0, 4)
