@@ -94,6 +94,39 @@ __device__ __forceinline__ void fsincos(double x, double* s, double* c) {
 __device__ __forceinline__ void fsincos(float x, float* s, float* c) { sincosf(x, s, c); }
 
 // ---------------------------------------------------------------------------
+// Products with the butterflies' irrational constants (sqrt(1/2), cos and sin
+// of pi/8, sqrt(3)/2).  In FP32 every such constant rounds below its exact
+// value, so a product with it shrinks |z| by 1e-8 to 3e-8 relative, the same
+// way in every transform: the mass of a complex64 state then decays by about
+// 1e-7 per step.  The FP32 path therefore carries each constant as hi + lo
+// (lo = the rounding residual) and adds the lo product inside the FMA of the
+// hi product, whose product is exact there: the result is the correctly
+// rounded product up to one unbiased rounding, and the decay goes away.  FP64
+// keeps the plain product (its residual bias is ~1e-17).
+// ---------------------------------------------------------------------------
+template <typename R> struct KConst {
+    R hi, lo;
+    constexpr KConst(double c) : hi(R(c)), lo(sizeof(R) == 4 ? R(c - double(R(c))) : R(0)) {}
+};
+
+// x * c
+template <typename R> __device__ __forceinline__ R kmul(R x, KConst<R> c) {
+    if constexpr (sizeof(R) == 4) return fmaf(x, c.hi, x * c.lo);
+    else return x * c.hi;
+}
+
+// a * (cr + i ci) for a constant rotation
+template <typename T, typename R> __device__ __forceinline__ T krot(T a, KConst<R> cr, KConst<R> ci) {
+    if constexpr (sizeof(R) == 4) {
+        const R tr = a.x * cr.lo - a.y * ci.lo;
+        const R ti = a.x * ci.lo + a.y * cr.lo;
+        return T{fmaf(a.x, cr.hi, fmaf(-a.y, ci.hi, tr)), fmaf(a.x, ci.hi, fmaf(a.y, cr.hi, ti))};
+    } else {
+        return T{a.x * cr.hi - a.y * ci.hi, a.x * ci.hi + a.y * cr.hi};
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Radix-R DFTs in registers.
 // ---------------------------------------------------------------------------
 template <int R, bool INV> struct DFT;
@@ -109,11 +142,11 @@ template <bool INV> struct DFT<2, INV> {
 template <bool INV> struct DFT<3, INV> {
     template <typename T> __device__ __forceinline__ static void run(T* v) {
         using R = typename RealOf<T>::R;
-        const R s3 = R(0.86602540378443864676372317075294);  // sqrt(3)/2
+        constexpr KConst<R> s3(0.86602540378443864676372317075294);  // sqrt(3)/2
         T s = cadd(v[1], v[2]);
-        T dd = csub(v[1], v[2]);
+        T dd = mul_ni<INV>(csub(v[1], v[2]));
         T a = T{v[0].x - R(0.5) * s.x, v[0].y - R(0.5) * s.y};
-        T b = cscale(mul_ni<INV>(dd), s3);  // -i sqrt(3)/2 (v1 - v2) forward
+        T b = T{kmul(dd.x, s3), kmul(dd.y, s3)};  // -i sqrt(3)/2 (v1 - v2) forward
         v[0] = cadd(v[0], s);
         v[1] = cadd(a, b);
         v[2] = csub(a, b);
@@ -134,17 +167,17 @@ template <bool INV> struct DFT<4, INV> {
 template <bool INV> struct DFT<8, INV> {
     template <typename T> __device__ __forceinline__ static void run(T* v) {
         using R = typename RealOf<T>::R;
-        const R c = R(0.70710678118654752440084436210485);  // sqrt(1/2)
+        constexpr KConst<R> c(0.70710678118654752440084436210485);  // sqrt(1/2)
         T e[4] = {v[0], v[2], v[4], v[6]};
         T o[4] = {v[1], v[3], v[5], v[7]};
         DFT<4, INV>::run(e);
         DFT<4, INV>::run(o);
         // o[k] *= W8^k, W8 = exp(-+ i pi/4)
-        T o1 = INV ? T{c * (o[1].x - o[1].y), c * (o[1].x + o[1].y)}
-                   : T{c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};
+        T o1 = INV ? T{kmul(o[1].x - o[1].y, c), kmul(o[1].x + o[1].y, c)}
+                   : T{kmul(o[1].x + o[1].y, c), kmul(o[1].y - o[1].x, c)};
         T o2 = mul_ni<INV>(o[2]);
-        T o3 = INV ? T{-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y)}
-                   : T{c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)};
+        T o3 = INV ? T{-kmul(o[3].x + o[3].y, c), kmul(o[3].x - o[3].y, c)}
+                   : T{kmul(o[3].y - o[3].x, c), -kmul(o[3].x + o[3].y, c)};
         v[0] = cadd(e[0], o[0]);
         v[4] = csub(e[0], o[0]);
         v[1] = cadd(e[1], o1);
@@ -160,9 +193,9 @@ template <bool INV> struct DFT<16, INV> {
     template <typename T> __device__ __forceinline__ static void run(T* v) {
         using R = typename RealOf<T>::R;
         // cos(pi m / 8) and sin(pi m / 8), m = 0..9
-        const R C1 = R(0.92387953251128675612818318939679);
-        const R S1 = R(0.38268343236508977172845998403040);
-        const R C2 = R(0.70710678118654752440084436210485);
+        constexpr double C1 = 0.92387953251128675612818318939679;
+        constexpr double S1 = 0.38268343236508977172845998403040;
+        constexpr double C2 = 0.70710678118654752440084436210485;
         // Y[n2][k1] = DFT4 over n1 of v[4 n1 + n2]
         T y[4][4];
 #pragma unroll
@@ -173,15 +206,18 @@ template <bool INV> struct DFT<16, INV> {
             for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
         }
         // twiddles W16^{n2 k1}
-        const R cs[10] = {R(1), C1, C2, S1, R(0), -S1, -C2, -C1, R(-1), -C1};
-        const R sn[10] = {R(0), S1, C2, C1, R(1), C1, C2, S1, R(0), -S1};
+        constexpr double cs[10] = {1.0, C1, C2, S1, 0.0, -S1, -C2, -C1, -1.0, -C1};
+        constexpr double sn[10] = {0.0, S1, C2, C1, 1.0, C1, C2, S1, 0.0, -S1};
 #pragma unroll
         for (int n2 = 1; n2 < 4; ++n2) {
 #pragma unroll
             for (int k1 = 1; k1 < 4; ++k1) {
                 const int m = n2 * k1;
-                const T w = T{cs[m], INV ? sn[m] : -sn[m]};
-                y[n2][k1] = cmul(y[n2][k1], w);
+                if (m == 4) {
+                    y[n2][k1] = mul_ni<INV>(y[n2][k1]);  // W16^4 = -+i
+                } else {
+                    y[n2][k1] = krot<T, R>(y[n2][k1], KConst<R>(cs[m]), KConst<R>(INV ? sn[m] : -sn[m]));
+                }
             }
         }
 #pragma unroll
