@@ -28,9 +28,17 @@
  *         Calls are asynchronous on that stream; only fse_plan_create and
  *         fse_plan_destroy synchronise.  A plan must not be used from two
  *         host threads at once.
- * Time.   The plan keeps the time t of the state (host side, FP64); the
- *         rotating-frame trap W(x~,t) = V(A(t) x~) depends on it.
- *         fse_step advances it by nsteps*dt.
+ * Time.   The plan keeps the time t of the state in DEVICE memory (FP64);
+ *         the rotating-frame trap W(x~,t) = V(A(t) x~), a dipole axis that
+ *         turns in the rotating frame and a turning optical lattice depend on
+ *         it.  Kernels read it on the device: fse_step and fse_step4 advance
+ *         it on the stream by nsteps*dt, and a call recorded into a HIP graph
+ *         (fse_step, fse_step4, fse_energy, fse_moments,
+ *         fse_nonlocal_potential, fse_mass, fse_angular_momentum,
+ *         fse_step_adjoint) replays at the time the plan has when the replay
+ *         runs.  Buffers a call clears are cleared by a kernel, not a runtime
+ *         memset.  Before capturing, make one eager call of each kind (first
+ *         calls allocate tables and buffers).
  * Errors. Every call returns an fse_status; nothing is thrown across the ABI.
  *         fse_last_error() returns a message for the calling thread's last
  *         failure.
@@ -125,6 +133,10 @@ fse_status fse_scratch_size(fse_plan plan, size_t* bytes);
  * FSE_ERR_STATE. */
 fse_status fse_set_workspace(fse_plan plan, void* dev_ptr, size_t bytes);
 
+/* Set / read the plan's time (host value, written to / read from the device
+ * copy).  Both wait for the device to finish its queued work first (host
+ * queries: not for use inside a graph capture).  FSE_ERR_ARG for a
+ * non-finite t. */
 fse_status fse_set_time(fse_plan plan, double t);
 fse_status fse_get_time(fse_plan plan, double* t);
 
@@ -299,6 +311,34 @@ typedef struct {
 
 fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxit, fse_gs_stats* stats,
                        void* stream);
+
+/* Ground state to convergence: fse_gs_step repeated until, after a step,
+ *   rule 1: ||psi^n - psi^{n+1}||_inf <= eps_diff * dt  (the stopping rule of
+ *           the paper's ground-state computations, Section 3.3), or
+ *   rule 2: |E(psi^{n+1}) - E(psi^n)| <= eps_energy,
+ * or max_steps steps have run (rule 0).  A rule whose tolerance is <= 0 is not
+ * used (rule 1 is tested first).  E is the energy of eq. energy in the frame
+ * of eq. SFSE (V unrotated, -Omega <Lz>, a dipole along n), the functional
+ * the flow decreases, reduced on the device in FP64.  energy_trace (host
+ * memory, nullable, at least max_steps + 1 doubles): E(psi^0), E(psi^1), ...
+ * up to the last step.  The energy is computed only when eps_energy > 0 or a
+ * trace is requested.  Synchronous, as fse_gs_step; tol and maxit are passed
+ * to each step.  FSE_ERR_ARG for dt, tol <= 0, maxit or max_steps < 1, or a
+ * non-finite tolerance; FSE_ERR_NUMERIC as fse_gs_step (psi then holds the
+ * last completed step). */
+typedef struct {
+    int steps;             /* gradient-flow steps taken */
+    int converged;         /* 1 if a stopping rule held */
+    int rule;              /* 1 difference, 2 energy change, 0 none (max_steps) */
+    int krylov_iterations; /* BiCGStab iterations over all steps */
+    double diff_inf;       /* max |psi^{n+1} - psi^n| of the last step */
+    double energy;         /* E of the final state (NaN if the energy was not computed) */
+    double energy_change;  /* |E^{n+1} - E^n| of the last step (NaN if not computed) */
+    double residual;       /* relative residual of the last step's Krylov solve */
+} fse_gs_run_stats;
+
+fse_status fse_gs_run(fse_plan plan, void* psi, double dt, double tol, int maxit, int max_steps, double eps_diff,
+                      double eps_energy, double* energy_trace, fse_gs_run_stats* stats, void* stream);
 
 /* Host-only: the GauSum multiplier Khat (before any FFT normalisation) on the
  * non-negative frequency octant, out[(k0*(N1+1)+k1)*(N2+1)+k2] for d = 3

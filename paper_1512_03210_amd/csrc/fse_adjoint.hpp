@@ -27,11 +27,13 @@ template <typename R>
 __global__ void k_adj_theta(const typename CT<R>::T* __restrict__ psi1, const R* __restrict__ Phi,
                             const R* __restrict__ U, R* __restrict__ theta, typename CT<R>::T* __restrict__ psi2,
                             long n, GridGeom g, PhaseArgs pa) {
+    double pcc, pcs;
+    phase_time(pa, &pcc, &pcs);
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         decode(i, g, i0, i1, i2);
         const double x = g.x0 + i0 * g.hx, y = g.y0 + i1 * g.hy, z = (g.d == 3) ? g.z0 + i2 * g.hz : 0.0;
-        const double P = pa.cz * z * z + (pa.ca - pa.cc) * y * y + (pa.ca + pa.cc) * x * x + pa.cs * 2.0 * x * y;
+        const double P = pa.cz * z * z + (pa.ca - pcc) * y * y + (pa.ca + pcc) * x * x + pcs * 2.0 * x * y;
         const double2 v = adj::up(psi1[i]);
         double th = pa.bdt * (v.x * v.x + v.y * v.y) + P;
         if (Phi) th += pa.ldt * (double)Phi[i];

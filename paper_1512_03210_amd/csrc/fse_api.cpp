@@ -86,7 +86,7 @@ struct fse_plan_s {
     fse_kernel kernel{};
     int prec = FSE_C128;
     bool nl = false;  // nonlocal term present
-    double t = 0.0;
+    double* tdev = nullptr;  // the time t of the state, in device memory (a batch points it into its own array)
     long n = 0;       // grid points
     int C0 = 0;       // columns of the axis-0 passes (n / N0)
     size_t csize = 16, rsize = 8;
@@ -376,7 +376,22 @@ fse::LineIdx conv_index(const fse_plan p) {
     return li;
 }
 
-fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
+// A time for the time-dependent coefficients: the plan's device time plus an
+// offset known on the host (dev), or a fixed time (not dev; t = 0 is the frame
+// of eq. SFSE, where H psi and the ground state live).
+struct TimeRef {
+    bool dev;
+    double off;
+};
+constexpr TimeRef kFrame{false, 0.0};
+TimeRef at_plan(double off = 0.0) { return TimeRef{true, off}; }
+
+double gdiff(const fse_plan p) { return (p->gamma[0] * p->gamma[0] - p->gamma[1] * p->gamma[1]) / 4.0; }
+
+// Whether the rotating part of the trap depends on time (rotation and gx != gy).
+bool trap_turns(const fse_plan p) { return p->Omega != 0.0 && gdiff(p) != 0.0; }
+
+fse::PhaseArgs phase_args(const fse_plan p, TimeRef tn, double dt) {
     fse::PhaseArgs a;
     a.x0 = -p->L[0];
     a.hx = p->h[0];
@@ -387,14 +402,18 @@ fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
     a.N2 = (p->d == 3) ? p->N[2] : 0;
     const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
     const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
-    // int_{tn}^{tn+dt} cos/sin(2 Omega s) ds
-    const double f = (p->Omega == 0.0) ? dt : std::sin(p->Omega * dt) / p->Omega;
-    const double sc = (p->Omega == 0.0) ? dt : std::cos(p->Omega * (2.0 * tn + dt)) * f;
-    const double ss = (p->Omega == 0.0) ? 0.0 : std::sin(p->Omega * (2.0 * tn + dt)) * f;
     a.ca = dt * (gx2 + gy2) / 4.0;
     a.cz = dt * gz2 / 2.0;
-    a.cc = (gx2 - gy2) / 4.0 * sc;
-    a.cs = (gx2 - gy2) / 4.0 * ss;
+    if (tn.dev && trap_turns(p)) {  // evaluated by the kernel at the device time
+        a.tp = p->tdev;
+        a.toff = tn.off;
+        a.tau = dt;
+        a.Om = p->Omega;
+        a.gd = gdiff(p);
+        a.cc = a.cs = 0.0;
+    } else {  // independent of the time, or at a fixed time
+        fse::trap_rotating(tn.off, dt, p->Omega, gdiff(p), &a.cc, &a.cs);
+    }
     a.bdt = p->beta * dt;
     a.ldt = p->lambda * dt;
     a.U = p->U;
@@ -408,48 +427,38 @@ fse::PhaseArgs phase_args(const fse_plan p, double tn, double dt) {
 // m(s) = A(s)^{-1} n is n_perp turned by +Omega s, and the time average of
 // m m^T has, for each harmonic cos/sin(a + b s), its midpoint value times
 // sinc(b tau / 2) (eq. Kernel_Rot).
-fse::QForm qform(const fse_plan p, double t, double tau) {
+fse::QForm qform(const fse_plan p, TimeRef t, double tau) {
     const double* n = p->kernel.n;
-    const double r = std::hypot(n[0], n[1]);
-    const double phi0 = (r > 0.0) ? std::atan2(n[1], n[0]) : 0.0;
-    const double W = p->Omega;
-    auto sinc = [](double x) { return (x == 0.0) ? 1.0 : std::sin(x) / x; };
-    auto mc = [&](double k) { return std::cos(k * (phi0 + W * (t + 0.5 * tau))) * sinc(0.5 * k * W * tau); };
-    auto ms = [&](double k) { return std::sin(k * (phi0 + W * (t + 0.5 * tau))) * sinc(0.5 * k * W * tau); };
-    const double M00 = r * r * (0.5 + 0.5 * mc(2.0)), M11 = r * r * (0.5 - 0.5 * mc(2.0));
-    const double M01 = r * r * 0.5 * ms(2.0), M02 = n[2] * r * mc(1.0), M12 = n[2] * r * ms(1.0);
-    const double M22 = n[2] * n[2];
     fse::QForm q{};
+    q.r = std::hypot(n[0], n[1]);
+    q.phi0 = (q.r > 0.0) ? std::atan2(n[1], n[0]) : 0.0;
+    q.n2 = n[2];
+    q.Om = p->Omega;
+    q.kscale = p->khat_scale;
+    q.d3 = (p->d == 3) ? 1 : 0;
     q.dk0 = kPi / (2.0 * p->L[0]);
     q.n0 = p->N[0];
     if (p->d == 3) {
-        // -1 + 3 Khat_C kappa^T M kappa; the line axis is axis 2
         q.dk1 = kPi / (2.0 * p->L[1]);
         q.dk2 = kPi / (2.0 * p->L[2]);
         q.n1 = p->N[1];
-        q.c0 = -p->khat_scale;
-        q.m00 = 3.0 * M00;
-        q.m11 = 3.0 * M11;
-        q.m22 = 3.0 * M22;
-        q.m01 = 3.0 * M01;
-        q.m02 = 3.0 * M02;
-        q.m12 = 3.0 * M12;
     } else {
-        // (3/2) Khat_C (kappa^T M_perp kappa - M22 |kappa|^2); the line axis is axis 1
         q.dk1 = 0.0;
         q.dk2 = kPi / (2.0 * p->L[1]);
         q.n1 = 0;
-        q.c0 = 0.0;
-        q.m00 = 1.5 * (M00 - M22);
-        q.m22 = 1.5 * (M11 - M22);
-        q.m02 = 1.5 * M01;
     }
+    if (t.dev && p->Omega != 0.0) {  // a turning axis: averaged on the device at the plan's time
+        q.tp = p->tdev;
+        q.toff = t.off;
+        q.tau = tau;
+    }
+    fse::qform_fill(q, t.dev ? 0.0 : t.off, tau);  // (time-independent without rotation)
     return q;
 }
 
 // Padded convolution along the contiguous axis with the plan's multiplier; a
 // qf plan uses the quadratic form over [t, t+tau].
-template <typename R> hipError_t conv_line(fse_plan p, double t, double tau, hipStream_t st) {
+template <typename R> hipError_t conv_line(fse_plan p, TimeRef t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     const int NL = p->last();
     void* X = (p->d == 3) ? p->X2 : p->X1;
@@ -461,44 +470,44 @@ template <typename R> hipError_t conv_line(fse_plan p, double t, double tau, hip
 // Lattice arguments: its time integral over [t, t+tau] in rotating coordinates
 // (8-node Gauss-Legendre in time; the trap integral P of a non-harmonic V has
 // no closed form), plus tau U; or its value at the instant t (tau = 0), plus U.
-fse::LatArgs lat_args(const fse_plan p, double t, double tau) {
+fse::LatArgs lat_args(const fse_plan p, TimeRef t, double tau) {
     fse::LatArgs la{};
     for (int j = 0; j < 3; ++j) {
         la.v[j] = p->lat_v[j];
         la.k[j] = p->lat_k[j];
     }
+    la.tau = tau;
+    la.Om = p->Omega;
     if (tau == 0.0) {
         la.nq = 1;
-        la.c[0] = std::cos(p->Omega * t);
-        la.s[0] = std::sin(p->Omega * t);
-        la.w[0] = 1.0;
+        la.gx[0] = 0.0;
+        la.gw[0] = 2.0;
         la.uf = 1.0;
-        return la;
+    } else {
+        std::vector<double> x, w;
+        fse::gauss_legendre(8, x, w);
+        la.nq = 8;
+        for (int q = 0; q < 8; ++q) {
+            la.gx[q] = x[q];
+            la.gw[q] = w[q];
+        }
+        la.uf = tau;
     }
-    std::vector<double> x, w;
-    fse::gauss_legendre(8, x, w);
-    la.nq = 8;
-    for (int q = 0; q < 8; ++q) {
-        const double sq = t + 0.5 * tau * (x[q] + 1.0);
-        la.c[q] = std::cos(p->Omega * sq);
-        la.s[q] = std::sin(p->Omega * sq);
-        la.w[q] = 0.5 * tau * w[q];
+    if (t.dev && p->Omega != 0.0) {  // the lattice turns: nodes at the device time
+        la.tp = p->tdev;
+        la.toff = t.off;
     }
-    la.uf = tau;
+    fse::lat_fill(la, t.dev ? 0.0 : t.off);  // (time-independent without rotation)
     return la;
 }
 
 // The potential array the pointwise kernels add: the grid potential U, or with a
 // lattice the lattice in the frame at time t (frame = true: the frame of
 // eq. SFSE, for H psi and the ground state) plus U, written to lat_buf.
-template <typename R> const void* extra_potential(fse_plan p, double t, bool frame, hipStream_t st, hipError_t* e) {
+template <typename R> const void* extra_potential(fse_plan p, TimeRef t, hipStream_t st, hipError_t* e) {
     *e = hipSuccess;
     if (!p->lat) return p->U;
-    fse::LatArgs la = lat_args(p, frame ? 0.0 : t, 0.0);
-    if (frame) {
-        la.c[0] = 1.0;
-        la.s[0] = 0.0;
-    }
+    const fse::LatArgs la = lat_args(p, t, 0.0);
     *e = fse::Launch<R>::lattice(p->lat_buf, p->U, p->n, geom(p), la, st);
     return p->lat_buf;
 }
@@ -513,7 +522,7 @@ fse_status scratch_ready(const fse_plan p) {
 }
 
 // Zero-padded GauSum convolution of the density held in X1 (after r2c), result back in X1.
-template <typename R> fse_status conv_passes(fse_plan p, double t, double tau, hipStream_t st) {
+template <typename R> fse_status conv_passes(fse_plan p, TimeRef t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     if (fse_status s = scratch_ready(p); s != FSE_OK) return s;
     if (p->d == 3) {
@@ -530,7 +539,7 @@ template <typename R> fse_status conv_passes(fse_plan p, double t, double tau, h
 // Phi[rho] into a real array; src 1: rho = |psi|^2, 2: rho given.
 // (t, tau: the time and averaging interval of a turning dipole axis, see qform)
 template <typename R>
-fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, double t, double tau, hipStream_t st) {
+fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, TimeRef t, double tau, hipStream_t st) {
     using L = fse::Launch<R>;
     if (!p->nl) {
         HIPCHK(fse::launch_zero(Phi, (size_t)p->n * p->rsize, st));
@@ -541,7 +550,7 @@ fse_status potential_impl(fse_plan p, const void* src, int srckind, void* Phi, d
     HIPCHK(L::r2c(N0, srckind, src, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
     fse_status s = conv_passes<R>(p, t, tau, st);
     if (s != FSE_OK) return s;
-    fse::PhaseArgs pa = phase_args(p, p->t, 0.0);
+    fse::PhaseArgs pa = phase_args(p, kFrame, 0.0);  // (mode 2 writes the potential only)
     HIPCHK(L::c2r_phase(N0, 2, p->X1, nullptr, Phi, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
     return FSE_OK;
 }
@@ -592,13 +601,13 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
     if (p->d == 3)
         PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
     for (int k = 0; k < nsteps; ++k) {
-        double tj = p->t + k * dt;
+        double tj = k * dt;  // offset of the sub-step from the plan's time at the call
         for (int j = 0; j < nw; ++j) {
             const double tau = w[j] * dt;
-            fse::PhaseArgs pa = phase_args(p, tj, tau);
+            fse::PhaseArgs pa = phase_args(p, at_plan(tj), tau);
             if (p->lat) {
                 // the sub-step's lattice integral (and tau U) as the phase's grid potential
-                HIPCHK(L::lattice(p->lat_buf, p->U, p->n, geom(p), lat_args(p, tj, tau), st));
+                HIPCHK(L::lattice(p->lat_buf, p->U, p->n, geom(p), lat_args(p, at_plan(tj), tau), st));
                 pa.U = p->lat_buf;
                 pa.udt = 1.0;
             }
@@ -608,11 +617,11 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                 if (p->d == 3) {
                     PLAUNCH(p, FSE_PASS_PAD_FWD, st,
                             L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
-                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, tj - tau, tau, st));
+                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, at_plan(tj - tau), tau, st));
                     PLAUNCH(p, FSE_PASS_CROP_INV, st,
                             L::strided(N1, true, 2, p->X2, p->X1, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
                 } else {
-                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, tj - tau, tau, st));
+                    PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, at_plan(tj - tau), tau, st));
                 }
                 PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
                         L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
@@ -629,19 +638,22 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
         }
     }
     PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
-    p->t += nsteps * dt;
+    HIPCHK(fse::launch_time_add(p->tdev, nsteps * dt, st));
     return FSE_OK;
 }
 
 // Energy / mass / Lz reductions; kind 0 mass, 1 energy, 2 Lz.
 template <typename R> hipError_t deriv_axis(fse_plan p, int axis, const void* v, void* out, hipStream_t st);
 
-template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int kind, double* out, hipStream_t st) {
+// tr: the time of W(x~, t) and of a turning dipole axis (the plan's device time, or kFrame for the frame of
+// eq. SFSE, where the ground state is sought).
+template <typename R>
+fse_status reduce_impl(fse_plan p, const void* psi, int kind, double* out, hipStream_t st, TimeRef tr = at_plan()) {
     using L = fse::Launch<R>;
     const fse::GridGeom g = geom(p);
     const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
     if (kind == 0) {
-        HIPCHK(L::red_local(psi, nullptr, nullptr, p->n, g, 0, 0, 0, 0, p->partials, 0, kRedBlocks, st));
+        HIPCHK(L::red_local(psi, nullptr, nullptr, p->n, g, 0, 0, 0, 0, nullptr, 0, 0, p->partials, 0, kRedBlocks, st));
         HIPCHK(fse::launch_red_final(p->partials, kRedBlocks, 1, 0, vol, (double)p->n, p->beta, p->lambda, p->Omega,
                                      out, st));
         return FSE_OK;
@@ -656,18 +668,20 @@ template <typename R> fse_status reduce_impl(fse_plan p, const void* psi, int ki
     if (kind == 1) {
         const bool use_phi = p->nl;
         if (use_phi) {
-            s = potential_impl<R>(p, psi, 1, Phi, p->t, 0.0, st);
+            s = potential_impl<R>(p, psi, 1, Phi, tr, 0.0, st);
             if (s != FSE_OK) return s;
         }
         const double gx2 = p->gamma[0] * p->gamma[0], gy2 = p->gamma[1] * p->gamma[1];
         const double gz2 = (p->d == 3) ? p->gamma[2] * p->gamma[2] : 0.0;
-        const double th = 2.0 * p->Omega * p->t;
         hipError_t ee;
-        const void* Ux = extra_potential<R>(p, p->t, false, st, &ee);
+        const void* Ux = extra_potential<R>(p, tr, st, &ee);
         HIPCHK(ee);
+        // W(x~, t) = V(A(t) x~): its rotating part at the device time, or at a fixed time
+        const bool dev = tr.dev && trap_turns(p);
+        const double th = 2.0 * p->Omega * tr.off;
         HIPCHK(L::red_local(psi, use_phi ? Phi : nullptr, Ux, p->n, g, (gx2 + gy2) / 4.0, gz2 / 2.0,
-                            (gx2 - gy2) / 4.0 * std::cos(th), (gx2 - gy2) / 4.0 * std::sin(th), p->partials, 0,
-                            kRedBlocks, st));
+                            dev ? 0.0 : gdiff(p) * std::cos(th), dev ? 0.0 : gdiff(p) * std::sin(th),
+                            dev ? p->tdev : nullptr, p->Omega, gdiff(p), p->partials, 0, kRedBlocks, st));
     } else {
         // slots 0..4 unused for Lz; keep them defined
         HIPCHK(fse::launch_zero(p->partials, sizeof(double) * kRedBlocks * 5, st));
@@ -749,11 +763,11 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     // forward: psi1 and theta of every step
     if ((s = kin_full<R>(p, psi0, S(0), kp_h, st)) != FSE_OK) return s;
     for (int k = 0; k < nsteps; ++k) {
-        if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, p->t + k * dt, dt, st)) != FSE_OK) return s;
-        fse::PhaseArgs pa = phase_args(p, p->t + k * dt, dt);
+        if (p->nl && (s = potential_impl<R>(p, S(k), 1, Phi, at_plan(k * dt), dt, st)) != FSE_OK) return s;
+        fse::PhaseArgs pa = phase_args(p, at_plan(k * dt), dt);
         const void* Ux = p->U;
         if (p->lat) {
-            HIPCHK(L::lattice(p->lat_buf, p->U, p->n, gg, lat_args(p, p->t + k * dt, dt), st));
+            HIPCHK(L::lattice(p->lat_buf, p->U, p->n, gg, lat_args(p, at_plan(k * dt), dt), st));
             Ux = p->lat_buf;
             pa.udt = 1.0;
         }
@@ -765,7 +779,7 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     if ((s = kin_full<R>(p, g, g, km_h, st)) != FSE_OK) return s;
     for (int k = nsteps - 1; k >= 0; --k) {
         HIPCHK(L::adj_q(g, S(k), TH(k), q, gU, p->n, dt, st));
-        if (p->nl && (s = potential_impl<R>(p, q, 2, Phi, p->t + k * dt, dt, st)) != FSE_OK) return s;
+        if (p->nl && (s = potential_impl<R>(p, q, 2, Phi, at_plan(k * dt), dt, st)) != FSE_OK) return s;
         HIPCHK(L::adj_g1(g, S(k), TH(k), q, p->nl ? Phi : nullptr, p->n, p->beta * dt, p->lambda * dt, st));
         if ((s = kin_full<R>(p, g, g, (k > 0) ? km_f : km_h, st)) != FSE_OK) return s;
     }
@@ -876,6 +890,19 @@ fse_status time_candidates(const std::vector<std::function<hipError_t()>>& fs, h
     return s;
 }
 
+// The plan's device time, read or written after the device has drained (host queries, not for capture).
+fse_status read_time(const fse_plan p, double* t) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(t, p->tdev, sizeof(double), hipMemcpyDeviceToHost));
+    return FSE_OK;
+}
+
+fse_status write_time(fse_plan p, double t) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(p->tdev, &t, sizeof(double), hipMemcpyHostToDevice));
+    return FSE_OK;
+}
+
 bool kin_has_alt(const fse_plan p) { return fse::line_has_alt(p->last()); }
 bool conv_has_alt(const fse_plan p) {
     const int n = p->last();
@@ -892,7 +919,8 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     void* A = p->diag;
     HIPCHK(fse::launch_zero(A, (size_t)p->n * p->csize, st));
     const double dt = std::isnan(p->kin_tau[1]) ? 1e-3 : p->kin_tau[1];
-    const double t_keep = p->t;
+    double t_keep = 0.0;
+    if ((s = read_time(p, &t_keep)) != FSE_OK) return s;
     const bool prof_keep = p->prof;
     p->prof = false;
     const int keep[3] = {p->sched[0], p->sched[1], p->sched[2]};
@@ -909,10 +937,10 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
         });
     std::vector<double> ms(fs.size());
     s = time_candidates(fs, st, ms.data());
-    p->t = t_keep;
     p->prof = prof_keep;
     for (int q = 0; q < 3; ++q) p->sched[q] = keep[q];
     if (s != FSE_OK) return s;
+    if ((s = write_time(p, t_keep)) != FSE_OK) return s;
     int best = -1;
     double tbest = 0.0;
     for (size_t c = 0; c < cands.size(); ++c) {
@@ -937,9 +965,10 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
 // rotation x = A(t) x~ applied to the FP64 totals.
 template <typename R> fse_status moments_impl(fse_plan p, const void* psi, double* out, hipStream_t st) {
     const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
-    const double th = p->Omega * p->t;
     HIPCHK(fse::Launch<R>::red_moments(psi, p->n, geom(p), p->partials, kRedBlocks, st));
-    HIPCHK(fse::launch_moments_final(p->partials, kRedBlocks, vol, std::cos(th), std::sin(th), out, st));
+    // the frame angle Omega t at the device time
+    HIPCHK(fse::launch_moments_final(p->partials, kRedBlocks, vol, 1.0, 0.0, p->Omega != 0.0 ? p->tdev : nullptr,
+                                     p->Omega, out, st));
     return FSE_OK;
 }
 
@@ -952,7 +981,7 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
     void* B = base + (size_t)p->n * p->csize;
     void* Phi = base + (size_t)p->n * 2 * p->csize;
     if (p->nl) {
-        s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, 0.0, 0.0, st);
+        s = potential_impl<R>(p, rho ? rho : psi, rho ? 2 : 1, Phi, kFrame, 0.0, st);
         if (s != FSE_OK) return s;
     }
     // kinetic part: H = (1/2)(-Lap+m^2)^s psi through the strided forward passes
@@ -978,7 +1007,7 @@ template <typename R> fse_status apply_H_impl(fse_plan p, const void* psi, void*
         HIPCHK(L::H_accum(H, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, p->Omega, 0, 0, 0, 0, 0, st));
     }
     hipError_t ee;
-    const void* Ux = extra_potential<R>(p, 0.0, true, st, &ee);
+    const void* Ux = extra_potential<R>(p, kFrame, st, &ee);
     HIPCHK(ee);
     HIPCHK(L::H_accum(H, nullptr, psi, rho, p->nl ? Phi : nullptr, Ux, p->n, g, 2, p->Omega, p->beta, p->lambda,
                       p->gamma[0], p->gamma[1], (p->d == 3) ? p->gamma[2] : 0.0, st));
@@ -1105,10 +1134,10 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
     const double c0 = 1.0 / dt;
     // frozen W^n = V + beta rho^n + lambda Phi^n
     if (p->nl) {
-        if ((s = potential_impl<R>(p, psi, 1, b.Phi, 0.0, 0.0, st)) != FSE_OK) return s;
+        if ((s = potential_impl<R>(p, psi, 1, b.Phi, kFrame, 0.0, st)) != FSE_OK) return s;
     }
     hipError_t ee;
-    const void* Ux = extra_potential<R>(p, 0.0, true, st, &ee);
+    const void* Ux = extra_potential<R>(p, kFrame, st, &ee);
     HIPCHK(ee);
     HIPCHK(L::gs_frozen(psi, p->nl ? b.Phi : nullptr, Ux, b.W, p->n, g, p->beta, p->lambda, p->gamma[0], p->gamma[1],
                         (p->d == 3) ? p->gamma[2] : 0.0, st));
@@ -1204,6 +1233,66 @@ template <typename R> fse_status gs_step_impl(fse_plan p, void* psi, double dt, 
         stats->converged = conv ? 1 : 0;
         stats->residual = res;
         stats->diff_inf = diff;
+    }
+    return FSE_OK;
+}
+
+// The energy E(psi) of eq. energy in the frame of eq. SFSE (the functional the
+// gradient flow decreases), reduced on the device in FP64 and read back.
+template <typename R> fse_status gs_energy(fse_plan p, const void* psi, double* E, hipStream_t st) {
+    fse_status s = reduce_impl<R>(p, psi, 1, p->gs_out, st, kFrame);
+    if (s != FSE_OK) return s;
+    double e[6];
+    HIPCHK(hipMemcpyAsync(e, p->gs_out, sizeof(e), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *E = e[5];
+    return FSE_OK;
+}
+
+// Ground-state steps until a stopping rule holds after a step: the paper's
+// ||phi^n - phi^{n+1}||_inf <= eps_diff dt (Section 3.3), or an energy change
+// |E^{n+1} - E^n| <= eps_energy; rules with a tolerance <= 0 are not used.
+template <typename R>
+fse_status gs_run_impl(fse_plan p, void* psi, double dt, double tol, int maxit, int max_steps, double eps_diff,
+                       double eps_energy, double* trace, fse_gs_run_stats* rs, hipStream_t st) {
+    GsBuf b;
+    fse_status s = ensure_gs(p, &b);
+    if (s != FSE_OK) return s;
+    const bool want_e = eps_energy > 0.0 || trace != nullptr;
+    double E = NAN, dE = NAN;
+    if (want_e && (s = gs_energy<R>(p, psi, &E, st)) != FSE_OK) return s;
+    if (trace) trace[0] = E;
+    fse_gs_stats s1{};
+    int n = 0, rule = 0;
+    long its = 0;
+    while (n < max_steps) {
+        if ((s = gs_step_impl<R>(p, psi, dt, tol, maxit, &s1, st)) != FSE_OK) return s;
+        ++n;
+        its += s1.iterations;
+        if (want_e) {
+            const double Eprev = E;
+            if ((s = gs_energy<R>(p, psi, &E, st)) != FSE_OK) return s;
+            dE = std::fabs(E - Eprev);
+            if (trace) trace[n] = E;
+        }
+        if (eps_diff > 0.0 && s1.diff_inf <= eps_diff * dt) {
+            rule = 1;
+            break;
+        }
+        if (eps_energy > 0.0 && dE <= eps_energy) {
+            rule = 2;
+            break;
+        }
+    }
+    if (rs) {
+        rs->steps = n;
+        rs->converged = rule != 0;
+        rs->rule = rule;
+        rs->krylov_iterations = (int)std::min<long>(its, 0x7fffffffL);
+        rs->diff_inf = s1.diff_inf;
+        rs->energy = E;
+        rs->energy_change = dE;
+        rs->residual = s1.residual;
     }
     return FSE_OK;
 }
@@ -1310,7 +1399,11 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
         }
     }
     if ((st = dev_alloc(p, (void**)&p->partials, sizeof(double) * kRedBlocks * kRedSlots)) != FSE_OK) return bail(st);
+    if ((st = dev_alloc(p, (void**)&p->tdev, sizeof(double))) != FSE_OK) return bail(st);
     if (hipStreamSynchronize(hs) != hipSuccess) return bail(fail(FSE_ERR_HIP, "stream synchronisation failed"));
+    const double t0 = 0.0;
+    if (hipMemcpy(p->tdev, &t0, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        return bail(fail(FSE_ERR_HIP, "copy of the initial time failed"));
     *out = p;
     return FSE_OK;
 }
@@ -1525,16 +1618,16 @@ fse_status fse_workspace_size(fse_plan plan, size_t* bytes) {
 }
 
 fse_status fse_set_time(fse_plan plan, double t) {
+    g_err.clear();
     if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
     if (!std::isfinite(t)) return fail(FSE_ERR_ARG, "t must be finite");
-    plan->t = t;
-    return FSE_OK;
+    return write_time(plan, t);
 }
 
 fse_status fse_get_time(fse_plan plan, double* t) {
+    g_err.clear();
     if (!plan || !t) return fail(FSE_ERR_ARG, "plan and t must not be NULL");
-    *t = plan->t;
-    return FSE_OK;
+    return read_time(plan, t);
 }
 
 fse_status fse_set_guard(fse_plan plan, double tol) {
@@ -1638,12 +1731,30 @@ fse_status fse_gs_step(fse_plan plan, void* psi, double dt, double tol, int maxi
                                   : gs_step_impl<float>(plan, psi, dt, tol, maxit, stats, st);
 }
 
+fse_status fse_gs_run(fse_plan plan, void* psi, double dt, double tol, int maxit, int max_steps, double eps_diff,
+                      double eps_energy, double* energy_trace, fse_gs_run_stats* stats, void* stream) {
+    g_err.clear();
+    if (!plan || !psi) return fail(FSE_ERR_ARG, "plan and psi must not be NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FSE_ERR_ARG, "dt must be finite and > 0");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FSE_ERR_ARG, "tol must be finite and > 0");
+    if (maxit < 1 || max_steps < 1) return fail(FSE_ERR_ARG, "maxit and max_steps must be >= 1");
+    if (!std::isfinite(eps_diff) || !std::isfinite(eps_energy))
+        return fail(FSE_ERR_ARG, "eps_diff and eps_energy must be finite");
+    if (plan->U && plan->Omega != 0.0)
+        return fail(FSE_ERR_UNSUPPORTED,
+                    "a grid potential set by fse_set_potential needs Omega = 0 in the ground-state step");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128
+               ? gs_run_impl<double>(plan, psi, dt, tol, maxit, max_steps, eps_diff, eps_energy, energy_trace, stats, st)
+               : gs_run_impl<float>(plan, psi, dt, tol, maxit, max_steps, eps_diff, eps_energy, energy_trace, stats, st);
+}
+
 fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, void* stream) {
     g_err.clear();
     if (!plan || !psi || !Phi) return fail(FSE_ERR_ARG, "plan, psi and Phi must not be NULL");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    return plan->prec == FSE_C128 ? potential_impl<double>(plan, psi, 1, Phi, plan->t, 0.0, st)
-                                  : potential_impl<float>(plan, psi, 1, Phi, plan->t, 0.0, st);
+    return plan->prec == FSE_C128 ? potential_impl<double>(plan, psi, 1, Phi, at_plan(), 0.0, st)
+                                  : potential_impl<float>(plan, psi, 1, Phi, at_plan(), 0.0, st);
 }
 
 fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* stream) {
@@ -1873,6 +1984,7 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
     }
     if (hipMalloc((void**)&b->t_dev, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_NOMEM, "hipMalloc"));
     if (hipMemset(b->t_dev, 0, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_HIP, "hipMemset"));
+    for (int i = 0; i < count; ++i) b->plans[i]->tdev = b->t_dev + i;  // the diagnostics read the instance's time
     std::vector<fse::BInst> desc;
     for (auto& g : b->groups) {
         g.first = desc.size();
@@ -1958,10 +2070,7 @@ fse_status fse_batch_step(fse_batch batch, void* psi_packed, int nsteps, void* s
         exec = it->second;
     }
     HIPCHK(hipGraphLaunch(exec, static_cast<hipStream_t>(stream)));
-    for (int i = 0; i < batch->count; ++i) {
-        batch->t_host[i] += nsteps * batch->inst[i].dt;
-        batch->plans[i]->t = batch->t_host[i];
-    }
+    for (int i = 0; i < batch->count; ++i) batch->t_host[i] += nsteps * batch->inst[i].dt;
     return FSE_OK;
 }
 
@@ -1970,8 +2079,7 @@ fse_status fse_batch_reduce(fse_batch batch, const void* psi_packed, double* out
     if (!batch || !psi_packed || !out_dev) return fail(FSE_ERR_ARG, "batch, psi_packed and out_dev must not be NULL");
     const char* base = static_cast<const char*>(psi_packed);
     for (int i = 0; i < batch->count; ++i) {
-        fse_plan p = batch->plans[i];
-        p->t = batch->t_host[i];
+        fse_plan p = batch->plans[i];  // (its device time is the instance's entry of the batch's array)
         const void* psi = base + batch->off[i] * batch->csize;
         hipStream_t st = static_cast<hipStream_t>(stream);
         fse_status s = (p->prec == FSE_C128) ? reduce_impl<double>(p, psi, 0, out_dev + 7 * i, st)

@@ -447,18 +447,21 @@ __device__ __forceinline__ void conv_full_body(
     const long row = mult_row(gl, li);
     R kq[FF::BK][FF::RK];
     if constexpr (QF) {
+        QForm qd = *qf;
+        if (qd.tp) qform_fill(qd, *qd.tp + qd.toff, qd.tau);
+        const QForm* q = &qd;
         // row frequencies (signed; odd products vanish at Nyquist indices)
         const int k0 = gl / li.D1, k1r = gl % li.D1;
-        const int k1 = (k1r <= qf->n1) ? k1r : k1r - li.D1;
-        const double a0 = k0 * qf->dk0, a1 = k1 * qf->dk1;
-        const double x0 = (k0 == qf->n0) ? 0.0 : a0, x1 = (k1r == qf->n1) ? 0.0 : a1;
-        const double base = qf->m00 * a0 * a0 + qf->m11 * a1 * a1 + 2.0 * qf->m01 * x0 * x1;
-        const double lin = 2.0 * (qf->m02 * x0 + qf->m12 * x1);
+        const int k1 = (k1r <= q->n1) ? k1r : k1r - li.D1;
+        const double a0 = k0 * q->dk0, a1 = k1 * q->dk1;
+        const double x0 = (k0 == q->n0) ? 0.0 : a0, x1 = (k1r == q->n1) ? 0.0 : a1;
+        const double base = q->m00 * a0 * a0 + q->m11 * a1 * a1 + 2.0 * q->m01 * x0 * x1;
+        const double lin = 2.0 * (q->m02 * x0 + q->m12 * x1);
         for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) {
             const int k2 = (p <= M / 2) ? p : p - M;
-            const double a2 = k2 * qf->dk2, x2 = (p == M / 2) ? 0.0 : a2;
-            const double Q = base + qf->m22 * a2 * a2 + lin * x2;
-            kq[b][r] = R(qf->c0 + (double)mult[row + min(p, M - p)] * Q);
+            const double a2 = k2 * q->dk2, x2 = (p == M / 2) ? 0.0 : a2;
+            const double Q = base + q->m22 * a2 * a2 + lin * x2;
+            kq[b][r] = R(q->c0 + (double)mult[row + min(p, M - p)] * Q);
         });
     } else {
         for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
@@ -668,12 +671,14 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
             yv = R(pa.y0 + c * pa.hy);
             zv = R(0);
         }
+        double pcc, pcs;
+        phase_time(pa, &pcc, &pcs);
         const R y2 = yv * yv;
-        const R base = R(pa.cz) * (zv * zv) + R(pa.ca - pa.cc) * y2;
+        const R base = R(pa.cz) * (zv * zv) + R(pa.ca - pcc) * y2;
         const R* Ux = static_cast<const R*>(pa.U);
         for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
             const R x = R(pa.x0 + e * pa.hx);
-            const R Pv = base + R(pa.ca + pa.cc) * (x * x) + R(pa.cs) * (R(2) * x * yv);
+            const R Pv = base + R(pa.ca + pcc) * (x * x) + R(pcs) * (R(2) * x * yv);
             const T v = psi[b][r];
             const R rho = v.x * v.x + v.y * v.y;
             R th = R(pa.bdt) * rho + R(pa.ldt) * phi[b][r] + Pv;
@@ -714,7 +719,6 @@ __global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_c2r_phase(const type
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
     const double tn = *b.t + kstep * b.dt;
-    const double f = (b.Omega == 0.0) ? b.dt : sin(b.Omega * b.dt) / b.Omega;
     PhaseArgs pa;
     pa.x0 = b.x0;
     pa.hx = b.hx;
@@ -725,8 +729,7 @@ __device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
     pa.N2 = 0;
     pa.ca = b.ca;
     pa.cz = 0.0;
-    pa.cc = (b.Omega == 0.0) ? b.gdiff * b.dt : b.gdiff * cos(b.Omega * (2.0 * tn + b.dt)) * f;
-    pa.cs = (b.Omega == 0.0) ? 0.0 : b.gdiff * sin(b.Omega * (2.0 * tn + b.dt)) * f;
+    trap_rotating(tn, b.dt, b.Omega, b.gdiff, &pa.cc, &pa.cs);
     pa.bdt = b.bdt;
     pa.ldt = b.ldt;
     pa.U = nullptr;
@@ -801,6 +804,11 @@ __global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_b_c2r_phase(void* ps
 static __global__ void k_b_time(const BInst* __restrict__ bi, int count, int nsteps) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) *bi[i].t += nsteps * bi[i].dt;
+}
+
+// Advances a plan's device time by dtot (one thread).
+static __global__ void k_time_add(double* t, double dtot) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t += dtot;
 }
 
 // ---------------------------------------------------------------------------
@@ -901,11 +909,18 @@ __device__ __forceinline__ void decode(long i, const GridGeom& g, int& i0, int& 
 
 // slots: 0 sum rho, 1 sum W rho, 2 sum rho^2, 3 sum Phi rho.
 // W = wa (x^2+y^2) + wz z^2 + wc (x^2-y^2) + ws 2xy, plus U when given.
+// With tp set, wc = gd cos(2 Omega t) and ws = gd sin(2 Omega t) at the device time t = *tp.
 template <typename R>
 __global__ __launch_bounds__(RED_THREADS) void k_red_local(const typename CT<R>::T* __restrict__ psi,
                                                            const R* __restrict__ Phi, const R* __restrict__ U, long n,
                                                            GridGeom g, double wa, double wz, double wc, double ws,
+                                                           const double* tp, double Om, double gd,
                                                            double* partials, int slot0) {
+    if (tp) {
+        const double th = 2.0 * Om * *tp;
+        wc = gd * cos(th);
+        ws = gd * sin(th);
+    }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (long i = blockIdx.x * (long)RED_THREADS + threadIdx.x; i < n; i += (long)gridDim.x * RED_THREADS) {
         int i0, i1, i2;
@@ -990,7 +1005,12 @@ __global__ __launch_bounds__(RED_THREADS) void k_red_moments(const typename CT<R
 // the eight moment slots, with x = A x~, A = [[c, s], [-s, c]] on (x, y):
 //   out = {N, x_c, y_c, z_c, delta_x, delta_y, delta_z}.  One block.
 static __global__ __launch_bounds__(RED_THREADS) void k_moments_final(const double* __restrict__ partials, int nblk,
-                                                               double vol, double c, double s, double* out) {
+                                                               double vol, double c, double s, const double* tp,
+                                                               double Om, double* out) {
+    if (tp) {  // frame angle Omega t at the device time
+        c = cos(Om * *tp);
+        s = sin(Om * *tp);
+    }
     __shared__ double tot[8];
     __shared__ double red[RED_THREADS / 64];
     for (int k = 0; k < 8; ++k) {
@@ -1101,6 +1121,7 @@ __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R
 // Lattice potential or its time integral (LatArgs), plus uf U when U is given; FP64 inside.
 template <typename R>
 __global__ void k_lattice(R* __restrict__ out, const R* __restrict__ U, long n, GridGeom g, LatArgs la) {
+    if (la.tp) lat_fill(la, *la.tp + la.toff);
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         decode(i, g, i0, i1, i2);

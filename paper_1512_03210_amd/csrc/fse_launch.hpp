@@ -42,9 +42,10 @@ template <typename R> struct Launch {
     // scale * exp(-i tau omega/2), kind 1 the resolvent scale / (c0 + omega/2), kind 2 scale * omega/2.
     static hipError_t build_kin(void* Q, int T0, int T1, int T2, double dmu0, double dmu1, double dmu2, double s,
                                 double m2, int kind, double tau, double c0, double scale, hipStream_t st);
+    // W = wa (x^2+y^2) + wz z^2 + wc (x^2-y^2) + ws 2xy; with tp set, wc and ws are gd cos / sin(2 Om *tp).
     static hipError_t red_local(const void* psi, const void* Phi, const void* U, long n, const GridGeom& g, double wa,
-                                double wz, double wc, double ws, double* partials, int slot0, int nblk,
-                                hipStream_t st);
+                                double wz, double wc, double ws, const double* tp, double Om, double gd,
+                                double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_kin(const void* ph, long n, const GridGeom& g, double dmu0, double dmu1, double dmu2,
                               double s, double m2, double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_lz(const void* psi, const void* D, long n, const GridGeom& g, int coord_axis,
@@ -100,15 +101,18 @@ bool line_has_alt(int n);
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);
 
-// out[0..6] = lab-frame {N, x_c, y_c, z_c, delta_x, delta_y, delta_z} from
-// the eight moment slots; (c, s) = (cos, sin) of the frame angle.
 // Zero fill of `bytes` (a multiple of 8) at p, as a kernel: unlike a runtime
 // memset it may be recorded into a captured graph like the other passes.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 // Numeric guard: g = {M0, M, flag}.  M0 = M if M0 is NaN (first check); flag
 // = 1 if M or M0 is not finite or |M - M0| > tol |M0| (the flag stays set).
 hipError_t launch_guard(double* g, double tol, hipStream_t st);
-hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
-                                hipStream_t st);
+// out[0..6] = lab-frame {N, x_c, y_c, z_c, delta_x, delta_y, delta_z} from
+// the eight moment slots; (c, s) = (cos, sin) of the frame angle, or with tp
+// set those of Om * *tp.
+hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, const double* tp,
+                                double Om, double* out, hipStream_t st);
+// *t += dtot on the stream (a plan's device time).
+hipError_t launch_time_add(double* t, double dtot, hipStream_t st);
 
 }  // namespace fse

@@ -79,9 +79,14 @@ hipError_t launch_guard(double* g, double tol, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, double* out,
-                                hipStream_t st) {
-    k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, out);
+hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, const double* tp,
+                                double Om, double* out, hipStream_t st) {
+    k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, tp, Om, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_time_add(double* t, double dtot, hipStream_t st) {
+    k_time_add<<<1, 64, 0, st>>>(t, dtot);
     return hipGetLastError();
 }
 

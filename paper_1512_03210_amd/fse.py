@@ -34,6 +34,7 @@ EXPORTS = [
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
     "fse_batch_reduce", "fse_batch_times", "fse_gs_step", "fse_set_guard", "fse_guard_status",
+    "fse_gs_run",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -52,6 +53,12 @@ class Kernel(ctypes.Structure):
 class GsStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("residual", ctypes.c_double),
                 ("diff_inf", ctypes.c_double)]
+
+
+class GsRunStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int), ("converged", ctypes.c_int), ("rule", ctypes.c_int),
+                ("krylov_iterations", ctypes.c_int), ("diff_inf", ctypes.c_double), ("energy", ctypes.c_double),
+                ("energy_change", ctypes.c_double), ("residual", ctypes.c_double)]
 
 
 class Instance(ctypes.Structure):
@@ -114,6 +121,7 @@ def lib():
         "fse_batch_reduce": (st, [vp, vp, vp, vp]),
         "fse_batch_times": (st, [vp, dp]),
         "fse_gs_step": (st, [vp, vp, d, d, i, ctypes.POINTER(GsStats), vp]),
+        "fse_gs_run": (st, [vp, vp, d, d, i, i, d, d, dp, ctypes.POINTER(GsRunStats), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -385,6 +393,22 @@ class Plan:
                                  _stream(stream)))
         return {"iterations": st.iterations, "converged": bool(st.converged), "residual": st.residual,
                 "diff_inf": st.diff_inf}
+
+    def gs_run(self, psi, dt: float, eps_diff: float = 0.0, eps_energy: float = 0.0, max_steps: int = 1000,
+               tol: float = 1e-12, maxit: int = 1000, trace: bool = True, stream=None) -> dict:
+        """Ground-state steps until ||psi^n - psi^{n+1}||_inf <= eps_diff dt or |E^{n+1} - E^n| <= eps_energy
+        (fse_gs_run; a tolerance <= 0 disables its rule), in place on psi; returns the statistics and, with
+        trace, the energies E(psi^0), ..., E(psi^steps)."""
+        self._check_psi(psi)
+        st = GsRunStats()
+        buf = (ctypes.c_double * (int(max_steps) + 1))() if trace else None
+        _check(lib().fse_gs_run(self._h, _ptr(psi), float(dt), float(tol), int(maxit), int(max_steps),
+                                float(eps_diff), float(eps_energy), buf, ctypes.byref(st), _stream(stream)))
+        out = {k: getattr(st, k) for k, _ in GsRunStats._fields_}
+        out["converged"] = bool(out["converged"])
+        if trace:
+            out["energies"] = [float(buf[k]) for k in range(st.steps + 1)]
+        return out
 
     def set_profiling(self, enable: bool):
         _check(lib().fse_set_profiling(self._h, 1 if enable else 0))

@@ -190,3 +190,45 @@ def test_full_size_step_against_oracle_samples(prec, tol, gate):
     _note(f"[gs] 256^3 prec={prec}: samples rel {err:.3e}; GPU {st['iterations']} its res {st['residual']:.1e}")
     assert st["converged"] and st["residual"] <= tol
     assert err < gate
+
+
+GS_RUN = W.Params(d=2, N=(32, 32), L=(7.0, 7.0), s=0.9, Omega=0.4, gamma=(1.0, 1.1), beta=10.0, lam=1.0,
+                  kernel="coulomb", coef=1.0 / (2.0 * math.pi), dt=0.5, name="gsrun2d")
+
+
+@pytest.mark.parametrize("rule,kw", [(1, dict(eps_diff=1e-9)), (2, dict(eps_energy=1e-12))])
+def test_run_to_convergence_against_oracle(rule, kw):
+    # fse_gs_run against the oracle's loop with the same stopping rule (Section 3.2 flow, Section 3.3 rule)
+    p = GS_RUN
+    psi0 = _psi0(p)
+    g = ogs.GroundState(_oracle(p), p.dt)
+    ref, n, orule, en = g.run_to(psi0, max_steps=600, rtol=1e-12, **kw)
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(psi0, fse.C128)
+    st = plan.gs_run(x, p.dt, max_steps=600, tol=1e-12, **kw)
+    err = _rel(x.cpu().numpy(), ref)
+    m = min(len(en), len(st["energies"]))
+    de = max(abs(a - b) for a, b in zip(en[:m], st["energies"][:m]))
+    _note(f"[gs-run] rule {rule}: GPU {st['steps']} steps ({st['krylov_iterations']} Krylov its), oracle {n}; "
+          f"rel L2 {err:.3e}; max energy difference {de:.3e}; E = {st['energy']:.15f}")
+    assert orule == rule and st["converged"] and st["rule"] == rule
+    assert abs(st["steps"] - n) <= 1
+    assert err < 1e-10
+    assert de < 1e-11 and abs(st["energy"] - en[-1]) < 1e-10
+    assert all(b <= a + 1e-13 for a, b in zip(st["energies"], st["energies"][1:]))  # the flow lowers E
+
+
+def test_run_argument_errors_and_max_steps():
+    p = GS_RUN
+    plan = fse.Plan.from_params(p, fse.C128)
+    x = _dev(_psi0(p), fse.C128)
+    for bad in (dict(dt=0.0), dict(max_steps=0), dict(tol=-1.0), dict(eps_diff=float("nan"))):
+        a = dict(dt=p.dt, max_steps=5, tol=1e-12)
+        a.update(bad)
+        dt = a.pop("dt")
+        with pytest.raises(fse.FseError):
+            plan.gs_run(x, dt, **a)
+    st = plan.gs_run(x, p.dt, eps_energy=1e-30, max_steps=3)
+    assert (st["steps"], st["rule"], st["converged"], len(st["energies"])) == (3, 0, False, 4)
+    st = plan.gs_run(x, p.dt, max_steps=2, trace=False)  # no rule, no trace: no energy computed
+    assert st["steps"] == 2 and math.isnan(st["energy"])
