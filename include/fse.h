@@ -261,6 +261,17 @@ fse_status fse_nonlocal_potential(fse_plan plan, const void* psi, void* Phi, voi
 /* Mass h^d sum |psi|^2 (eq. mass) -> out_dev[0]. */
 fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the mass of
+ * fse_mass, computed by the same kernels, with the per-block partial sums in a
+ * fixed 32 KiB device array of the library instead of the plan's buffer.  No
+ * allocation of any kind; asynchronous on `stream`; out_dev[0] as fse_mass.
+ * The partials need 4 x 1024 doubles for any grid size (a larger need would be
+ * refused with FSE_ERR_ARG).  All calls on one device share that device's
+ * array: calls that overlap on one device (two streams, two host threads)
+ * race and must be ordered by the caller. */
+fse_status fse_mass_noalloc(fse_plan plan, const void* psi, double* out_dev, void* stream);
+
 /* Energy parts (eq. energy), in rotating coordinates at the plan's time with
  * W(x~,t) = V(A(t)x~):
  * out_dev[0..5] = E_kin, E_pot, E_int, E_non, E_rot = -Omega <Lz>, E_total.

@@ -1297,6 +1297,52 @@ fse_status gs_run_impl(fse_plan p, void* psi, double dt, double tol, int maxit, 
     return FSE_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Allocation-free mass reduction (fse_mass_noalloc): the per-block partial
+// sums live in a fixed device array instead of the plan's buffer.  Host code
+// never passes the array's name to a kernel (in host code it names a host-side
+// stand-in); its device address is taken once per device with
+// hipGetSymbolAddress and kept.  Every call on a device shares that device's
+// array, so calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+constexpr int kNoallocSlots = 4;  // k_red_local writes four slots per block
+static __device__ __align__(256) double scratch[kNoallocSlots * kRedBlocks];
+constexpr size_t kScratchBytes = sizeof(double) * kNoallocSlots * kRedBlocks;
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_dev;  // device ordinal -> address of that device's scratch
+
+fse_status scratch_address(double** out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_dev.find(dev);
+    if (it == g_scratch_dev.end()) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(FSE_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        it = g_scratch_dev.emplace(dev, static_cast<double*>(ptr)).first;
+    }
+    *out = it->second;
+    return FSE_OK;
+}
+
+template <typename R> fse_status mass_noalloc_impl(fse_plan p, const void* psi, double* out, hipStream_t st) {
+    // the partials this reduction writes: kNoallocSlots slots of kRedBlocks blocks, whatever the grid size
+    const size_t need = sizeof(double) * kNoallocSlots * kRedBlocks;
+    if (need > kScratchBytes)
+        return fail(FSE_ERR_ARG, "the reduction needs %zu bytes of scratch, more than the %zu available", need,
+                    kScratchBytes);
+    double* sp = nullptr;
+    if (fse_status s = scratch_address(&sp); s != FSE_OK) return s;
+    const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
+    HIPCHK(fse::Launch<R>::red_local(psi, nullptr, nullptr, p->n, geom(p), 0, 0, 0, 0, nullptr, 0, 0, sp, 0, kRedBlocks,
+                                     st));
+    HIPCHK(fse::launch_red_final(sp, kRedBlocks, 1, 0, vol, (double)p->n, p->beta, p->lambda, p->Omega, out, st));
+    return FSE_OK;
+}
+
 void destroy(fse_plan p) {
     if (!p) return;
     for (hipEvent_t e : p->ev) (void)hipEventDestroy(e);
@@ -1763,6 +1809,14 @@ fse_status fse_mass(fse_plan plan, const void* psi, double* out_dev, void* strea
     hipStream_t st = static_cast<hipStream_t>(stream);
     return plan->prec == FSE_C128 ? reduce_impl<double>(plan, psi, 0, out_dev, st)
                                   : reduce_impl<float>(plan, psi, 0, out_dev, st);
+}
+
+fse_status fse_mass_noalloc(fse_plan plan, const void* psi, double* out_dev, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    return plan->prec == FSE_C128 ? mass_noalloc_impl<double>(plan, psi, out_dev, st)
+                                  : mass_noalloc_impl<float>(plan, psi, out_dev, st);
 }
 
 fse_status fse_energy(fse_plan plan, const void* psi, double* out_dev, void* stream) {

@@ -34,7 +34,7 @@ EXPORTS = [
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
     "fse_batch_reduce", "fse_batch_times", "fse_gs_step", "fse_set_guard", "fse_guard_status",
-    "fse_gs_run",
+    "fse_mass_noalloc", "fse_gs_run",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -104,6 +104,7 @@ def lib():
         "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
         "fse_nonlocal_potential": (st, [vp, vp, vp, vp]),
         "fse_mass": (st, [vp, vp, vp, vp]),
+        "fse_mass_noalloc": (st, [vp, vp, vp, vp]),
         "fse_energy": (st, [vp, vp, vp, vp]),
         "fse_angular_momentum": (st, [vp, vp, vp, vp]),
         "fse_moments": (st, [vp, vp, vp, vp]),
@@ -371,6 +372,16 @@ class Plan:
 
     def mass(self, psi, stream=None):
         return self._scalar(lib().fse_mass, psi, 1, stream)
+
+    def mass_noalloc(self, psi, out, stream=None):
+        """fse_mass_noalloc into the caller's float64 device tensor `out` (at least one element): the
+        library allocates nothing for this call."""
+        import torch
+        self._check_psi(psi)
+        if out.dtype != torch.float64 or not out.is_cuda or out.numel() < 1 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 device tensor with at least one element")
+        _check(lib().fse_mass_noalloc(self._h, _ptr(psi), _ptr(out), _stream(stream)))
+        return out
 
     def energy(self, psi, stream=None):
         """Device tensor [E_kin, E_pot, E_int, E_non, E_rot, E_total]."""
