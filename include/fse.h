@@ -146,6 +146,23 @@ fse_status fse_get_time(fse_plan plan, double* t);
  * dt may be negative (backward in time); nsteps >= 0.  t += nsteps*dt. */
 fse_status fse_step(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
+/* FP64 mass renormalisation of a step call (fse_step, fse_step4).  The split
+ * step conserves the discrete mass exactly (eq. MassEnerg); in FP32 the FFT
+ * twiddle tables carry modulus residuals of up to 5e-8 that bias it by about
+ * 1e-8 per transform, depending on the data.  With renormalisation on, a call
+ * reduces the mass of psi in FP64 at its start, reduces it again before its
+ * last pass (the inverse FFT of axis 0) and scales that pass's output by
+ * sqrt(M_start / M_before): the call returns a state with the mass it was
+ * given (to FP64 reduction accuracy), at the cost of two extra reads of the
+ * state per call.  The bias inside a call is not corrected.  Default: on for
+ * complex64 plans, off for complex128.  Asynchronous; graph-capturable. */
+fse_status fse_set_mass_renorm(fse_plan plan, int enable);
+
+/* Whether it is on, and (factor_mass nullable, 3 doubles) the last call's
+ * factor, the mass before the exit pass and the mass at the call's start
+ * (synchronises the device). */
+fse_status fse_get_mass_renorm(fse_plan plan, int* enabled, double* factor_mass);
+
 /* Optional numeric guard (failure detection; the paper has none).  With
  * tol > 0, every fse_step and fse_step4 call ends with an FP64 mass reduction
  * of its result on the call's stream, compared on the device with the mass
@@ -245,6 +262,13 @@ fse_status fse_step_adjoint(fse_plan plan, const void* psi0, int nsteps, double 
  * operator of eq. AME, whose expectation fse_angular_momentum returns).
  * out must not alias psi. */
 fse_status fse_apply_Lz(fse_plan plan, const void* psi, void* out, void* stream);
+
+/* Gradient of g <Lz> with respect to psi (torch's convention, as
+ * fse_step_adjoint): <Lz> = h^d sum conj(psi) Lz psi with Lz Hermitian, so
+ *   out = 2 h^d g Lz psi,
+ * g = *g_dev (one double in device memory, e.g. the upstream gradient of a
+ * loss; NULL means g = 1).  out must not alias psi. */
+fse_status fse_angular_momentum_grad(fse_plan plan, const void* psi, const double* g_dev, void* out, void* stream);
 
 /* H psi in the lab frame (the operator of eq. SFSE; with a frozen density it
  * is the operator A^{BE,n} of Section 3.2 without its I/dt part):
@@ -434,6 +458,10 @@ fse_status fse_get_profile(fse_plan plan, double* ms, int* count, int npass);
  * to measure the achievable HBM bandwidth and to calibrate the memory
  * counters against a kernel of known traffic. */
 fse_status fse_device_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* The same copy with non-temporal loads and stores (streaming past the
+ * caches), the reference for buffers far beyond the last-level cache. */
+fse_status fse_device_copy_nt(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Message describing the calling thread's last error ("" if none). */
 const char* fse_last_error(void);

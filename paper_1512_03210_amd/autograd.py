@@ -9,14 +9,13 @@ pass reverses the segments last to first, each call of fse_step_adjoint
 recomputing its own forward states from the segment's checkpoint.
 The plan is left with U as its grid potential and its time advanced by
 nsteps dt, as after the same fse_step calls.
-angular_momentum(plan, psi) is <Lz> with the gradient 2 h^d Lz psi.
+angular_momentum(plan, psi) is <Lz> with the gradient 2 h^d Lz psi (fse_angular_momentum_grad).
 
 Gradients follow torch's convention for complex tensors,
 dL/dRe(psi) + i dL/dIm(psi), which is also the library's.
 """
 from __future__ import annotations
 
-import math
 
 import torch
 
@@ -66,10 +65,9 @@ class _Lz(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, g):
-        plan = ctx.plan
-        vol = math.prod(2.0 * Lj / Nj for Nj, Lj in zip(plan.N, plan.L))
-        lz = plan.apply_Lz(ctx.psi)
-        return (2.0 * vol * g).to(plan.rdtype) * lz, None
+        # 2 h^d g Lz psi, computed by the library with g read on the device
+        gd = g.detach().to(device=ctx.psi.device, dtype=torch.float64).reshape(1)
+        return ctx.plan.angular_momentum_grad(ctx.psi, gd), None
 
 
 def angular_momentum(plan, psi):

@@ -87,6 +87,10 @@ struct fse_plan_s {
     int prec = FSE_C128;
     bool nl = false;  // nonlocal term present
     double* tdev = nullptr;  // the time t of the state, in device memory (a batch points it into its own array)
+    // FP64 mass renormalisation of a step call (fse_set_mass_renorm; on by default for complex64):
+    // renorm = {mass at the call's start, factor, mass before the exit pass}, device memory
+    bool renorm_on = false;
+    double* renorm = nullptr;
     long n = 0;       // grid points
     int C0 = 0;       // columns of the axis-0 passes (n / N0)
     size_t csize = 16, rsize = 8;
@@ -593,6 +597,14 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
     const int nlines = (int)p->lines_last();
     const fse::LineIdx ki = kin_index(p);
     const int N1 = p->N[1], N2 = (p->d == 3) ? p->N[2] : 1;
+    const double vol = p->h[0] * p->h[1] * ((p->d == 3) ? p->h[2] : 1.0);
+    if (p->renorm_on) {  // the mass at the start of the call, FP64
+        PLAUNCH(p, FSE_PASS_EDGE, st,
+                L::red_local(psi, nullptr, nullptr, p->n, geom(p), 0, 0, 0, 0, nullptr, 0, 0, p->partials, 0,
+                             kRedBlocks, st));
+        PLAUNCH(p, FSE_PASS_EDGE, st,
+                fse::launch_red_final(p->partials, kRedBlocks, 1, 0, vol, (double)p->n, 0, 0, 0, p->renorm, st));
+    }
     // entry: half linear step, leaving the axis-0 inverse pending
     PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
     if (p->d == 3)
@@ -637,7 +649,17 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                 PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
         }
     }
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
+    const double* scale = nullptr;
+    if (p->renorm_on) {
+        // mass of the state before the exit pass (the pending axis-0 inverse scales it by N0), and the factor
+        // that restores the mass at the start of the call, applied by the exit pass
+        PLAUNCH(p, FSE_PASS_EDGE, st,
+                L::red_local(psi, nullptr, nullptr, p->n, geom(p), 0, 0, 0, 0, nullptr, 0, 0, p->partials, 0,
+                             kRedBlocks, st));
+        PLAUNCH(p, FSE_PASS_EDGE, st, fse::launch_renorm_factor(p->partials, kRedBlocks, vol, (double)N0, p->renorm, st));
+        scale = p->renorm + 1;
+    }
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st, scale));
     HIPCHK(fse::launch_time_add(p->tdev, nsteps * dt, st));
     return FSE_OK;
 }
@@ -786,8 +808,10 @@ fse_status adjoint_impl(fse_plan p, const void* psi0, int nsteps, double dt, voi
     return FSE_OK;
 }
 
-// out = Lz psi = -i (x D_y - y D_x) psi.
-template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void* out, hipStream_t st) {
+// out = c Lz psi = -i c (x D_y - y D_x) psi, c = scale (times *gdev when gdev is not null).
+template <typename R>
+fse_status apply_Lz_impl(fse_plan p, const void* psi, void* out, hipStream_t st, double scale = 1.0,
+                         const double* gdev = nullptr) {
     using L = fse::Launch<R>;
     fse_status s = ensure_diag(p);
     if (s != FSE_OK) return s;
@@ -795,9 +819,9 @@ template <typename R> fse_status apply_Lz_impl(fse_plan p, const void* psi, void
     const fse::GridGeom g = geom(p);
     HIPCHK(fse::launch_zero(out, (size_t)p->n * p->csize, st));
     HIPCHK(deriv_axis<R>(p, 1, psi, B, st));
-    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 0, -1.0, 0, 0, 0, 0, 0, st));
+    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 0, -scale, 0, 0, 0, 0, 0, st, gdev));
     HIPCHK(deriv_axis<R>(p, 0, psi, B, st));
-    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, -1.0, 0, 0, 0, 0, 0, st));
+    HIPCHK(L::H_accum(out, B, psi, nullptr, nullptr, nullptr, p->n, g, 1, -scale, 0, 0, 0, 0, 0, st, gdev));
     return FSE_OK;
 }
 
@@ -1446,6 +1470,8 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
     }
     if ((st = dev_alloc(p, (void**)&p->partials, sizeof(double) * kRedBlocks * kRedSlots)) != FSE_OK) return bail(st);
     if ((st = dev_alloc(p, (void**)&p->tdev, sizeof(double))) != FSE_OK) return bail(st);
+    if ((st = dev_alloc(p, (void**)&p->renorm, 4 * sizeof(double))) != FSE_OK) return bail(st);
+    p->renorm_on = (precision == FSE_C64);
     if (hipStreamSynchronize(hs) != hipSuccess) return bail(fail(FSE_ERR_HIP, "stream synchronisation failed"));
     const double t0 = 0.0;
     if (hipMemcpy(p->tdev, &t0, sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
@@ -1674,6 +1700,28 @@ fse_status fse_get_time(fse_plan plan, double* t) {
     g_err.clear();
     if (!plan || !t) return fail(FSE_ERR_ARG, "plan and t must not be NULL");
     return read_time(plan, t);
+}
+
+fse_status fse_set_mass_renorm(fse_plan plan, int enable) {
+    g_err.clear();
+    if (!plan) return fail(FSE_ERR_ARG, "plan must not be NULL");
+    plan->renorm_on = enable != 0;
+    return FSE_OK;
+}
+
+fse_status fse_get_mass_renorm(fse_plan plan, int* enabled, double* factor_mass) {
+    g_err.clear();
+    if (!plan || !enabled) return fail(FSE_ERR_ARG, "plan and enabled must not be NULL");
+    *enabled = plan->renorm_on ? 1 : 0;
+    if (factor_mass) {
+        double r[3];
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(r, plan->renorm, sizeof(r), hipMemcpyDeviceToHost));
+        factor_mass[0] = r[1];
+        factor_mass[1] = r[2];
+        factor_mass[2] = r[0];
+    }
+    return FSE_OK;
 }
 
 fse_status fse_set_guard(fse_plan plan, double tol) {
@@ -1942,6 +1990,16 @@ fse_status fse_apply_Lz(fse_plan plan, const void* psi, void* out, void* stream)
                                   : apply_Lz_impl<float>(plan, psi, out, st);
 }
 
+fse_status fse_angular_momentum_grad(fse_plan plan, const void* psi, const double* g_dev, void* out, void* stream) {
+    g_err.clear();
+    if (!plan || !psi || !out) return fail(FSE_ERR_ARG, "plan, psi and out must not be NULL");
+    if (psi == out) return fail(FSE_ERR_ARG, "psi and out must not alias");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const double vol = plan->h[0] * plan->h[1] * ((plan->d == 3) ? plan->h[2] : 1.0);
+    return plan->prec == FSE_C128 ? apply_Lz_impl<double>(plan, psi, out, st, 2.0 * vol, g_dev)
+                                  : apply_Lz_impl<float>(plan, psi, out, st, 2.0 * vol, g_dev);
+}
+
 fse_status fse_moments(fse_plan plan, const void* psi, double* out_dev, void* stream) {
     g_err.clear();
     if (!plan || !psi || !out_dev) return fail(FSE_ERR_ARG, "plan, psi and out_dev must not be NULL");
@@ -2178,6 +2236,16 @@ fse_status fse_device_copy(void* dst, const void* src, size_t bytes, void* strea
         return fail(FSE_ERR_ARG, "bytes and both pointers must be multiples of 16");
     if (bytes == 0) return FSE_OK;
     HIPCHK(fse::launch_copy16(dst, src, (long)(bytes / 16), static_cast<hipStream_t>(stream)));
+    return FSE_OK;
+}
+
+fse_status fse_device_copy_nt(void* dst, const void* src, size_t bytes, void* stream) {
+    g_err.clear();
+    if (!dst || !src) return fail(FSE_ERR_ARG, "dst and src must not be NULL");
+    if ((bytes % 16) != 0 || ((uintptr_t)dst % 16) != 0 || ((uintptr_t)src % 16) != 0)
+        return fail(FSE_ERR_ARG, "bytes and both pointers must be multiples of 16");
+    if (bytes == 0) return FSE_OK;
+    HIPCHK(fse::launch_copy16(dst, src, (long)(bytes / 16), static_cast<hipStream_t>(stream), true));
     return FSE_OK;
 }
 

@@ -47,7 +47,9 @@ __global__ void k_gs_frozen(const typename CT<R>::T* __restrict__ psi, const R* 
 // Column tiles as in the plain column pass; C columns, x from the row index,
 // y from the column (c / N2 in 3D, c in 2D).
 template <typename R, int N, int OP>
-__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_gs_cols(
+__global__ __launch_bounds__((ColCfg<R, N>::NTH))
+FSE_COL_OCC(R, N, ColCfg<R, N>::W * pitch_cols<N>(N) * csz<R>(), ColCfg<R, N>::NTH)
+void k_gs_cols(
     const typename CT<R>::T* __restrict__ v, const typename CT<R>::T* __restrict__ Dx,
     const typename CT<R>::T* __restrict__ Dy, const R* __restrict__ W, const typename CT<R>::T* A,
     typename CT<R>::T* out, int C, GridGeom g, double Omega, const typename CT<R>::T* __restrict__ twN) {
@@ -55,7 +57,7 @@ __global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_gs_cols(
     using Cf = ColCfg<R, N>;
     constexpr int Wt = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols<N>(N);
-    using F = Fft<T, N, OP == 2, TPL, FwdPlan<N>>;
+    using F = Fft<T, N, OP == 2, TPL, ColPlan<N>>;
     __shared__ T lds[Wt * P];
     const int l = threadIdx.x % Wt, jt = threadIdx.x / Wt;
     const int c = blockIdx.x * Wt + l;

@@ -36,8 +36,18 @@ namespace fse {
 //   Line tiles (contiguous axis): LPB whole lines, lanes ordered
 //   position-fastest.
 // ---------------------------------------------------------------------------
+// Radix plan of the column (strided-axis) transforms.
+template <int N> struct ColPlanOf { using L = FwdPlan<N>; };
+#ifdef FSE_COLPLAN256
+template <> struct ColPlanOf<256> { using L = RList<8, 8, 4>; };
+#endif
+#ifdef FSE_COLPLAN512
+template <> struct ColPlanOf<512> { using L = RList<16, 8, 4>; };
+#endif
+template <int N> using ColPlan = typename ColPlanOf<N>::L;
+
 template <int N, typename PL> struct PlanOf { using L = PL; };
-template <int N> struct PlanOf<N, void> { using L = FwdPlan<N>; };
+template <int N> struct PlanOf<N, void> { using L = ColPlan<N>; };
 
 // Column tile: W columns of 128 B, TPL threads per column (the plan's first
 // radix sets the points per thread); PL = void selects the plain plan.
@@ -52,9 +62,31 @@ template <typename R, int N, typename PL = void> struct ColCfg {
 // it keeps three arrays per thread live, so where the plain plan gives a
 // thread 16 points this one gives it 8 (one more LDS exchange per transform,
 // half the registers per array: occupancy 4 instead of 2).
-template <typename R, int N> struct FusedPlan { using L = void; };
+template <typename R, int N> struct FusedPlan { using L = FwdPlan<N>; };
 template <> struct FusedPlan<double, 256> { using L = RList<8, 8, 4>; };
 template <typename R, int N> using FusedCfg = ColCfg<R, N, typename FusedPlan<R, N>::L>;
+
+// Waves per SIMD that the LDS of one workgroup allows (160 KB per CU, four
+// SIMDs).  Column kernels hold 37-78 KB of LDS, so the LDS caps them at 2-4
+// waves per SIMD.  For FP64 up to length 256 their register budget is set to
+// that same occupancy (FSE_COL_OCC): left to itself the compiler spends spare
+// registers on scheduling and can end one wave below it (the FP64 phase
+// kernel: 130 VGPRs and 3 waves, where 128 give 4 with no spills).  The
+// complex64 phase kernel needs 161 and would spill at 128, and the 512-point
+// tiles spill too, so those keep the compiler's choice.
+constexpr int lds_waves(int lds_bytes, int nth) {
+    const int wg = (160 * 1024) / lds_bytes;
+    const int w = (wg < 1 ? 1 : wg) * (nth / 64) / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+template <typename R, int N> constexpr int col_occ(int lds_bytes, int nth) {
+#ifdef FSE_PHASE_OCC
+    if (sizeof(R) == 4 && N == 256 && nth == 256) return lds_waves(lds_bytes, nth);
+#endif
+    return (sizeof(R) == 8 && N <= 256) ? lds_waves(lds_bytes, nth) : 1;
+}
+#define FSE_COL_OCC(R, N, ...) __attribute__((amdgpu_waves_per_eu(col_occ<R, N>(__VA_ARGS__), 8)))
+template <typename R> constexpr int csz() { return (int)sizeof(typename CT<R>::T); }
 
 constexpr int floor_pow2(int x) {
     int p = 1;
@@ -93,7 +125,10 @@ template <typename R, int N, bool CONV, int V = 0> struct LineCfg {
     // strand less of the 160 KB per CU than a few large ones (FP64 256^3:
     // convolution 16 -> 17 lines per CU, kinetic pass 8 -> 9; both ~2.5 %
     // faster than with a 40 KB budget)
-    static constexpr int BUDGET = 10240 / (P * (int)sizeof(T) * SUB);
+#ifndef FSE_LINE_BUDGET
+#define FSE_LINE_BUDGET 10240
+#endif
+    static constexpr int BUDGET = FSE_LINE_BUDGET / (P * (int)sizeof(T) * SUB);
     static constexpr int LPB0 = floor_pow2(BUDGET < 1 ? 1 : BUDGET);
     static constexpr int LPB1 = (LPB0 * TPL * SUB > 256) ? 256 / (TPL * SUB) : LPB0;
     static constexpr int LPBW = (TPL * SUB >= 64) ? 1 : 64 / (TPL * SUB);  // at least one full wavefront
@@ -129,14 +164,26 @@ template <int N, int TPL, typename F> __device__ __forceinline__ void for_rows_i
 // columns of B2 at b0 = blockIdx.y, forward or inverse, in place allowed.
 // twN: exp(-2 pi i m/N), m < N.
 // ---------------------------------------------------------------------------
+// Multiply by f = 1 + d, d = *scale - 1 (a factor within rounding distance of 1): in FP32 as v + v d with the
+// product inside the FMA, so that the tiny d is not lost to the rounding of f itself.
+template <typename R> __device__ __forceinline__ typename CT<R>::T scale_near_one(typename CT<R>::T v, double f) {
+    if constexpr (sizeof(R) == 4) {
+        const float dd = float(f - 1.0);
+        return typename CT<R>::T{fmaf(v.x, dd, v.x), fmaf(v.y, dd, v.y)};
+    } else {
+        return typename CT<R>::T{v.x * f, v.y * f};
+    }
+}
+
 template <typename R, int N, bool INV>
 __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename CT<R>::T* out,
-                                                            int B2, const typename CT<R>::T* twN, int bx, int by, typename CT<R>::T* lds) {
+                                                            int B2, const typename CT<R>::T* twN, int bx, int by, typename CT<R>::T* lds,
+                                                            const double* scale = nullptr) {
     using T = typename CT<R>::T;
     using C = ColCfg<R, N>;
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols<N>(N);
-    using F = Fft<T, N, INV, TPL, FwdPlan<N>>;
+    using F = Fft<T, N, INV, TPL, ColPlan<N>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
@@ -148,17 +195,25 @@ __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename 
         typename F::Out u;
         for_pos<N, TPL, F::R0>(jt, [&](int b, int r, int e) { v[b][r] = lv ? g[(long)e * B2] : T{0, 0}; });
         F::run(v, u, line, jt, twN);
+        if (scale) {
+            const double f = *scale;
+            for_pos<N, TPL, F::RK>(jt, [&](int b, int r, int) { u[b][r] = scale_near_one<R>(u[b][r], f); });
+        }
         for_pos<N, TPL, F::RK>(jt, [&](int b, int r, int e) {
             if (lv) o[(long)e * B2] = u[b][r];
         });
     }
 }
 
+// scale: null, or a device factor applied to the output (the complex64 mass renormalisation).
 template <typename R, int N, bool INV>
-__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
-                                                            int B2, const typename CT<R>::T* twN) {
+__global__ __launch_bounds__((ColCfg<R, N>::NTH))
+FSE_COL_OCC(R, N, ColCfg<R, N>::W * pitch_cols<N>(N) * csz<R>(), ColCfg<R, N>::NTH)
+void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
+                                                            int B2, const typename CT<R>::T* twN,
+                                                            const double* scale) {
     __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols<N>(N)];
-    cols_body<R, N, INV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds);
+    cols_body<R, N, INV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -175,8 +230,8 @@ __device__ __forceinline__ void cols_deriv_body(const typename CT<R>::T* in, typ
     using C = ColCfg<R, N>;
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols<N>(N);
-    using FF = Fft<T, N, false, TPL, FwdPlan<N>>;
-    using FI = Fft<T, N, true, TPL, InvPlan<N>>;
+    using FF = Fft<T, N, false, TPL, ColPlan<N>>;
+    using FI = Fft<T, N, true, TPL, typename Rev<ColPlan<N>>::L>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
@@ -200,7 +255,9 @@ __device__ __forceinline__ void cols_deriv_body(const typename CT<R>::T* in, typ
 }
 
 template <typename R, int N>
-__global__ __launch_bounds__((ColCfg<R, N>::NTH)) void k_cols_deriv(const typename CT<R>::T* in,
+__global__ __launch_bounds__((ColCfg<R, N>::NTH))
+FSE_COL_OCC(R, N, ColCfg<R, N>::W * pitch_cols<N>(N) * csz<R>(), ColCfg<R, N>::NTH)
+void k_cols_deriv(const typename CT<R>::T* in,
                                                                      typename CT<R>::T* out, int B2,
                                                                      const typename CT<R>::T* twN, double dmu,
                                                                      double scale) {
@@ -223,7 +280,7 @@ __device__ __forceinline__ void cols_full_body(const typename CT<R>::T* in,
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols<M>(M);
     constexpr bool INV = (PAD == 2);
-    using F = Fft<T, M, INV, TPL, FwdPlan<M>>;
+    using F = Fft<T, M, INV, TPL, ColPlan<M>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
@@ -242,7 +299,9 @@ __device__ __forceinline__ void cols_full_body(const typename CT<R>::T* in,
 }
 
 template <typename R, int M, int PAD>
-__global__ __launch_bounds__((ColCfg<R, M>::NTH)) void k_cols_full(const typename CT<R>::T* in,
+__global__ __launch_bounds__((ColCfg<R, M>::NTH))
+FSE_COL_OCC(R, M, ColCfg<R, M>::W * pitch_cols<M>(M) * csz<R>(), ColCfg<R, M>::NTH)
+void k_cols_full(const typename CT<R>::T* in,
                                                                    typename CT<R>::T* out, int B2,
                                                                    const typename CT<R>::T* twM) {
     __shared__ typename CT<R>::T lds[ColCfg<R, M>::W * pitch_cols<M>(M)];
@@ -514,8 +573,8 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
     using Cf = ColCfg<R, N0>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols<N0>(N0 + 1);
-    using FI = Fft<T, N0, true, TPL, FwdPlan<N0>>;
-    using FF = Fft<T, N0, false, TPL, FwdPlan<N0>>;
+    using FI = Fft<T, N0, true, TPL, ColPlan<N0>>;
+    using FF = Fft<T, N0, false, TPL, ColPlan<N0>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
@@ -567,7 +626,9 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
 }
 
 template <typename R, int N0, int SRC>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_r2c(const void* src, typename CT<R>::T* X1,
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH))
+FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), ColCfg<R, N0>::NTH)
+void k_r2c(const void* src, typename CT<R>::T* X1,
                                                             int C, const typename CT<R>::T* __restrict__ twN,
                                                             const typename CT<R>::T* __restrict__ tw2N) {
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
@@ -698,7 +759,9 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
 }
 
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_c2r_phase(const typename CT<R>::T* X1,
+__global__ __launch_bounds__((FusedCfg<R, N0>::NTH))
+FSE_COL_OCC(R, N0, FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), FusedCfg<R, N0>::NTH)
+void k_c2r_phase(const typename CT<R>::T* X1,
                                                                   typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
                                                                   const typename CT<R>::T* __restrict__ twN,
@@ -738,12 +801,14 @@ __device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
 }
 
 template <typename R, int N0, bool INV>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_cols(void* psi, const BInst* bi, int N1,
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH))
+FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0) * csz<R>(), ColCfg<R, N0>::NTH)
+void k_b_cols(void* psi, const BInst* bi, int N1,
                                                                 const typename CT<R>::T* twN0) {
     using T = typename CT<R>::T;
     T* x = static_cast<T*>(psi) + bi[blockIdx.y].psi_off;
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0)];
-    cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds);
+    cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds, nullptr);
 }
 
 template <typename R, int N1>
@@ -758,7 +823,9 @@ __global__ __launch_bounds__((LineCfg<R, N1, false>::NTH)) void k_b_kin(void* ps
 }
 
 template <typename R, int N0>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH)) void k_b_r2c(void* psi, const BInst* bi, int N1,
+__global__ __launch_bounds__((ColCfg<R, N0>::NTH))
+FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), ColCfg<R, N0>::NTH)
+void k_b_r2c(void* psi, const BInst* bi, int N1,
                                                                const typename CT<R>::T* __restrict__ twN0,
                                                                const typename CT<R>::T* __restrict__ tw2N0) {
     using T = typename CT<R>::T;
@@ -788,7 +855,9 @@ __global__ __launch_bounds__((LineCfg<R, N1, true>::NTH)) void k_b_conv_halves(
 }
 
 template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((FusedCfg<R, N0>::NTH)) void k_b_c2r_phase(void* psi, const BInst* bi,
+__global__ __launch_bounds__((FusedCfg<R, N0>::NTH))
+FSE_COL_OCC(R, N0, FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), FusedCfg<R, N0>::NTH)
+void k_b_c2r_phase(void* psi, const BInst* bi,
                                                                      int N1, int kstep,
                                                                      const typename CT<R>::T* __restrict__ twN0,
                                                                      const typename CT<R>::T* __restrict__ tw2N0) {
@@ -1039,6 +1108,27 @@ static __global__ __launch_bounds__(RED_THREADS) void k_moments_final(const doub
     }
 }
 
+// Mass renormalisation factor: r = {M_ref, f, M}; f = sqrt(M_ref / (mscale * M)) with M the FP64 sum
+// of the nblk partials times vol, or 1 if that is zero or not finite (one block).
+static __global__ __launch_bounds__(RED_THREADS) void k_renorm_factor(const double* __restrict__ partials, int nblk,
+                                                                      double vol, double mscale, double* r) {
+    __shared__ double red[RED_THREADS / 64];
+    double x = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RED_THREADS) x += partials[b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+        const double M = mscale * vol * t;
+        const double f = sqrt(r[0] / M);
+        r[2] = M;
+        r[1] = (M > 0.0 && isfinite(f)) ? f : 1.0;
+    }
+}
+
 // Final combination (one block).  tot[s] = sum over blocks of slot s.
 //   KIND 0 (mass):   out[0] = vol * tot[0]
 //   KIND 1 (energy): out = {kin, pot, int, non, rot, total} from
@@ -1092,12 +1182,15 @@ static __global__ __launch_bounds__(RED_THREADS) void k_red_final(const double* 
 //   WHAT 0: H += i Omega x D  (D = D_y psi)
 //   WHAT 1: H += -i Omega y D (D = D_x psi)
 //   WHAT 2: H += (V + beta rho + lam Phi) psi, rho = |psi|^2 or rho_in.
+// For WHAT 0 and 1, Omega is multiplied by *wscale when wscale is not null.
 template <typename R>
 __global__ void k_H_accum(typename CT<R>::T* __restrict__ H, const typename CT<R>::T* __restrict__ D,
                           const typename CT<R>::T* __restrict__ psi, const R* __restrict__ rho_in,
                           const R* __restrict__ Phi, const R* __restrict__ U, long n, GridGeom g, int what,
-                          double Omega, double beta, double lam, double g0, double g1, double g2) {
+                          double Omega, double beta, double lam, double g0, double g1, double g2,
+                          const double* __restrict__ wscale) {
     using T = typename CT<R>::T;
+    if (wscale) Omega *= *wscale;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         int i0, i1, i2;
         decode(i, g, i0, i1, i2);
@@ -1140,18 +1233,34 @@ __global__ void k_lattice(R* __restrict__ out, const R* __restrict__ U, long n, 
 
 // Plain streaming copy (HBM bandwidth calibration): 16-byte vectors, each
 // thread loads four elements 256 apart, then stores them; one pass, no loop.
-static __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src, long n) {
+// NT: non-temporal loads and stores (the data is not kept in the caches).
+template <bool NT>
+__global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src, long n) {
     const long base = (long)blockIdx.x * 1024L + threadIdx.x;
     double2 v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const long i = base + 256L * u;
-        if (i < n) v[u] = src[i];
+        if (i < n) {
+            if constexpr (NT) {
+                v[u].x = __builtin_nontemporal_load(&src[i].x);
+                v[u].y = __builtin_nontemporal_load(&src[i].y);
+            } else {
+                v[u] = src[i];
+            }
+        }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const long i = base + 256L * u;
-        if (i < n) dst[i] = v[u];
+        if (i < n) {
+            if constexpr (NT) {
+                __builtin_nontemporal_store(v[u].x, &dst[i].x);
+                __builtin_nontemporal_store(v[u].y, &dst[i].y);
+            } else {
+                dst[i] = v[u];
+            }
+        }
     }
 }
 

@@ -17,8 +17,9 @@ bool line_size_ok(int M);
 template <typename R> struct Launch {
     // Strided length-N FFT over [B0][rows][B2]; mode 0 plain (N -> N rows), 1 zero-padded forward
     // (N -> 2N rows), 2 cropped inverse (2N -> N rows).  twN: length-N twiddles, tw2N: length 2N.
+    // scale (mode 0 only): null, or a device factor near 1 applied to the output.
     static hipError_t strided(int N, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* twN,
-                              const void* tw2N, hipStream_t st);
+                              const void* tw2N, hipStream_t st, const double* scale = nullptr);
     // Contiguous line pass on lines of N points; mode 0 padded conv (real multiplier over 2N frequencies),
     // 1 kinetic (complex table), 2 fwd, 3 inv.  var 1 selects the alternative radix schedule (AltRadix) of
     // the conv and kinetic transforms where the length has one, else the plain schedule is used.
@@ -52,9 +53,11 @@ template <typename R> struct Launch {
                              double* partials, int slot0, int nblk, hipStream_t st);
     static hipError_t red_moments(const void* psi, long n, const GridGeom& g, double* partials, int nblk,
                                   hipStream_t st);
+    // (what 0 and 1: Omega times *wscale when wscale is not null)
     static hipError_t H_accum(void* H, const void* D, const void* psi, const void* rho_in, const void* Phi,
                               const void* U, long n, const GridGeom& g, int what, double Omega, double beta,
-                              double lam, double g0, double g1, double g2, hipStream_t st);
+                              double lam, double g0, double g1, double g2, hipStream_t st,
+                              const double* wscale = nullptr);
     // Fourier derivative along one axis in one pass, out = D in (out of place allowed): strided axis of
     // [B0][N][B2] (line = false) or nlines = B0 contiguous lines of N points (line = true); the
     // multiplier is i p dmu scale for frequency index p (Nyquist kept as -N/2).
@@ -93,7 +96,7 @@ hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, 
 
 hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st);
 
-hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st);
+hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, bool nontemporal = false);
 
 // Whether the line transform of length n has an alternative radix schedule (AltRadix).
 bool line_has_alt(int n);
@@ -112,6 +115,9 @@ hipError_t launch_guard(double* g, double tol, hipStream_t st);
 // set those of Om * *tp.
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, const double* tp,
                                 double Om, double* out, hipStream_t st);
+// r[1] = sqrt(r[0] / (mscale * vol * sum of the nblk partials)) (1 if not finite), r[2] = that mass.
+hipError_t launch_renorm_factor(const double* partials, int nblk, double vol, double mscale, double* r,
+                                hipStream_t st);
 // *t += dtot on the stream (a plan's device time).
 hipError_t launch_time_add(double* t, double dtot, hipStream_t st);
 

@@ -39,10 +39,13 @@ bool line_has_alt(int n) {
     }
 }
 
-hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st) {
+hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, bool nontemporal) {
     const long g = (n16 + 1023) / 1024;  // 1024 elements per workgroup
     if (g > 0x7fffffffL) return hipErrorInvalidValue;
-    k_copy16<<<(unsigned)g, 256, 0, st>>>(static_cast<double2*>(dst), static_cast<const double2*>(src), n16);
+    if (nontemporal)
+        k_copy16<true><<<(unsigned)g, 256, 0, st>>>(static_cast<double2*>(dst), static_cast<const double2*>(src), n16);
+    else
+        k_copy16<false><<<(unsigned)g, 256, 0, st>>>(static_cast<double2*>(dst), static_cast<const double2*>(src), n16);
     return hipGetLastError();
 }
 
@@ -82,6 +85,12 @@ hipError_t launch_guard(double* g, double tol, hipStream_t st) {
 hipError_t launch_moments_final(const double* partials, int nblk, double vol, double c, double s, const double* tp,
                                 double Om, double* out, hipStream_t st) {
     k_moments_final<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, c, s, tp, Om, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_renorm_factor(const double* partials, int nblk, double vol, double mscale, double* r,
+                                hipStream_t st) {
+    k_renorm_factor<<<1, RED_THREADS, 0, st>>>(partials, nblk, vol, mscale, r);
     return hipGetLastError();
 }
 

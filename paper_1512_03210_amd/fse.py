@@ -34,7 +34,8 @@ EXPORTS = [
     "fse_get_symbol", "fse_last_error", "fse_version", "fse_set_profiling", "fse_get_profile",
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
     "fse_batch_reduce", "fse_batch_times", "fse_gs_step", "fse_set_guard", "fse_guard_status",
-    "fse_mass_noalloc", "fse_gs_run",
+    "fse_mass_noalloc", "fse_gs_run", "fse_angular_momentum_grad", "fse_set_mass_renorm", "fse_get_mass_renorm",
+    "fse_device_copy_nt",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -93,6 +94,8 @@ def lib():
         "fse_step": (st, [vp, vp, i, d, vp]),
         "fse_step4": (st, [vp, vp, i, d, vp]),
         "fse_set_guard": (st, [vp, d]),
+        "fse_set_mass_renorm": (st, [vp, i]),
+        "fse_get_mass_renorm": (st, [vp, ip, dp]),
         "fse_guard_status": (st, [vp, ip, dp]),
         "fse_set_potential": (st, [vp, vp]),
         "fse_set_lattice": (st, [vp, dp, dp]),
@@ -101,6 +104,7 @@ def lib():
         "fse_plan_set_schedule": (st, [vp, ip]),
         "fse_step_adjoint": (st, [vp, vp, i, d, vp, vp, vp]),
         "fse_apply_Lz": (st, [vp, vp, vp, vp]),
+        "fse_angular_momentum_grad": (st, [vp, vp, vp, vp, vp]),
         "fse_apply_H": (st, [vp, vp, vp, vp, vp]),
         "fse_nonlocal_potential": (st, [vp, vp, vp, vp]),
         "fse_mass": (st, [vp, vp, vp, vp]),
@@ -115,6 +119,7 @@ def lib():
         "fse_set_profiling": (st, [vp, i]),
         "fse_get_profile": (st, [vp, dp, ip, i]),
         "fse_device_copy": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "fse_device_copy_nt": (st, [vp, vp, ctypes.c_size_t, vp]),
         "fse_batch_create": (st, [ctypes.POINTER(vp), i, ctypes.POINTER(Instance), i, vp]),
         "fse_batch_destroy": (st, [vp]),
         "fse_batch_offsets": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
@@ -172,9 +177,11 @@ def gausum_symbol_host(d, N, L, kernel: Kernel) -> np.ndarray:
     return out.reshape(shape)
 
 
-def device_copy(dst, src, nbytes: int, stream=None):
-    """Streaming copy kernel (HBM calibration); dst/src are device tensors."""
-    _check(lib().fse_device_copy(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
+def device_copy(dst, src, nbytes: int, stream=None, nontemporal: bool = False):
+    """Streaming copy kernel (HBM calibration); dst/src are device tensors; nontemporal: loads and stores that
+    bypass the caches (fse_device_copy_nt)."""
+    fn = lib().fse_device_copy_nt if nontemporal else lib().fse_device_copy
+    _check(fn(_ptr(dst), _ptr(src), int(nbytes), _stream(stream)))
 
 
 def version() -> str:
@@ -209,6 +216,8 @@ class Plan:
         self._h = ctypes.c_void_p()
         self._U = None
         self._ws = None
+        self._lattice = None  # (v, k) as set by set_lattice, for checkpoints
+        self._kernel_kw = {}  # kernel options beyond the parameter set (delta, ht), for checkpoints
         _check(lib().fse_plan_create(ctypes.byref(self._h), self.d, _iarr(self.N), _darr(self.L), s, Omega,
                                      _darr(gamma), beta, lam,
                                      ctypes.byref(kernel) if kernel is not None else None,
@@ -216,8 +225,11 @@ class Plan:
 
     @classmethod
     def from_params(cls, p, precision=C128, stream=None, **kw):
+        """Plan of a parameter set; kw: further kernel options (delta, ht of make_kernel)."""
         kern = None if p.kernel == "none" else make_kernel(p.kernel, mu=p.mu, prefactor=p.c, axis=p.axis, **kw)
-        return cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kern, precision, p.m, stream)
+        plan = cls(p.d, p.N, p.L, p.s, p.Omega, p.gamma, p.beta, p.lam, kern, precision, p.m, stream)
+        plan._kernel_kw = {k: float(v) for k, v in kw.items()}
+        return plan
 
     def close(self):
         if self._h:
@@ -258,8 +270,10 @@ class Plan:
         """Optical lattice sum_j v[j] sin^2(k[j] x_j) added to the trap (fse_set_lattice); None removes it."""
         if v is None:
             _check(lib().fse_set_lattice(self._h, None, None))
+            self._lattice = None
         else:
             _check(lib().fse_set_lattice(self._h, _darr(v), _darr(k)))
+            self._lattice = ([float(a) for a in v], [float(a) for a in k])
 
     def set_potential(self, U=None):
         """Grid potential U(x~) added to the step's phase and the energy (fse_set_potential);
@@ -289,6 +303,22 @@ class Plan:
         _check(lib().fse_apply_Lz(self._h, _ptr(psi), _ptr(out), _stream(stream)))
         return out
 
+    def angular_momentum_grad(self, psi, g=None, out=None, stream=None):
+        """2 h^d g Lz psi, the gradient of g <Lz> (fse_angular_momentum_grad); g: a float64 device scalar
+        tensor (None: 1)."""
+        import torch
+        self._check_psi(psi)
+        out = torch.empty_like(psi) if out is None else out
+        self._check_psi(out)
+        gp = None
+        if g is not None:
+            if g.dtype != torch.float64 or not g.is_cuda or g.numel() != 1:
+                raise ValueError("g must be a float64 device tensor with one element")
+            g = g.contiguous()
+            gp = _ptr(g)
+        _check(lib().fse_angular_momentum_grad(self._h, _ptr(psi), gp, _ptr(out), _stream(stream)))
+        return out
+
     @property
     def time(self) -> float:
         t = ctypes.c_double()
@@ -298,6 +328,17 @@ class Plan:
     @time.setter
     def time(self, t: float):
         _check(lib().fse_set_time(self._h, float(t)))
+
+    def set_mass_renorm(self, enable: bool):
+        """FP64 mass renormalisation of each step call (fse_set_mass_renorm; default on for complex64)."""
+        _check(lib().fse_set_mass_renorm(self._h, 1 if enable else 0))
+
+    def mass_renorm(self):
+        """(enabled, last factor, mass before the exit pass, mass at the call's start) (fse_get_mass_renorm)."""
+        e = ctypes.c_int()
+        r = (ctypes.c_double * 3)()
+        _check(lib().fse_get_mass_renorm(self._h, ctypes.byref(e), r))
+        return bool(e.value), float(r[0]), float(r[1]), float(r[2])
 
     def set_guard(self, tol: float = 0.0):
         """Numeric guard (fse_set_guard): with tol > 0 every step call ends with a device-side mass check
@@ -350,8 +391,7 @@ class Plan:
         self._check_psi(out)
         rp = None
         if rho_frozen is not None:
-            if rho_frozen.dtype != self.rdtype or tuple(rho_frozen.shape) != self.N or not rho_frozen.is_contiguous():
-                raise ValueError("rho_frozen must be a contiguous real tensor of the plan's precision and shape")
+            self._check_real(rho_frozen, "rho_frozen")
             rp = _ptr(rho_frozen)
         _check(lib().fse_apply_H(self._h, _ptr(psi), _ptr(out), rp, _stream(stream)))
         return out
@@ -360,6 +400,7 @@ class Plan:
         import torch
         self._check_psi(psi)
         out = torch.empty(self.N, dtype=self.rdtype, device=psi.device) if out is None else out
+        self._check_real(out, "out")
         _check(lib().fse_nonlocal_potential(self._h, _ptr(psi), _ptr(out), _stream(stream)))
         return out
 

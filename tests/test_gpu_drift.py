@@ -62,3 +62,33 @@ def test_drift_1000_steps(oracle_run, prec, tol_state, tol_scalar):
     assert abs(m - mo) < tol_scalar
     assert abs(e[5] - eo[5]) < tol_scalar * max(1.0, abs(eo[5]))
     assert abs(lz - lzo) < tol_scalar * max(1.0, abs(lzo))
+
+
+@pytest.mark.parametrize("name", ["plain2d", "dipole3d_128"])
+def test_complex64_mass_renormalisation(name):
+    # complex64, 1000 steps in one call: with the FP64 renormalisation (the default) the call returns the mass it
+    # was given; without it the FP32 twiddle residuals bias the mass by a few 1e-8 per step
+    p = W.preset(name)
+    psi0 = W.initial_state(p, seed=0).astype(np.complex64)
+    out = {}
+    for on in (True, False):
+        plan = fse.Plan.from_params(p, fse.C64)
+        assert plan.mass_renorm()[0]  # on by default for complex64
+        plan.set_mass_renorm(on)
+        x = torch.from_numpy(psi0).cuda()
+        m0 = plan.mass(x).item()
+        plan.step(x, STEPS, p.dt)
+        m1 = plan.mass(x).item()
+        out[on] = (m1 - m0, plan.mass_renorm(), x.to(torch.complex128))
+    ref = fse.Plan.from_params(p, fse.C128)
+    assert not ref.mass_renorm()[0]  # off for complex128
+    y = torch.from_numpy(W.initial_state(p, seed=0)).cuda()
+    ref.step(y, STEPS, p.dt)
+    e_on = float(torch.linalg.vector_norm(out[True][2] - y) / torch.linalg.vector_norm(y))
+    e_off = float(torch.linalg.vector_norm(out[False][2] - y) / torch.linalg.vector_norm(y))
+    _note(f"[renorm] {name}: dmass on {out[True][0]:.2e}, off {out[False][0]:.2e}; factor {out[True][1][1]!r}; "
+          f"state vs FP64 on {e_on:.3e}, off {e_off:.3e}")
+    # the exit transform, after the mass is measured, adds its own FP32 rounding (~1e-8)
+    assert abs(out[True][0]) < 1e-7
+    assert abs(out[True][1][1] - 1.0) < 1e-3 and out[True][1][1] != 1.0
+    assert e_on <= e_off * 1.05
