@@ -6,7 +6,11 @@
   tssp1-tssp3) from workloads.initial_state(seed=0);
 * batch_sweep_long.txt -- one instance of each grid size of the 64-instance
   2D sweep (instances 0, 17, 38, 63: 128^2, 256^2, 384^2, 512^2) after 500
-  steps from workloads.vortex_lattice_2d(N, L, seed=k).
+  steps from workloads.vortex_lattice_2d(N, L, seed=k);
+* plain2d_long.txt -- the 2D plain case (64^2 on [-8,8]^2, s = 0.75,
+  Omega = 0.5, beta = 100, lam = 1 Coulomb GauSum on 128^2 padding,
+  dt = 1e-3) after 100 and 1000 steps from workloads.initial_state(seed=0),
+  at every grid point.
 
 Each run records, per stored step, the FP64 oracle's mass, total energy and
 <Lz> (eqs. mass, energy, AME; the energy in rotating coordinates at that
@@ -18,7 +22,7 @@ samples.  This script calls only oracle/ and the seeded input generators of
 workloads/ (no library code).
 
 Usage (about 15 minutes on 8 cores):
-    python tests/golden/make_long_runs.py [case3d|batch]   (default: both)
+    python tests/golden/make_long_runs.py [case3d|batch|plain2d]   (default: all)
 """
 from __future__ import annotations
 
@@ -35,6 +39,7 @@ from oracle import diagnostics, scheme  # noqa: E402
 
 SAMPLE_SEED = 20261203
 CASE3D = ("dipole3d_128", (100, 1000), 2048)     # preset, stored steps, samples per half
+PLAIN2D = ("plain2d", (100, 1000))              # preset, stored steps (every grid point)
 BATCH = ((0, 17, 38, 63), 500, 512)              # instances, steps, samples per half
 
 
@@ -58,20 +63,20 @@ def write_samples(f, key, idx, shape, psi):
         f.write(f"{key} " + " ".join(str(int(q)) for q in pos) + f" {float(v.real)!r} {float(v.imag)!r}\n")
 
 
-def case3d():
-    name, steps, ns = CASE3D
+def case3d(full=False):
+    name, steps, ns = PLAIN2D + (None,) if full else CASE3D
     p = W.preset(name)
     out = os.path.join(HERE, f"{name}_long.txt")
     psi = W.initial_state(p, seed=0)
     prob = scheme.Problem.from_params(p)
-    idx = sample_indices(psi, ns, np.random.default_rng(SAMPLE_SEED))
+    idx = np.arange(psi.size) if full else sample_indices(psi, ns, np.random.default_rng(SAMPLE_SEED))
     with open(out, "w") as f:
         f.write(f"# oracle TS2-GauSum (eqs. tssp1-tssp3), workload {name}, N={p.N}, L={p.L}, s={p.s}, "
                 f"Omega={p.Omega}, beta={p.beta}, lam={p.lam}, kernel={p.kernel}, dt={p.dt}\n")
         f.write("# psi0 = workloads.initial_state(seed=0); t0=0; written by make_long_runs.py\n")
         m, e, lz = scalars(prob, p, psi, 0.0)
         f.write(f"# scalars step=0 mass={m!r} energy={e!r} lz={lz!r}\n")
-        f.write("# step i0 i1 i2 re im\n")
+        f.write("# step " + " ".join(f"i{j}" for j in range(p.d)) + " re im\n")
         t, done = 0.0, 0
         for target in steps:
             psi, t = prob.run(psi, target - done, p.dt, t)
@@ -110,8 +115,10 @@ def batch():
 
 
 if __name__ == "__main__":
-    what = sys.argv[1] if len(sys.argv) > 1 else "both"
-    if what in ("batch", "both"):
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if what in ("batch", "all"):
         batch()
-    if what in ("case3d", "both"):
+    if what in ("case3d", "all"):
         case3d()
+    if what in ("plain2d", "all"):
+        case3d(full=True)

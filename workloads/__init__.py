@@ -15,6 +15,8 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
+import re
 from typing import Sequence
 
 import numpy as np
@@ -31,6 +33,7 @@ __all__ = [
     "PRESETS",
     "preset",
     "batch_sweep",
+    "stored_long_run",
 ]
 
 
@@ -228,6 +231,14 @@ def harmonic_potential(N, L, gamma) -> np.ndarray:
     return V
 
 
+def adjoint_case_inputs(p: Params):
+    """psi0, V(x) = |x|^2/2 and the target state of the differentiation case (complex128 / float64):
+    the Gaussian initial state of the 96^3 cases (seed 0), the isotropic harmonic trap as a grid array, and
+    the displaced target (seed 1)."""
+    return (anisotropic_gaussian(p.N, p.L, (1.0,) * p.d, seed=0), harmonic_potential(p.N, p.L, (1.0,) * p.d),
+            adjoint_target(p.N, p.L, seed=1))
+
+
 def adjoint_target(N, L, seed=1):
     """Target state of the differentiation case: a Gaussian displaced by half a
     unit along x with a phase ramp along y, plus seeded noise, normalised."""
@@ -256,3 +267,37 @@ def batch_sweep(count=64, sizes=(128, 256, 384, 512), seed=0, beta=500.0, lam=1.
                           gamma=(1.0, 1.0), beta=beta, lam=lam, kernel="coulomb", mu=1.0,
                           dt=dt, steps=steps, name=f"batch-{i}-{n}"))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Stored oracle values of the full-length runs (tests/golden/*_long.txt,
+# written by tests/golden/make_long_runs.py, which calls only the oracle).
+# ---------------------------------------------------------------------------
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden")
+
+
+def stored_long_run(name: str):
+    """Parse tests/golden/<name>_long.txt.
+
+    Returns (scalars, samples): scalars[key] = (mass, energy, lz) and
+    samples[key] = (index tuple of arrays, complex128 values), where key is the
+    step (single runs) or the instance number (the batched sweep, whose scalars
+    are keyed (k, step)).
+    """
+    path = os.path.join(GOLDEN_DIR, f"{name}_long.txt")
+    scalars, rows = {}, []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# scalars"):
+                kv = dict(re.findall(r"(\w+)=(\S+)", line))
+                key = (int(kv["k"]), int(kv["step"])) if "k" in kv else int(kv["step"])
+                scalars[key] = (float(kv["mass"]), float(kv["energy"]), float(kv["lz"]))
+            elif line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    data = np.array(rows, dtype=float)
+    samples = {}
+    for key in np.unique(data[:, 0]).astype(int):
+        r = data[data[:, 0] == key]
+        idx = tuple(r[:, j].astype(int) for j in range(1, r.shape[1] - 2))
+        samples[int(key)] = (idx, r[:, -2] + 1j * r[:, -1])
+    return scalars, samples
