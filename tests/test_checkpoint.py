@@ -41,3 +41,25 @@ def test_load_checks_the_stored_shape(tmp_path):
     json.dump(meta, open(prefix + ".json", "w"))
     with pytest.raises(ValueError):
         checkpoint.load(prefix, device="cpu")
+
+
+def test_plan_state_is_stored_and_read_back(tmp_path):
+    # the plan's grid potential, lattice, schedule and kernel options go into the files (a bare binding object
+    # stands in for the plan: no GPU here)
+    p = W.preset("plain2d")
+    plan = fse.Plan.__new__(fse.Plan)
+    plan.precision = fse.C128
+    plan._U = torch.arange(p.npts, dtype=torch.float64).reshape(p.N)
+    plan._lattice = ([10.0, 10.0], [3.14, 3.14])
+    plan._kernel_kw = {"delta": 1e-3, "ht": 0.12}
+    plan.schedule = lambda: {"schedule": [1, 0, 0], "tuned_ms": [-1] * 8}
+    prefix = os.path.join(tmp_path, "ck")
+    psi = torch.zeros(p.N, dtype=torch.complex128)
+    checkpoint.save(prefix, p, psi, 0.5, fse.C128, plan=plan)
+    _, _, t, pr, st = checkpoint.load_full(prefix, device="cpu")
+    assert (t, pr) == (0.5, fse.C128)
+    assert torch.equal(st["U"], plan._U)
+    assert st["lattice"] == [[10.0, 10.0], [3.14, 3.14]] and st["schedule"] == [1, 0, 0]
+    assert st["kernel_options"] == {"delta": 1e-3, "ht": 0.12}
+    checkpoint.save(prefix, p, psi, 0.5, fse.C128)  # without the plan: no plan state
+    assert checkpoint.load_full(prefix, device="cpu")[4] is None
