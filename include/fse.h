@@ -191,34 +191,41 @@ fse_status fse_guard_status(fse_plan plan, int* tripped, double* masses);
  * three kinetic sub-steps (half linear steps that meet are merged). */
 fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
+/* Entries of a pass schedule (fse_plan_tune, fse_plan_get_schedule, fse_plan_set_schedule). */
+#define FSE_NSCHED 4
+
 /* Autotuner of the plan's pass schedule.  Times, on the plan's own workspace,
  * the compiled alternatives of its tunable passes and keeps the fastest:
  *   sched[0]  radix schedule of the kinetic line transform (0 plain, 1 the
  *             alternative, where the line length has one: 256, 512);
  *   sched[1]  radix schedule of the convolution line transform (same values);
  *   sched[2]  visit order of the kinetic line pass (1: the four lines that
- *             share a table row together; 3D only).
- * Another schedule replaces the current one only when it is at least 2 %
+ *             share a table row together; 3D only);
+ *   sched[3]  radix plan of the step's column transforms along axis 0 (and
+ *             axis 1 in 3D): 0 plain, 1 the alternative where the length has
+ *             one (256 as 8.8.4 beside 16.16).
+ * Another schedule replaces the current one only when it is at least 1 %
  * faster, so repeated tuning is stable.  Results are cached for the process
  * per device name and architecture, grid, precision and presence of the
  * nonlocal term; with cache_path non-NULL they are also looked up in, and
- * appended to, that text file ("key<TAB>s0 s1 s2" lines), so a cached shape is
- * not timed again.  Candidates are timed on whole steps (two TS2 steps on the
- * plan's scratch state, every allowed schedule, interleaved over five
- * rounds), since a pass timed alone can stay in the last-level cache.
+ * appended to, that text file ("key<TAB>s0 s1 s2 s3" lines), so a cached
+ * shape is not timed again.  Candidates are timed on whole steps (two TS2
+ * steps on the plan's scratch state, every allowed schedule, interleaved over
+ * five rounds), since a pass timed alone can stay in the last-level cache.
  * Synchronous on `stream`; allocates the diagnostics buffer and the step's
  * kinetic tables if absent; overwrites the plan's workspace, not the caller's
  * state; the plan's time is unchanged.
- * Without tuning a plan uses the default schedule {0, 0, 1 in 3D FP64 else 0}. */
+ * Without tuning a plan uses the default schedule {0, 0, 1 in 3D FP64 else 0, 0}. */
 fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream);
 
-/* The plan's schedule (sched[3], as above) and, if tuned_ms is not NULL, the
- * last measurement: 8 values, the time in ms of one step with schedule
- * {k, c, o} at index k + 2c + 4o (-1 where not measured). */
+/* The plan's schedule (sched[FSE_NSCHED], as above) and, if tuned_ms is not
+ * NULL, the last measurement: 2^FSE_NSCHED values, the time in ms of one step
+ * with schedule {k, c, o, v} at index k + 2c + 4o + 8v (-1 where not
+ * measured). */
 fse_status fse_plan_get_schedule(fse_plan plan, int* sched, double* tuned_ms);
 
-/* Force a schedule (entries 0 or 1).  FSE_ERR_UNSUPPORTED for an alternative
- * the plan's lengths do not have, or a mirrored order in 2D. */
+/* Force a schedule (sched[FSE_NSCHED], entries 0 or 1).  FSE_ERR_UNSUPPORTED
+ * for an alternative the plan's lengths do not have, or a mirrored order in 2D. */
 fse_status fse_plan_set_schedule(fse_plan plan, const int* sched);
 
 /* Optical lattice added to the harmonic trap: V_L = sum_j v[j] sin^2(k[j] x_j)

@@ -63,6 +63,8 @@ fse_status fail(fse_status st, const char* fmt, ...) {
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kRedBlocks = 1024;
 constexpr int kRedSlots = 8;
+constexpr int kNSched = FSE_NSCHED;  // entries of a pass schedule (fse.h)
+constexpr double kTuneMargin = 0.01;  // another schedule must be 1 % faster to replace the current one
 
 #define HIPCHK(expr)                                                                              \
     do {                                                                                          \
@@ -111,13 +113,15 @@ struct fse_plan_s {
     void* adj = nullptr;      // adjoint workspace (fse_step_adjoint), grown on demand
     // pass schedule: [0] radix variant of the kinetic line transforms, [1] of
     // the convolution line transforms, [2] kinetic visit order (1 mirrored,
-    // 3D only); defaults set at creation, changed by fse_plan_tune/set_schedule
-    int sched[3] = {0, 0, 0};
+    // 3D only), [3] radix plan of the step's column transforms (1: the
+    // alternative where the length has one); defaults set at creation,
+    // changed by fse_plan_tune/set_schedule
+    int sched[kNSched] = {0, 0, 0, 0};
     // dipole with products n_i n_j or an axis that turns in the rotating frame:
     // khat holds the Coulomb-part symbol and each convolution gets a QForm
     bool qf = false;
     double khat_scale = 1.0;  // 1 / prod(2 N_j), carried by khat
-    double tune_ms[8] = {-1, -1, -1, -1, -1, -1, -1, -1};  // ms per step of each schedule, last fse_plan_tune
+    double tune_ms[1 << kNSched] = {};  // ms per step of each schedule, last fse_plan_tune (-1: not timed)
     size_t adj_bytes = 0;
     void* gs = nullptr;    // ground-state solver: 10 n complex + 2 n real, allocated on first use
     double* gs_out = nullptr;
@@ -606,12 +610,14 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                 fse::launch_red_final(p->partials, kRedBlocks, 1, 0, vol, (double)p->n, 0, 0, 0, p->renorm, st));
     }
     // entry: half linear step, leaving the axis-0 inverse pending
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st));
+    const int cv = p->sched[3];
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, false, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st, nullptr, cv));
     if (p->d == 3)
-        PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+        PLAUNCH(p, FSE_PASS_EDGE, st,
+                L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st, nullptr, cv));
     PLAUNCH(p, FSE_PASS_EDGE, st, L::line(NL, 1, psi, nlines, kh, ki, p->tw[NL], nullptr, st, p->sched[0]));
     if (p->d == 3)
-        PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+        PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st, nullptr, cv));
     for (int k = 0; k < nsteps; ++k) {
         double tj = k * dt;  // offset of the sub-step from the plan's time at the call
         for (int j = 0; j < nw; ++j) {
@@ -625,7 +631,7 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
             }
             tj += tau;
             if (p->nl) {
-                PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st));
+                PLAUNCH(p, FSE_PASS_R2C, st, L::r2c(N0, 0, psi, p->X1, p->C0, p->tw[N0], p->tw[2 * N0], st, cv));
                 if (p->d == 3) {
                     PLAUNCH(p, FSE_PASS_PAD_FWD, st,
                             L::strided(N1, false, 1, p->X1, p->X2, N0 + 1, N2, p->tw[N1], p->tw[2 * N1], st));
@@ -643,10 +649,12 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
             }
             void* tab = (j < nw - 1) ? ki_tab : (k == nsteps - 1) ? kh : kf;
             if (p->d == 3)
-                PLAUNCH(p, FSE_PASS_F1, st, L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+                PLAUNCH(p, FSE_PASS_F1, st,
+                        L::strided(N1, false, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st, nullptr, cv));
             PLAUNCH(p, FSE_PASS_KIN, st, L::line(NL, 1, psi, nlines, tab, ki, p->tw[NL], nullptr, st, p->sched[0]));
             if (p->d == 3)
-                PLAUNCH(p, FSE_PASS_I1, st, L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st));
+                PLAUNCH(p, FSE_PASS_I1, st,
+                        L::strided(N1, true, 0, psi, psi, N0, N2, p->tw[N1], nullptr, st, nullptr, cv));
         }
     }
     const double* scale = nullptr;
@@ -659,7 +667,7 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
         PLAUNCH(p, FSE_PASS_EDGE, st, fse::launch_renorm_factor(p->partials, kRedBlocks, vol, (double)N0, p->renorm, st));
         scale = p->renorm + 1;
     }
-    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st, scale));
+    PLAUNCH(p, FSE_PASS_EDGE, st, L::strided(N0, true, 0, psi, psi, 1, p->C0, p->tw[N0], nullptr, st, scale, cv));
     HIPCHK(fse::launch_time_add(p->tdev, nsteps * dt, st));
     return FSE_OK;
 }
@@ -838,7 +846,7 @@ fse_status apply_Lz_impl(fse_plan p, const void* psi, void* out, hipStream_t st,
 // optionally in a text file of "key<TAB>k c o" lines.
 // ---------------------------------------------------------------------------
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 3>> g_tune_cache;
+std::map<std::string, std::array<int, kNSched>> g_tune_cache;
 
 // Numeric guard.  guard_poll: the outcome of the last completed check, without
 // waiting (a check still running is looked at by a later call).  guard_check:
@@ -928,6 +936,10 @@ fse_status write_time(fse_plan p, double t) {
 }
 
 bool kin_has_alt(const fse_plan p) { return fse::line_has_alt(p->last()); }
+// The step's column transforms run along axis 0 (and axis 1 in 3D).
+bool cols_have_alt(const fse_plan p) {
+    return fse::col_has_alt(p->N[0]) || (p->d == 3 && fse::col_has_alt(p->N[1]));
+}
 bool conv_has_alt(const fse_plan p) {
     const int n = p->last();
     return p->nl && ((2 * n <= 512) ? fse::line_has_alt(2 * n) : fse::line_has_alt(n));
@@ -935,8 +947,8 @@ bool conv_has_alt(const fse_plan p) {
 
 // Times every schedule the plan allows on whole steps (two TS2 steps on the
 // plan's scratch state, so that each pass meets the caches as in a run) and
-// keeps the fastest; tune_ms[k + 2c + 4o] is the time per step of schedule
-// {k, c, o}.  The plan's time is restored.
+// keeps the fastest; tune_ms[k + 2c + 4o + 8v] is the time per step of
+// schedule {k, c, o, v}.  The plan's time is restored.
 template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     fse_status s = ensure_diag(p);
     if (s != FSE_OK) return s;
@@ -947,41 +959,44 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     if ((s = read_time(p, &t_keep)) != FSE_OK) return s;
     const bool prof_keep = p->prof;
     p->prof = false;
-    const int keep[3] = {p->sched[0], p->sched[1], p->sched[2]};
+    int keep[kNSched];
+    for (int q = 0; q < kNSched; ++q) keep[q] = p->sched[q];
     for (double& t : p->tune_ms) t = -1.0;
-    std::vector<std::array<int, 3>> cands;
-    for (int o = 0; o < ((p->d == 3) ? 2 : 1); ++o)
-        for (int c = 0; c < (conv_has_alt(p) ? 2 : 1); ++c)
-            for (int k = 0; k < (kin_has_alt(p) ? 2 : 1); ++k) cands.push_back({k, c, o});
+    std::vector<std::array<int, kNSched>> cands;
+    for (int v = 0; v < (cols_have_alt(p) ? 2 : 1); ++v)
+        for (int o = 0; o < ((p->d == 3) ? 2 : 1); ++o)
+            for (int c = 0; c < (conv_has_alt(p) ? 2 : 1); ++c)
+                for (int k = 0; k < (kin_has_alt(p) ? 2 : 1); ++k) cands.push_back({k, c, o, v});
     std::vector<std::function<hipError_t()>> fs;
     for (const auto& cd : cands)
         fs.push_back([=]() {
-            for (int q = 0; q < 3; ++q) p->sched[q] = cd[q];
+            for (int q = 0; q < kNSched; ++q) p->sched[q] = cd[q];
             return step_impl<R>(p, A, 2, dt, 2, st) == FSE_OK ? hipSuccess : hipErrorLaunchFailure;
         });
     std::vector<double> ms(fs.size());
     s = time_candidates(fs, st, ms.data());
     p->prof = prof_keep;
-    for (int q = 0; q < 3; ++q) p->sched[q] = keep[q];
+    for (int q = 0; q < kNSched; ++q) p->sched[q] = keep[q];
     if (s != FSE_OK) return s;
     if ((s = write_time(p, t_keep)) != FSE_OK) return s;
     int best = -1;
     double tbest = 0.0;
     for (size_t c = 0; c < cands.size(); ++c) {
         const auto& cd = cands[c];
-        p->tune_ms[cd[0] + 2 * cd[1] + 4 * cd[2]] = 0.5 * ms[c];
-        if (cd[0] == keep[0] && cd[1] == keep[1] && cd[2] == keep[2]) {
+        p->tune_ms[cd[0] + 2 * cd[1] + 4 * cd[2] + 8 * cd[3]] = 0.5 * ms[c];
+        if (std::equal(cd.begin(), cd.end(), keep)) {
             best = (int)c;
             tbest = ms[c];
         }
     }
-    // keep the current schedule unless another one is 2 % faster
+    // keep the current schedule unless another one is faster by more than the
+    // threshold (repeated tuning then returns the same schedule)
     for (size_t c = 0; c < cands.size(); ++c)
-        if (ms[c] < 0.98 * tbest) {
+        if (ms[c] < (1.0 - kTuneMargin) * tbest) {
             tbest = ms[c];
             best = (int)c;
         }
-    for (int q = 0; q < 3; ++q) p->sched[q] = cands[best][q];
+    for (int q = 0; q < kNSched; ++q) p->sched[q] = cands[best][q];
     return FSE_OK;
 }
 
@@ -1414,6 +1429,7 @@ static fse_status create_plan(fse_plan* out, int d, const int* N, const double* 
     // default schedule: plain radix schedules; the mirrored kinetic visit
     // order in 3D FP64 (measured faster there, slower for the complex64 table)
     p->sched[2] = (d == 3 && precision == FSE_C128) ? 1 : 0;
+    for (double& t : p->tune_ms) t = -1.0;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     auto bail = [&](fse_status e) {
         destroy(p);
@@ -1891,26 +1907,29 @@ fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream) {
                 char* tab = std::strrchr(line, '\t');
                 if (!tab) continue;
                 *tab = '\0';
-                int a = -1, b = -1, c = -1;
-                if (key == line && std::sscanf(tab + 1, "%d %d %d", &a, &b, &c) == 3 && a >= 0 && a <= 1 &&
-                    b >= 0 && b <= 1 && c >= 0 && c <= 1)
-                    g_tune_cache[key] = {a, b, c};
+                std::array<int, kNSched> v{};
+                int used = 0;
+                if (key == line && std::sscanf(tab + 1, "%d %d %d %d%n", &v[0], &v[1], &v[2], &v[3], &used) == 4 &&
+                    std::all_of(v.begin(), v.end(), [](int x) { return x == 0 || x == 1; }))
+                    g_tune_cache[key] = v;
             }
             std::fclose(f);
         }
         it = g_tune_cache.find(key);
     }
     if (it != g_tune_cache.end()) {
-        for (int k = 0; k < 3; ++k) plan->sched[k] = it->second[k];
+        for (int k = 0; k < kNSched; ++k) plan->sched[k] = it->second[k];
+        for (double& t : plan->tune_ms) t = -1.0;
         return FSE_OK;
     }
     fse_status s = plan->prec == FSE_C128 ? tune_measure<double>(plan, st) : tune_measure<float>(plan, st);
     if (s != FSE_OK) return s;
-    g_tune_cache[key] = {plan->sched[0], plan->sched[1], plan->sched[2]};
+    g_tune_cache[key] = {plan->sched[0], plan->sched[1], plan->sched[2], plan->sched[3]};
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(FSE_ERR_ARG, "cannot append to the tuning cache %s", cache_path);
-        std::fprintf(f, "%s\t%d %d %d\n", key.c_str(), plan->sched[0], plan->sched[1], plan->sched[2]);
+        std::fprintf(f, "%s\t%d %d %d %d\n", key.c_str(), plan->sched[0], plan->sched[1], plan->sched[2],
+                     plan->sched[3]);
         std::fclose(f);
     }
     return FSE_OK;
@@ -1919,23 +1938,25 @@ fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream) {
 fse_status fse_plan_get_schedule(fse_plan plan, int* sched, double* tuned_ms) {
     g_err.clear();
     if (!plan || !sched) return fail(FSE_ERR_ARG, "plan and sched must not be NULL");
-    for (int k = 0; k < 3; ++k) sched[k] = plan->sched[k];
+    for (int k = 0; k < kNSched; ++k) sched[k] = plan->sched[k];
     if (tuned_ms)
-        for (int k = 0; k < 8; ++k) tuned_ms[k] = plan->tune_ms[k];
+        for (int k = 0; k < (1 << kNSched); ++k) tuned_ms[k] = plan->tune_ms[k];
     return FSE_OK;
 }
 
 fse_status fse_plan_set_schedule(fse_plan plan, const int* sched) {
     g_err.clear();
     if (!plan || !sched) return fail(FSE_ERR_ARG, "plan and sched must not be NULL");
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < kNSched; ++k)
         if (sched[k] != 0 && sched[k] != 1) return fail(FSE_ERR_ARG, "schedule entries are 0 or 1");
     if (sched[0] == 1 && !kin_has_alt(plan))
         return fail(FSE_ERR_UNSUPPORTED, "line length %d has no alternative radix schedule", plan->last());
     if (sched[1] == 1 && !conv_has_alt(plan))
         return fail(FSE_ERR_UNSUPPORTED, "the convolution of this plan has no alternative radix schedule");
     if (sched[2] == 1 && plan->d != 3) return fail(FSE_ERR_UNSUPPORTED, "the mirrored visit order is 3D only");
-    for (int k = 0; k < 3; ++k) plan->sched[k] = sched[k];
+    if (sched[3] == 1 && !cols_have_alt(plan))
+        return fail(FSE_ERR_UNSUPPORTED, "the column transforms of this plan have no alternative radix plan");
+    for (int k = 0; k < kNSched; ++k) plan->sched[k] = sched[k];
     return FSE_OK;
 }
 

@@ -36,15 +36,23 @@ namespace fse {
 //   Line tiles (contiguous axis): LPB whole lines, lanes ordered
 //   position-fastest.
 // ---------------------------------------------------------------------------
-// Radix plan of the column (strided-axis) transforms.
-template <int N> struct ColPlanOf { using L = FwdPlan<N>; };
-#ifdef FSE_COLPLAN256
-template <> struct ColPlanOf<256> { using L = RList<8, 8, 4>; };
-#endif
-#ifdef FSE_COLPLAN512
-template <> struct ColPlanOf<512> { using L = RList<16, 8, 4>; };
-#endif
-template <int N> using ColPlan = typename ColPlanOf<N>::L;
+// Radix plan of the column (strided-axis) transforms: CV = 0 the plain plan,
+// CV = 1 an alternative where the length has one (256 as 8.8.4 beside 16.16:
+// twice the threads per column, 8 points each, one more LDS exchange; the
+// autotuner picks per plan).
+template <int N, int CV = 0> struct ColPlanOf {
+    static constexpr bool has_alt = false;
+    using L = FwdPlan<N>;
+};
+template <> struct ColPlanOf<256, 1> {
+    static constexpr bool has_alt = true;
+    using L = RList<8, 8, 4>;
+};
+template <> struct ColPlanOf<256, 0> {
+    static constexpr bool has_alt = true;
+    using L = FwdPlan<256>;
+};
+template <int N, int CV = 0> using ColPlan = typename ColPlanOf<N, CV>::L;
 
 template <int N, typename PL> struct PlanOf { using L = PL; };
 template <int N> struct PlanOf<N, void> { using L = ColPlan<N>; };
@@ -80,9 +88,6 @@ constexpr int lds_waves(int lds_bytes, int nth) {
     return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 template <typename R, int N> constexpr int col_occ(int lds_bytes, int nth) {
-#ifdef FSE_PHASE_OCC
-    if (sizeof(R) == 4 && N == 256 && nth == 256) return lds_waves(lds_bytes, nth);
-#endif
     return (sizeof(R) == 8 && N <= 256) ? lds_waves(lds_bytes, nth) : 1;
 }
 #define FSE_COL_OCC(R, N, ...) __attribute__((amdgpu_waves_per_eu(col_occ<R, N>(__VA_ARGS__), 8)))
@@ -125,10 +130,7 @@ template <typename R, int N, bool CONV, int V = 0> struct LineCfg {
     // strand less of the 160 KB per CU than a few large ones (FP64 256^3:
     // convolution 16 -> 17 lines per CU, kinetic pass 8 -> 9; both ~2.5 %
     // faster than with a 40 KB budget)
-#ifndef FSE_LINE_BUDGET
-#define FSE_LINE_BUDGET 10240
-#endif
-    static constexpr int BUDGET = FSE_LINE_BUDGET / (P * (int)sizeof(T) * SUB);
+    static constexpr int BUDGET = 10240 / (P * (int)sizeof(T) * SUB);
     static constexpr int LPB0 = floor_pow2(BUDGET < 1 ? 1 : BUDGET);
     static constexpr int LPB1 = (LPB0 * TPL * SUB > 256) ? 256 / (TPL * SUB) : LPB0;
     static constexpr int LPBW = (TPL * SUB >= 64) ? 1 : 64 / (TPL * SUB);  // at least one full wavefront
@@ -175,15 +177,15 @@ template <typename R> __device__ __forceinline__ typename CT<R>::T scale_near_on
     }
 }
 
-template <typename R, int N, bool INV>
+template <typename R, int N, bool INV, int CV = 0>
 __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename CT<R>::T* out,
                                                             int B2, const typename CT<R>::T* twN, int bx, int by, typename CT<R>::T* lds,
                                                             const double* scale = nullptr) {
     using T = typename CT<R>::T;
-    using C = ColCfg<R, N>;
+    using C = ColCfg<R, N, ColPlan<N, CV>>;
     constexpr int W = C::W, TPL = C::TPL;
     constexpr int P = pitch_cols<N>(N);
-    using F = Fft<T, N, INV, TPL, ColPlan<N>>;
+    using F = Fft<T, N, INV, TPL, ColPlan<N, CV>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < B2;
@@ -206,14 +208,14 @@ __device__ __forceinline__ void cols_body(const typename CT<R>::T* in, typename 
 }
 
 // scale: null, or a device factor applied to the output (the complex64 mass renormalisation).
-template <typename R, int N, bool INV>
-__global__ __launch_bounds__((ColCfg<R, N>::NTH))
-FSE_COL_OCC(R, N, ColCfg<R, N>::W * pitch_cols<N>(N) * csz<R>(), ColCfg<R, N>::NTH)
+template <typename R, int N, bool INV, int CV = 0>
+__global__ __launch_bounds__((ColCfg<R, N, ColPlan<N, CV>>::NTH))
+FSE_COL_OCC(R, N, ColCfg<R, N>::W * pitch_cols<N>(N) * csz<R>(), ColCfg<R, N, ColPlan<N, CV>>::NTH)
 void k_cols(const typename CT<R>::T* in, typename CT<R>::T* out,
                                                             int B2, const typename CT<R>::T* twN,
                                                             const double* scale) {
     __shared__ typename CT<R>::T lds[ColCfg<R, N>::W * pitch_cols<N>(N)];
-    cols_body<R, N, INV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds, scale);
+    cols_body<R, N, INV, CV>(in, out, B2, twN, blockIdx.x, blockIdx.y, lds, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -565,16 +567,16 @@ __global__ __launch_bounds__((LineCfg<R, M, false, V>::NTH)) void k_conv_full(
 // m >= N0/2):
 //   X_k = (Z_k + conj Z_{N0-k})/2 + exp(-i pi k/N0) (Z_k - conj Z_{N0-k})/(2i).
 // ---------------------------------------------------------------------------
-template <typename R, int N0, int SRC>
+template <typename R, int N0, int SRC, int CV = 0>
 __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
                                                             int C, const typename CT<R>::T* twN,
                                                             const typename CT<R>::T* tw2N, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
-    using Cf = ColCfg<R, N0>;
+    using Cf = ColCfg<R, N0, ColPlan<N0, CV>>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols<N0>(N0 + 1);
-    using FI = Fft<T, N0, true, TPL, ColPlan<N0>>;
-    using FF = Fft<T, N0, false, TPL, ColPlan<N0>>;
+    using FI = Fft<T, N0, true, TPL, ColPlan<N0, CV>>;
+    using FF = Fft<T, N0, false, TPL, ColPlan<N0, CV>>;
     const int l = threadIdx.x % W, jt = threadIdx.x / W;
     const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
@@ -625,14 +627,14 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
     });
 }
 
-template <typename R, int N0, int SRC>
-__global__ __launch_bounds__((ColCfg<R, N0>::NTH))
-FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), ColCfg<R, N0>::NTH)
+template <typename R, int N0, int SRC, int CV = 0>
+__global__ __launch_bounds__((ColCfg<R, N0, ColPlan<N0, CV>>::NTH))
+FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), ColCfg<R, N0, ColPlan<N0, CV>>::NTH)
 void k_r2c(const void* src, typename CT<R>::T* X1,
                                                             int C, const typename CT<R>::T* __restrict__ twN,
                                                             const typename CT<R>::T* __restrict__ tw2N) {
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
-    r2c_body<R, N0, SRC>(src, X1, C, twN, tw2N, blockIdx.x, blockIdx.y, lds);
+    r2c_body<R, N0, SRC, CV>(src, X1, C, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------

@@ -18,8 +18,9 @@ template <typename R> struct Launch {
     // Strided length-N FFT over [B0][rows][B2]; mode 0 plain (N -> N rows), 1 zero-padded forward
     // (N -> 2N rows), 2 cropped inverse (2N -> N rows).  twN: length-N twiddles, tw2N: length 2N.
     // scale (mode 0 only): null, or a device factor near 1 applied to the output.
+    // cv (mode 0): 1 selects the alternative radix plan of the column transform where the length has one.
     static hipError_t strided(int N, bool inv, int mode, const void* in, void* out, int B0, int B2, const void* twN,
-                              const void* tw2N, hipStream_t st, const double* scale = nullptr);
+                              const void* tw2N, hipStream_t st, const double* scale = nullptr, int cv = 0);
     // Contiguous line pass on lines of N points; mode 0 padded conv (real multiplier over 2N frequencies),
     // 1 kinetic (complex table), 2 fwd, 3 inv.  var 1 selects the alternative radix schedule (AltRadix) of
     // the conv and kinetic transforms where the length has one, else the plain schedule is used.
@@ -31,7 +32,7 @@ template <typename R> struct Launch {
     static hipError_t conv_qf(int N, void* data, int nlines, const void* mult, LineIdx li, const void* tw2N,
                               const QForm& q, hipStream_t st);
     static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
-                          hipStream_t st);
+                          hipStream_t st, int cv = 0);
     // Axis-0 complex-to-real + nonlinear phase; mode 0 full, 1 phase only, 2 potential output only.
     static hipError_t c2r_phase(int N0, int mode, const void* X1, void* S, void* Phi, int C, const PhaseArgs& pa,
                                 const void* twN, const void* tw2N, hipStream_t st);
@@ -100,6 +101,8 @@ hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, b
 
 // Whether the line transform of length n has an alternative radix schedule (AltRadix).
 bool line_has_alt(int n);
+// Whether the column transform of length n has an alternative radix plan (ColPlanOf).
+bool col_has_alt(int n);
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);

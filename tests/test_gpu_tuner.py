@@ -29,12 +29,17 @@ def _require_gpu():
 
 
 # contiguous axis of 256 points: the kinetic lines (256) and the convolution
-# lines (512) both have an alternative radix schedule
+# lines (512) both have an alternative radix schedule; a 256-point axis 0 (or
+# axis 1 in 3D) has an alternative column plan
 CASES = {
     "rot3d": W.Params(d=3, N=(16, 24, 256), L=(4.0, 5.0, 12.0), s=0.8, Omega=0.5, gamma=(1.0, 1.2, 0.3),
                       beta=50.0, lam=5.0, kernel="coulomb", dt=1e-3, name="rot3d"),
     "rot2d": W.Params(d=2, N=(48, 256), L=(6.0, 12.0), s=0.7, Omega=0.6, gamma=(1.0, 0.5), beta=40.0, lam=2.0,
                       kernel="coulomb", dt=1e-3, name="rot2d"),
+    "cols3d": W.Params(d=3, N=(24, 256, 16), L=(5.0, 12.0, 4.0), s=0.9, Omega=0.4, gamma=(1.2, 0.3, 1.5),
+                       beta=30.0, lam=4.0, kernel="ddi3", dt=1e-3, name="cols3d"),
+    "cols2d": W.Params(d=2, N=(256, 48), L=(12.0, 6.0), s=0.8, Omega=0.5, gamma=(0.4, 1.1), beta=40.0, lam=2.0,
+                       kernel="coulomb", dt=1e-3, name="cols2d"),
 }
 _REF = {}
 
@@ -54,8 +59,16 @@ def _ref(name):
     return _REF[name]
 
 
-def _schedules(d):
-    return [list(s) for s in itertools.product((0, 1), (0, 1), (0, 1) if d == 3 else (0,))]
+def _schedules(plan):
+    """Every schedule the plan accepts."""
+    out = []
+    for sc in itertools.product((0, 1), repeat=fse.NSCHED):
+        try:
+            plan.set_schedule(list(sc))
+        except fse.FseError:
+            continue
+        out.append(list(sc))
+    return out
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -65,7 +78,9 @@ def test_every_schedule_against_oracle(name, prec, tol):
     psi0, ref = _ref(name)
     cd = np.complex128 if prec == fse.C128 else np.complex64
     plan = fse.Plan.from_params(p, prec)
-    for sc in _schedules(p.d):
+    scheds = _schedules(plan)
+    assert len(scheds) == {"rot3d": 8, "rot2d": 4, "cols3d": 4, "cols2d": 2}[name]
+    for sc in scheds:
         plan.set_schedule(sc)
         plan.time = 0.0
         x = torch.from_numpy(psi0.astype(cd)).cuda()
@@ -81,8 +96,9 @@ def test_tune_is_stable_and_file_cache_round_trips(tmp_path):
     a = fse.Plan.from_params(p, fse.C64)
     r1 = a.tune(cache_path=path)
     _note(f"[tuner] rot3d c64: {r1}")
-    assert all(v in (0, 1) for v in r1["schedule"])
-    assert all(t > 0 for t in r1["tuned_ms"])  # every schedule timed (3D, alternatives at 256 and 512)
+    assert all(v in (0, 1) for v in r1["schedule"]) and len(r1["schedule"]) == fse.NSCHED
+    # every allowed schedule timed (3D, line alternatives at 256 and 512, no 256-point column axis): 8 of 16
+    assert sum(t > 0 for t in r1["tuned_ms"]) == 8 and all(t == -1.0 for t in r1["tuned_ms"][8:])
     assert a.time == 0.0  # tuning runs steps on scratch and restores the plan's time
     with open(path) as f:
         lines = [l for l in f.read().splitlines() if l]
@@ -108,4 +124,22 @@ def test_invalid_schedules_rejected():
     small = fse.Plan.from_params(W.preset("plain2d"), fse.C128)  # 64-point lines: no alternative
     with pytest.raises(fse.FseError):
         small.set_schedule([1, 0, 0])
-    assert small.schedule()["schedule"] == [0, 0, 0]
+    assert small.schedule()["schedule"] == [0, 0, 0, 0]
+    with pytest.raises(fse.FseError):
+        small.set_schedule([0, 0, 0, 1])  # 64-point columns: no alternative plan
+    cols = fse.Plan.from_params(CASES["cols2d"], fse.C128)
+    cols.set_schedule([0, 0, 0, 1])
+    assert cols.schedule()["schedule"] == [0, 0, 0, 1]
+
+
+def test_tuning_a_column_axis_of_256_points():
+    p = CASES["cols3d"]
+    plan = fse.Plan.from_params(p, fse.C128)
+    r = plan.tune()
+    _note(f"[tuner] cols3d c128: {r}")
+    timed = [i for i, t in enumerate(r["tuned_ms"]) if t > 0]
+    assert len(timed) == 4 and all(i & 8 for i in timed[2:])  # the column plan alternative was timed
+    psi0, ref = _ref("cols3d")
+    x = torch.from_numpy(psi0).cuda()
+    plan.step(x, 2, p.dt)
+    assert float(np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)) < 1e-12
