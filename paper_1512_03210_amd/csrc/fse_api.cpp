@@ -374,6 +374,9 @@ fse::LineIdx conv_index(const fse_plan p) {
         li.F1 = 2 * p->N[1];
         li.T1 = p->N[1] + 1;
         li.T2 = p->N[2] + 1;
+        // lines k1 and 2 N1 - k1 share a multiplier row: visited side by side
+        // (one workgroup), the row is fetched once
+        li.X1 = 1;
     } else {
         li.D1 = 1;
         li.F0 = 0;
@@ -418,6 +421,7 @@ fse::PhaseArgs phase_args(const fse_plan p, TimeRef tn, double dt) {
         a.tau = dt;
         a.Om = p->Omega;
         a.gd = gdiff(p);
+        a.sf = std::sin(p->Omega * dt) / p->Omega;
         a.cc = a.cs = 0.0;
     } else {  // independent of the time, or at a fixed time
         fse::trap_rotating(tn.off, dt, p->Omega, gdiff(p), &a.cc, &a.cs);
@@ -2136,6 +2140,7 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
             const double gx2 = q.gamma[0] * q.gamma[0], gy2 = q.gamma[1] * q.gamma[1];
             d.ca = q.dt * (gx2 + gy2) / 4.0;
             d.gdiff = (gx2 - gy2) / 4.0;
+            d.sf = (q.Omega == 0.0) ? q.dt : std::sin(q.Omega * q.dt) / q.Omega;
             d.bdt = q.beta * q.dt;
             d.ldt = q.lambda * q.dt;
             d.x0 = -q.L[0];

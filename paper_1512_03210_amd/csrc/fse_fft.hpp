@@ -20,6 +20,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "fse_math.hpp"
+
 namespace fse {
 
 template <typename R> struct CT;
@@ -49,49 +51,6 @@ template <bool INV, typename T> __device__ __forceinline__ T mul_ni(T a) {
 template <bool INV, typename T> __device__ __forceinline__ T twmul(T a, T w) {
     return INV ? cmulc(a, w) : cmul(a, w);
 }
-
-// ---------------------------------------------------------------------------
-// Sine and cosine.
-// FP64: Cody-Waite reduction x = k pi/2 + r with pi/2 split into three doubles
-// (the first two with 33 significant bits, so k*P1 and k*P2 are exact for
-// |k| < 2^20; beyond that the reduction error stays within a few ulp of x, the
-// rounding the argument itself carries), then the Taylor series of sin and
-// cos on |r| <= pi/4 to degree 19 and 20 (truncation below 1e-22) and the
-// quadrant k mod 4.  FP32: the library routine.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void fsincos(double x, double* s, double* c) {
-    const double k = rint(x * 0.6366197723675814);  // 2/pi
-    double r = fma(-k, 1.5707963267341256, x);
-    r = fma(-k, 6.077100506303966e-11, r);
-    r = fma(-k, 2.0222662487959506e-21, r);
-    const double r2 = r * r;
-    double ps = -8.22063524662433e-18;  // -1/19!
-    ps = fma(ps, r2, 2.8114572543455206e-15);
-    ps = fma(ps, r2, -7.647163731819816e-13);
-    ps = fma(ps, r2, 1.6059043836821613e-10);
-    ps = fma(ps, r2, -2.505210838544172e-08);
-    ps = fma(ps, r2, 2.7557319223985893e-06);
-    ps = fma(ps, r2, -0.0001984126984126984);
-    ps = fma(ps, r2, 0.008333333333333333);
-    ps = fma(ps, r2, -0.16666666666666666);
-    const double sn = fma(r * r2, ps, r);
-    double pc = 4.110317623312165e-19;  // 1/20!
-    pc = fma(pc, r2, -1.5619206968586225e-16);
-    pc = fma(pc, r2, 4.779477332387385e-14);
-    pc = fma(pc, r2, -1.1470745597729725e-11);
-    pc = fma(pc, r2, 2.08767569878681e-09);
-    pc = fma(pc, r2, -2.755731922398589e-07);
-    pc = fma(pc, r2, 2.48015873015873e-05);
-    pc = fma(pc, r2, -0.001388888888888889);
-    pc = fma(pc, r2, 0.041666666666666664);
-    pc = fma(pc, r2, -0.5);
-    const double cs = fma(r2, pc, 1.0);
-    const int q = (int)(k - 4.0 * floor(0.25 * k));  // k mod 4, exact for any integral k
-    *s = (q == 0) ? sn : (q == 1) ? cs : (q == 2) ? -sn : -cs;
-    *c = (q == 0) ? cs : (q == 1) ? -sn : (q == 2) ? -cs : sn;
-}
-
-__device__ __forceinline__ void fsincos(float x, float* s, float* c) { sincosf(x, s, c); }
 
 // ---------------------------------------------------------------------------
 // Products with the butterflies' irrational constants (sqrt(1/2), cos and sin

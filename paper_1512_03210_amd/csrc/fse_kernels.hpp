@@ -495,7 +495,10 @@ __device__ __forceinline__ void conv_full_body(
     using FF = Fft<T, M, false, TPL, LineFwd<M, V>, WS, 2>;
     using FI = Fft<T, M, true, TPL, LineInv<M, V>, WS, 2>;
     const int jt = threadIdx.x % TPL;
-    const int dl = threadIdx.x / TPL;
+    // one line per wavefront (TPL = 64): the line index is uniform, so the
+    // line and multiplier-row arithmetic stays in scalar registers and the
+    // loads take a scalar base with 32-bit lane offsets
+    const int dl = (TPL == 64) ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPL) : threadIdx.x / TPL;
     const int gv = bx * LPB + dl;
     const bool valid = gv < nlines;
     const int gl = valid ? line_at(gv, li) : 0;
@@ -794,7 +797,7 @@ __device__ __forceinline__ PhaseArgs batch_phase(const BInst& b, int kstep) {
     pa.N2 = 0;
     pa.ca = b.ca;
     pa.cz = 0.0;
-    trap_rotating(tn, b.dt, b.Omega, b.gdiff, &pa.cc, &pa.cs);
+    trap_rotating_dev(tn, b.dt, b.Omega, b.gdiff, b.sf, &pa.cc, &pa.cs);
     pa.bdt = b.bdt;
     pa.ldt = b.ldt;
     pa.U = nullptr;
@@ -988,9 +991,10 @@ __global__ __launch_bounds__(RED_THREADS) void k_red_local(const typename CT<R>:
                                                            const double* tp, double Om, double gd,
                                                            double* partials, int slot0) {
     if (tp) {
-        const double th = 2.0 * Om * *tp;
-        wc = gd * cos(th);
-        ws = gd * sin(th);
+        double s2, c2;
+        fsincos(2.0 * Om * *tp, &s2, &c2);
+        wc = gd * c2;
+        ws = gd * s2;
     }
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (long i = blockIdx.x * (long)RED_THREADS + threadIdx.x; i < n; i += (long)gridDim.x * RED_THREADS) {

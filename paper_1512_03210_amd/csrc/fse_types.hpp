@@ -10,6 +10,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "fse_math.hpp"
+
 namespace fse {
 
 // The rotating part of the trap integral P(x~; t, t+tau) (eq. int_poten) for
@@ -26,6 +28,16 @@ __host__ __device__ inline void trap_rotating(double t, double tau, double Om, d
     const double f = sin(Om * tau) / Om;
     *cc = gd * (cos(Om * (2.0 * t + tau)) * f);
     *cs = gd * (sin(Om * (2.0 * t + tau)) * f);
+}
+
+// The same on the device with the time-independent factor sf = sin(Om tau)/Om
+// (tau without rotation) taken from the host: one sine/cosine pair per thread.
+__device__ inline void trap_rotating_dev(double t, double tau, double Om, double gd, double sf, double* cc,
+                                         double* cs) {
+    double s, c;
+    fsincos(Om * (2.0 * t + tau), &s, &c);
+    *cc = gd * (c * sf);
+    *cs = gd * (s * sf);
 }
 
 // Row of the multiplier table for a contiguous line: i0 = line / D1,
@@ -52,15 +64,16 @@ struct PhaseArgs {
     double ldt;                      // lambda * dt
     const void* U;                   // optional real potential on the grid (plan precision) or null
     double udt;                      // dt, the factor of U in the phase
-    // time-dependent cc, cs: with tp set they are trap_rotating(*tp + toff, tau, Om, gd)
+    // time-dependent cc, cs: with tp set they are trap_rotating(*tp + toff, tau, Om, gd);
+    // sf = sin(Om tau)/Om
     const double* tp = nullptr;
-    double toff = 0.0, tau = 0.0, Om = 0.0, gd = 0.0;
+    double toff = 0.0, tau = 0.0, Om = 0.0, gd = 0.0, sf = 0.0;
 };
 
 // cc, cs of the phase arguments at the device time (or as given when tp is null).
 __device__ inline void phase_time(const PhaseArgs& pa, double* cc, double* cs) {
     if (pa.tp) {
-        trap_rotating(*pa.tp + pa.toff, pa.tau, pa.Om, pa.gd, cc, cs);
+        trap_rotating_dev(*pa.tp + pa.toff, pa.tau, pa.Om, pa.gd, pa.sf, cc, cs);
     } else {
         *cc = pa.cc;
         *cs = pa.cs;
@@ -168,6 +181,7 @@ struct BInst {
     double dt, Omega;
     double ca;           // dt (gx^2 + gy^2)/4
     double gdiff;        // (gx^2 - gy^2)/4
+    double sf;           // sin(Omega dt)/Omega (dt without rotation)
     double bdt, ldt;     // beta dt, lambda dt
     double x0, hx, y0, hy;
 };
