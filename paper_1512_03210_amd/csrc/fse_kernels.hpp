@@ -346,6 +346,17 @@ __device__ __forceinline__ int line_at(int gl, const LineIdx& li) {
     return gl;
 }
 
+// Workgroups are dispatched to the eight XCDs round-robin (w mod 8), each XCD
+// with its own L2.  Visit position pairs (2j, 2j+1), which share a multiplier
+// row in mirror order, go to workgroups w and w + 8: the same XCD, one after
+// the other (a bijection on every group of 16; the identity when the grid is
+// not a multiple of 16).
+__device__ __forceinline__ int xcd_pairs(int w, int nw) {
+    if (nw & 15) return w;
+    const int s = w >> 3;  // dispatch slot on the XCD
+    return ((s >> 1) << 4) + ((w & 7) << 1) + (s & 1);
+}
+
 __device__ __forceinline__ long mult_row(int gl, const LineIdx& li) {
     const int k0 = fold(gl / li.D1, li.F0), k1 = fold(gl % li.D1, li.F1);
     return (long)(k0 * li.T1 + k1) * li.T2;
@@ -499,7 +510,7 @@ __device__ __forceinline__ void conv_full_body(
     // line and multiplier-row arithmetic stays in scalar registers and the
     // loads take a scalar base with 32-bit lane offsets
     const int dl = (TPL == 64) ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPL) : threadIdx.x / TPL;
-    const int gv = bx * LPB + dl;
+    const int gv = ((LPB == 1) ? xcd_pairs(bx, gridDim.x) : bx) * LPB + dl;
     const bool valid = gv < nlines;
     const int gl = valid ? line_at(gv, li) : 0;
     T* line = lds + dl * P;
