@@ -227,6 +227,9 @@ template <int R0, int... Rs> struct Rev<RList<R0, Rs...>> {
     using L = typename Cat<typename Rev<RList<Rs...>>::L, RList<R0>>::L;
 };
 
+template <typename L> struct Tail;
+template <int R0, int... Rs> struct Tail<RList<R0, Rs...>> { using L = RList<Rs...>; };
+
 // Radices strictly between the first and the last.
 template <typename L> struct Mid;
 template <int R0> struct Mid<RList<R0>> { using L = RList<>; };
@@ -337,6 +340,63 @@ __device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const TwP<T, M, TPL
     }
 }
 
+// Twiddle sources of a transform's stages after the first: the table (TW_TABLE),
+// the table with the twiddles kept in registers (TW_KEEP), or the registers kept
+// by an earlier transform with the same stages (TW_REUSE: no table reads and no
+// products; an inverse takes the conjugates of the same values, so its results
+// are the same as from the table).
+enum : int { TW_TABLE = 0, TW_KEEP = 1, TW_REUSE = 2 };
+
+// Kept twiddles W^r (r >= 1) of the butterflies of each stage of the list L,
+// whose first stage has NS = NS0.
+template <typename T, int M, int TPL, int NS0, typename L> struct TwKeep {
+    static constexpr int LEN = 0;
+};
+template <typename T, int M, int TPL, int NS0, int R0, int... Rs>
+struct TwKeep<T, M, TPL, NS0, RList<R0, Rs...>> {
+    static constexpr int LEN = 1 + sizeof...(Rs);
+    T w[Shape<M, TPL, R0>::B][R0];
+    TwKeep<T, M, TPL, NS0 * R0, RList<Rs...>> next;
+};
+template <typename K> __device__ __forceinline__ auto& tw_last(K& k) {
+    if constexpr (K::LEN == 1) return k.w;
+    else return tw_last(k.next);
+}
+
+// bfly with a twiddle source (TW_KEEP stores into w, TW_REUSE reads from it).
+template <int MODE, typename T, int M, bool INV, int TPL, int NS, int RAD, int B, int TWL>
+__device__ __forceinline__ void bfly_tw(T (&v)[B][RAD], int jt, const TwP<T, M, TPL, NS, RAD, TWL>& tp,
+                                        T (&w)[B][RAD]) {
+    using S = Shape<M, TPL, RAD>;
+    static_assert(B == S::B, "register array shape");
+#pragma unroll
+    for (int b = 0; b < S::B; ++b) {
+        const int j = jt + b * TPL;
+        if (S::active(j)) {
+            if constexpr (NS > 1) {
+                T p[4];
+                if constexpr (MODE != TW_REUSE) {
+#pragma unroll
+                    for (int bit = 0; bit < 4; ++bit)
+                        if (bit < TwP<T, M, TPL, NS, RAD, TWL>::NP) p[bit] = tp.p[b][bit];
+                }
+#pragma unroll
+                for (int r = 1; r < RAD; ++r) {
+                    T t;
+                    if constexpr (MODE == TW_REUSE) {
+                        t = w[b][r];
+                    } else {
+                        t = twpow<INV, T, RAD>(p, r);
+                        if constexpr (MODE == TW_KEEP) w[b][r] = t;
+                    }
+                    v[b][r] = twmul<INV>(v[b][r], t);
+                }
+            }
+            DFT<RAD, INV>::run(v[b]);
+        }
+    }
+}
+
 template <typename T, int M, bool INV, int TPL, int NS, int RAD, int B>
 __device__ __forceinline__ void bfly(T (&v)[B][RAD], int jt, const T* __restrict__ tw) {
     TwP<T, M, TPL, NS, RAD, 4> tp;
@@ -410,6 +470,29 @@ struct MidStages<T, M, INV, TPL, NS, RList<R0, Rs...>, WS, TWL> {
     }
 };
 
+// Middle stages with a twiddle source (see TW_TABLE); K holds this stage's
+// kept twiddles and those of the stages after it.
+template <typename T, int M, bool INV, int TPL, int NS, typename L, bool WS, int TWL, int MODE> struct MidStagesTw;
+template <typename T, int M, bool INV, int TPL, int NS, bool WS, int TWL, int MODE>
+struct MidStagesTw<T, M, INV, TPL, NS, RList<>, WS, TWL, MODE> {
+    template <typename K> __device__ __forceinline__ static void run(T*, int, const T*, K&) {}
+};
+template <typename T, int M, bool INV, int TPL, int NS, int R0, int... Rs, bool WS, int TWL, int MODE>
+struct MidStagesTw<T, M, INV, TPL, NS, RList<R0, Rs...>, WS, TWL, MODE> {
+    template <typename K>
+    __device__ __forceinline__ static void run(T* line, int jt, const T* __restrict__ tw, K& keep) {
+        T v[Shape<M, TPL, R0>::B][R0];
+        TwP<T, M, TPL, NS, R0, TWL> tp;
+        if constexpr (MODE != TW_REUSE) tp.load(jt, tw);
+        lds_sync<WS>();
+        get<T, M, TPL, R0>(v, line, jt);
+        lds_sync<WS>();
+        bfly_tw<MODE, T, M, INV, TPL, NS, R0>(v, jt, tp, keep.w);
+        put<T, M, TPL, NS, R0>(v, line, jt);
+        MidStagesTw<T, M, INV, TPL, NS * R0, RList<Rs...>, WS, TWL, MODE>::run(line, jt, tw, keep.next);
+    }
+};
+
 // Whole transform with register-resident ends.
 //   in:  v = inputs at positions j + r*M/R0 (first radix R0 of the plan L)
 //   out: u = outputs at positions j + r*M/Rk (last radix Rk)
@@ -444,6 +527,27 @@ template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int
             lds_sync<WS>();
             get<T, M, TPL, RK>(u, line, jt);
             bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tp);
+        }
+    }
+
+    // Twiddles of the stages after the first kept in registers: a transform
+    // run with TW_KEEP fills `keep`, a later one with the same stages (the same
+    // plan, or the inverse of a palindromic one) runs with TW_REUSE from it.
+    using Keep = TwKeep<T, M, TPL, R0, typename Tail<L>::L>;
+    template <int MODE>
+    __device__ __forceinline__ static void run_tw(T (&v)[B0][R0], T (&u)[BK][RK], T* line, int jt,
+                                                  const T* __restrict__ tw, Keep& keep) {
+        if constexpr (NSTAGE == 1) {
+            run(v, u, line, jt, tw);
+        } else {
+            bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
+            put<T, M, TPL, 1, R0>(v, line, jt);
+            MidStagesTw<T, M, INV, TPL, R0, typename Mid<L>::L, WS, TWL, MODE>::run(line, jt, tw, keep);
+            TwP<T, M, TPL, M / RK, RK, TWL> tp;
+            if constexpr (MODE != TW_REUSE) tp.load(jt, tw);
+            lds_sync<WS>();
+            get<T, M, TPL, RK>(u, line, jt);
+            bfly_tw<MODE, T, M, INV, TPL, M / RK, RK>(u, jt, tp, tw_last(keep));
         }
     }
 };

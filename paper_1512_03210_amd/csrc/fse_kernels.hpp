@@ -22,6 +22,8 @@
 //   k_line<kin>   forward FFT, kinetic phase exp(-i tau omega/2)/n from a
 //                 table folded by |p|, inverse FFT (contiguous axis).
 #pragma once
+#include <type_traits>
+
 #include "fse_fft.hpp"
 #include "fse_types.hpp"
 
@@ -398,7 +400,12 @@ __device__ __forceinline__ void lines_body(
             if (MODE == 0 && h == 1) x = cmul(x, tw2[e]);
             v[b][r] = x;
         });
-        FF::run(v, u, line, jt, twN);
+        // FP32 kinetic pass with a palindromic plan: the inverse takes the
+        // forward's twiddles from registers
+        constexpr bool KEEP = MODE == 1 && sizeof(R) == 4 && std::is_same<LineFwd<N, V>, LineInv<N, V>>::value;
+        typename FF::Keep keep;
+        if constexpr (KEEP) FF::template run_tw<TW_KEEP>(v, u, line, jt, twN, keep);
+        else FF::run(v, u, line, jt, twN);
         if constexpr (MODE == 2) {
             for_pos<N, TPL, FF::RK>(jt, [&](int b, int r, int e) {
                 if (valid) g[e] = u[b][r];
@@ -417,7 +424,8 @@ __device__ __forceinline__ void lines_body(
             });
             typename FI::Out w;
             lds_sync<WS>();
-            FI::run(u, w, line, jt, twN);
+            if constexpr (KEEP) FI::template run_tw<TW_REUSE>(u, w, line, jt, twN, keep);
+            else FI::run(u, w, line, jt, twN);
             if constexpr (MODE == 1) {
                 for_pos<N, TPL, FI::RK>(jt, [&](int b, int r, int e) {
                     if (valid) g[e] = w[b][r];
@@ -541,13 +549,19 @@ __device__ __forceinline__ void conv_full_body(
     } else {
         for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
     }
-    FF::run(v, u, line, jt, twM);
+    // FP32 (bound by VALU issue) with a palindromic plan: the inverse takes the
+    // forward's twiddles from registers
+    constexpr bool KEEP = sizeof(R) == 4 && std::is_same<LineFwd<M, V>, LineInv<M, V>>::value;
+    typename FF::Keep keep;
+    if constexpr (KEEP) FF::template run_tw<TW_KEEP>(v, u, line, jt, twM, keep);
+    else FF::run(v, u, line, jt, twM);
     for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int) {
         u[b][r] = T{u[b][r].x * kq[b][r], u[b][r].y * kq[b][r]};
     });
     typename FI::Out w;
     lds_sync<WS>();
-    FI::run(u, w, line, jt, twM);
+    if constexpr (KEEP) FI::template run_tw<TW_REUSE>(u, w, line, jt, twM, keep);
+    else FI::run(u, w, line, jt, twM);
     for_pos<M, TPL, FI::RK>(jt, [&](int b, int r, int e) {
         if (valid && e < N) g[e] = w[b][r];
     });
@@ -595,13 +609,18 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
     const int col0 = bx * W;
     const bool lv = (col0 + l) < C;
     T* line = lds + l * P;
+    // FP32: the forward transform of the packed density has the stages of the
+    // state's inverse and takes its twiddles from registers
+    constexpr bool KEEP = SRC == 0 && sizeof(R) == 4;
+    typename FI::Keep keep;
     // density at the thread's positions, then into LDS (real part)
     if constexpr (SRC == 0) {
         const T* g = static_cast<const T*>(src) + col0 + l;
         typename FI::In v;
         typename FI::Out u;
         for_pos<N0, TPL, FI::R0>(jt, [&](int b, int r, int e) { v[b][r] = lv ? g[(long)e * C] : T{0, 0}; });
-        FI::run(v, u, line, jt, twN);
+        if constexpr (KEEP) FI::template run_tw<TW_KEEP>(v, u, line, jt, twN, keep);
+        else FI::run(v, u, line, jt, twN);
         __syncthreads();
         for_pos<N0, TPL, FI::RK>(jt, [&](int b, int r, int e) {
             line[padx<N0>(e)].x = u[b][r].x * u[b][r].x + u[b][r].y * u[b][r].y;
@@ -623,7 +642,8 @@ __device__ __forceinline__ void r2c_body(const void* src, typename CT<R>::T* X1,
         z[b][r] = (m < N0 / 2) ? T{line[padx<N0>(2 * m)].x, line[padx<N0>(2 * m + 1)].x} : T{0, 0};
     });
     __syncthreads();
-    FF::run(z, Z, line, jt, twN);
+    if constexpr (KEEP) FF::template run_tw<TW_REUSE>(z, Z, line, jt, twN, keep);
+    else FF::run(z, Z, line, jt, twN);
     __syncthreads();
     for_pos<N0, TPL, FF::RK>(jt, [&](int b, int r, int k) { line[padx<N0>(k)] = Z[b][r]; });
     __syncthreads();
