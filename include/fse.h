@@ -440,6 +440,21 @@ fse_status fse_batch_reduce(fse_batch batch, const void* psi_packed, double* out
 /* Current time of every instance (host memory, count values). */
 fse_status fse_batch_times(fse_batch batch, double* t);
 
+/* The FP64 mass renormalisation of fse_set_mass_renorm for every instance of
+ * a batch step call: the call reduces each instance's mass at its start and
+ * before its exit pass, which scales the instance by sqrt(M_start /
+ * M_before) (eq. MassEnerg: the scheme conserves the discrete mass exactly).
+ * Default: on for complex64 batches, off for complex128.  Changing it
+ * synchronises the device and drops the captured graphs (the next
+ * fse_batch_step records them again). */
+fse_status fse_batch_set_mass_renorm(fse_batch batch, int enable);
+
+/* Whether it is on, and (factor_mass nullable, host memory, 3 x count doubles)
+ * per instance the last call's factor, the mass before the exit pass and the
+ * mass at the call's start (1, 1, 1 before the first renormalising call;
+ * synchronises the device). */
+fse_status fse_batch_get_mass_renorm(fse_batch batch, int* enabled, double* factor_mass);
+
 /* Per-pass timing for benchmarking.  While enabled, fse_step records a HIP
  * event pair on its stream around every kernel launch.  fse_get_profile
  * synchronises those events, adds the elapsed milliseconds per pass kind

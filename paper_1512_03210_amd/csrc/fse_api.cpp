@@ -62,6 +62,7 @@ fse_status fail(fse_status st, const char* fmt, ...) {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kRedBlocks = 1024;
+constexpr int kBatchRed = 32;  // partial sums per instance of the batched mass reduction
 constexpr int kRedSlots = 8;
 constexpr int kNSched = FSE_NSCHED;  // entries of a pass schedule (fse.h)
 constexpr double kTuneMargin = 0.01;  // another schedule must be 1 % faster to replace the current one
@@ -1526,6 +1527,11 @@ struct fse_batch_s {
     hipStream_t cap = nullptr;
     hipEvent_t fork = nullptr;
     std::map<std::pair<int, void*>, hipGraphExec_t> graphs;
+    // FP64 mass renormalisation of a step call (on by default for complex64): per instance
+    // {mass at the call's start, factor, mass before the exit pass, -} and kBatchRed partial sums
+    bool renorm_on = false;
+    double* rn = nullptr;
+    double* partials = nullptr;
 };
 
 namespace {
@@ -1541,6 +1547,8 @@ void batch_destroy(fse_batch b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->d_all) (void)hipFree(b->d_all);
     if (b->t_dev) (void)hipFree(b->t_dev);
+    if (b->rn) (void)hipFree(b->rn);
+    if (b->partials) (void)hipFree(b->partials);
     // plans sharing a multiplier do not own it; destroy them after its owner's users
     for (auto it = b->plans.rbegin(); it != b->plans.rend(); ++it) destroy(*it);
     delete b;
@@ -1558,6 +1566,10 @@ template <typename R> fse_status batch_record_group(fse_batch b, const fse_batch
     void* a1 = rep->tw[N1];
     void* b1 = g.nl ? rep->tw[2 * N1] : nullptr;
     hipStream_t st = g.s;
+    const bool rn = b->renorm_on;
+    double* part = b->partials + g.first * kBatchRed;  // (the groups' branches run concurrently: disjoint ranges)
+    const long npts = (long)N0 * N1;
+    if (rn) HIPCHK(L::batch_mass(0, npts, 1.0, psi, d, cnt, part, kBatchRed, st));
     HIPCHK(L::batch(0, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
     HIPCHK(L::batch(2, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
     for (int k = 0; k < nsteps; ++k) {
@@ -1570,7 +1582,9 @@ template <typename R> fse_status batch_record_group(fse_batch b, const fse_batch
         }
         HIPCHK(L::batch(2, N0, N1, psi, d, cnt, (k == nsteps - 1) ? 0 : 1, lk, a0, b0, a1, b1, st));
     }
-    HIPCHK(L::batch(1, N0, N1, psi, d, cnt, 0, lk, a0, b0, a1, b1, st));
+    // the exit pass applies each instance's factor (which = 1) after the mass before it is taken
+    if (rn) HIPCHK(L::batch_mass(1, npts, (double)N0, psi, d, cnt, part, kBatchRed, st));
+    HIPCHK(L::batch(1, N0, N1, psi, d, cnt, rn ? 1 : 0, lk, a0, b0, a1, b1, st));
     return FSE_OK;
 }
 
@@ -2122,6 +2136,15 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
     if (hipMalloc((void**)&b->t_dev, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_NOMEM, "hipMalloc"));
     if (hipMemset(b->t_dev, 0, sizeof(double) * count) != hipSuccess) return bail(fail(FSE_ERR_HIP, "hipMemset"));
     for (int i = 0; i < count; ++i) b->plans[i]->tdev = b->t_dev + i;  // the diagnostics read the instance's time
+    if (hipMalloc((void**)&b->rn, sizeof(double) * 4 * count) != hipSuccess ||
+        hipMalloc((void**)&b->partials, sizeof(double) * kBatchRed * count) != hipSuccess)
+        return bail(fail(FSE_ERR_NOMEM, "hipMalloc"));
+    {
+        std::vector<double> r0(4 * (size_t)count, 1.0);  // factor 1 until a renormalising call sets it
+        if (hipMemcpy(b->rn, r0.data(), sizeof(double) * r0.size(), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(FSE_ERR_HIP, "hipMemcpy"));
+    }
+    b->renorm_on = (precision == FSE_C64);
     std::vector<fse::BInst> desc;
     for (auto& g : b->groups) {
         g.first = desc.size();
@@ -2147,6 +2170,7 @@ fse_status fse_batch_create(fse_batch* out, int count, const fse_instance* inst,
             d.hx = p->h[0];
             d.y0 = -q.L[1];
             d.hy = p->h[1];
+            d.rn = b->rn + 4 * i;
             desc.push_back(d);
         }
         if (hipStreamCreateWithFlags(&g.s, hipStreamNonBlocking) != hipSuccess ||
@@ -2184,6 +2208,36 @@ fse_status fse_batch_times(fse_batch batch, double* t) {
     g_err.clear();
     if (!batch || !t) return fail(FSE_ERR_ARG, "batch and t must not be NULL");
     for (int i = 0; i < batch->count; ++i) t[i] = batch->t_host[i];
+    return FSE_OK;
+}
+
+fse_status fse_batch_set_mass_renorm(fse_batch batch, int enable) {
+    g_err.clear();
+    if (!batch) return fail(FSE_ERR_ARG, "batch must not be NULL");
+    if ((enable != 0) != batch->renorm_on) {
+        // the captured graphs carry the setting: record them again
+        HIPCHK(hipDeviceSynchronize());
+        for (auto& kv : batch->graphs) (void)hipGraphExecDestroy(kv.second);
+        batch->graphs.clear();
+        batch->renorm_on = enable != 0;
+    }
+    return FSE_OK;
+}
+
+fse_status fse_batch_get_mass_renorm(fse_batch batch, int* enabled, double* factor_mass) {
+    g_err.clear();
+    if (!batch || !enabled) return fail(FSE_ERR_ARG, "batch and enabled must not be NULL");
+    *enabled = batch->renorm_on ? 1 : 0;
+    if (factor_mass) {
+        std::vector<double> r(4 * (size_t)batch->count);
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(r.data(), batch->rn, sizeof(double) * r.size(), hipMemcpyDeviceToHost));
+        for (int i = 0; i < batch->count; ++i) {  // (the order of fse_get_mass_renorm)
+            factor_mass[3 * i] = r[4 * i + 1];
+            factor_mass[3 * i + 1] = r[4 * i + 2];
+            factor_mass[3 * i + 2] = r[4 * i];
+        }
+    }
     return FSE_OK;
 }
 

@@ -840,11 +840,12 @@ template <typename R, int N0, bool INV>
 __global__ __launch_bounds__((ColCfg<R, N0>::NTH))
 FSE_COL_OCC(R, N0, ColCfg<R, N0>::W * pitch_cols<N0>(N0) * csz<R>(), ColCfg<R, N0>::NTH)
 void k_b_cols(void* psi, const BInst* bi, int N1,
-                                                                const typename CT<R>::T* twN0) {
+                                                                const typename CT<R>::T* twN0, int scaled) {
     using T = typename CT<R>::T;
     T* x = static_cast<T*>(psi) + bi[blockIdx.y].psi_off;
     __shared__ typename CT<R>::T lds[ColCfg<R, N0>::W * pitch_cols<N0>(N0)];
-    cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds, nullptr);
+    // scaled: the exit pass applies the instance's mass renormalisation factor
+    cols_body<R, N0, INV>(x, x, N1, twN0, blockIdx.x, 0, lds, scaled ? bi[blockIdx.y].rn + 1 : nullptr);
 }
 
 template <typename R, int N1>
@@ -1163,6 +1164,60 @@ static __global__ __launch_bounds__(RED_THREADS) void k_renorm_factor(const doub
         const double f = sqrt(r[0] / M);
         r[2] = M;
         r[1] = (M > 0.0 && isfinite(f)) ? f : 1.0;
+    }
+}
+
+// Batched FP64 mass of the instances of a group (grid.y = instance within the
+// group, n points each): per-block partial sums of |psi|^2 into
+// partials[instance * gridDim.x + block].
+template <typename R>
+__global__ __launch_bounds__(RED_THREADS) void k_b_mass_part(const void* psi, const BInst* __restrict__ bi, long n,
+                                                             double* __restrict__ partials) {
+    using T = typename CT<R>::T;
+    __shared__ double red[RED_THREADS / 64];
+    const T* x = static_cast<const T*>(psi) + bi[blockIdx.y].psi_off;
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)RED_THREADS + threadIdx.x; i < n; i += (long)gridDim.x * RED_THREADS) {
+        const T v = x[i];
+        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+        partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// One block per instance of the group: M = mscale * hx * hy * (sum of its
+// partials).  slot 0: rn[0] = M (the mass at the call's start); slot 1:
+// rn[2] = M and rn[1] = sqrt(rn[0] / M), the factor the exit pass applies (1
+// when M is zero or the factor is not finite).
+static __global__ __launch_bounds__(RED_THREADS) void k_b_mass_final(const double* __restrict__ partials, int nblk,
+                                                                     const BInst* __restrict__ bi, double mscale,
+                                                                     int slot) {
+    __shared__ double red[RED_THREADS / 64];
+    const BInst& b = bi[blockIdx.x];
+    double x = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += RED_THREADS) x += partials[(long)blockIdx.x * nblk + k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RED_THREADS / 64; ++w) t += red[w];
+        const double M = mscale * b.hx * b.hy * t;
+        if (slot == 0) {
+            b.rn[0] = M;
+        } else {
+            const double f = sqrt(b.rn[0] / M);
+            b.rn[2] = M;
+            b.rn[1] = (M > 0.0 && isfinite(f)) ? f : 1.0;
+        }
     }
 }
 

@@ -40,6 +40,11 @@ template <typename R> struct Launch {
     static hipError_t batch(int kind, int N0, int N1, void* psi, const BInst* bi, int count, int which, LineIdx li,
                             const void* twN0, const void* tw2N0, const void* twN1, const void* tw2N1,
                             hipStream_t st);
+    // Batched FP64 mass of `count` equal-size instances of n points (nblk partial sums each): slot 0
+    // stores it as the call's start mass, slot 1 as the mass before the exit pass (times mscale, the
+    // pending axis-0 inverse's N0) together with the factor that restores the start mass.
+    static hipError_t batch_mass(int slot, long n, double mscale, const void* psi, const BInst* bi, int count,
+                                 double* partials, int nblk, hipStream_t st);
     // Even Fourier table on the non-negative octant, omega = (|mu|^2 + m2)^s: kind 0 the phase
     // scale * exp(-i tau omega/2), kind 1 the resolvent scale / (c0 + omega/2), kind 2 scale * omega/2.
     static hipError_t build_kin(void* Q, int T0, int T1, int T2, double dmu0, double dmu1, double dmu2, double s,
@@ -96,6 +101,9 @@ template <typename R> struct Launch {
 hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, double* out, hipStream_t st);
 
 hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t st);
+// Per instance (one block each) of the batched mass: see Launch<R>::batch_mass.
+hipError_t launch_b_mass_final(const double* partials, int nblk, const BInst* bi, int count, double mscale, int slot,
+                               hipStream_t st);
 
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, bool nontemporal = false);
 

@@ -22,6 +22,12 @@ hipError_t launch_batch_time(const BInst* bi, int count, int nsteps, hipStream_t
     return hipGetLastError();
 }
 
+hipError_t launch_b_mass_final(const double* partials, int nblk, const BInst* bi, int count, double mscale, int slot,
+                               hipStream_t st) {
+    k_b_mass_final<<<(unsigned)count, RED_THREADS, 0, st>>>(partials, nblk, bi, mscale, slot);
+    return hipGetLastError();
+}
+
 hipError_t launch_gs_slots(const double* partials, int nblk, int nslot, int op, double* out, hipStream_t st) {
     k_gs_slots<<<(unsigned)nslot, RED_THREADS, 0, st>>>(partials, nblk, op, out);
     return hipGetLastError();

@@ -184,6 +184,7 @@ struct BInst {
     double sf;           // sin(Omega dt)/Omega (dt without rotation)
     double bdt, ldt;     // beta dt, lambda dt
     double x0, hx, y0, hy;
+    double* rn;          // FP64 mass renormalisation {mass at the call's start, factor, mass before the exit pass}
 };
 
 }  // namespace fse

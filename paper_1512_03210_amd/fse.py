@@ -36,7 +36,7 @@ EXPORTS = [
     "fse_device_copy", "fse_batch_create", "fse_batch_destroy", "fse_batch_offsets", "fse_batch_step",
     "fse_batch_reduce", "fse_batch_times", "fse_gs_step", "fse_set_guard", "fse_guard_status",
     "fse_mass_noalloc", "fse_gs_run", "fse_angular_momentum_grad", "fse_set_mass_renorm", "fse_get_mass_renorm",
-    "fse_device_copy_nt",
+    "fse_device_copy_nt", "fse_batch_set_mass_renorm", "fse_batch_get_mass_renorm",
 ]
 PASS_NAMES = ["edge", "r2c", "pad_fwd", "conv", "crop_inv", "c2r_phase", "f1", "kin", "i1"]
 
@@ -127,6 +127,8 @@ def lib():
         "fse_batch_step": (st, [vp, vp, i, vp]),
         "fse_batch_reduce": (st, [vp, vp, vp, vp]),
         "fse_batch_times": (st, [vp, dp]),
+        "fse_batch_set_mass_renorm": (st, [vp, i]),
+        "fse_batch_get_mass_renorm": (st, [vp, ip, dp]),
         "fse_gs_step": (st, [vp, vp, d, d, i, ctypes.POINTER(GsStats), vp]),
         "fse_gs_run": (st, [vp, vp, d, d, i, i, d, d, dp, ctypes.POINTER(GsRunStats), vp]),
     }
@@ -556,3 +558,17 @@ class Batch:
         t = (ctypes.c_double * self.count)()
         _check(lib().fse_batch_times(self._h, t))
         return list(t)
+
+    def set_mass_renorm(self, enable: bool):
+        """FP64 mass renormalisation of every instance per step call (fse_batch_set_mass_renorm; default on for
+        complex64)."""
+        _check(lib().fse_batch_set_mass_renorm(self._h, 1 if enable else 0))
+
+    def mass_renorm(self):
+        """(enabled, array (count, 3): per instance the last factor, the mass before the exit pass and the mass at
+        the call's start) (fse_batch_get_mass_renorm)."""
+        import numpy as np
+        e = ctypes.c_int()
+        r = (ctypes.c_double * (3 * self.count))()
+        _check(lib().fse_batch_get_mass_renorm(self._h, ctypes.byref(e), r))
+        return bool(e.value), np.array(r[:], dtype=np.float64).reshape(self.count, 3)

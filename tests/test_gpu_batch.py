@@ -183,3 +183,40 @@ def test_batch_dipole_instances_keep_their_own_axis():
         err = float(np.linalg.norm(got - r) / np.linalg.norm(r))
         _note(f"[batch] dipole instance {params[k].name}: {err:.3e}")
         assert err < 1e-11
+
+
+def test_complex64_batch_mass_renormalisation():
+    # complex64, 300 steps in one call: with the FP64 renormalisation (the default) every instance returns the
+    # mass it was given; without it the FP32 twiddle residuals bias the mass; the state against the FP64 batch
+    # does not get worse
+    params = _instances()
+    states = _states(params, seed0=50)
+    nsteps = 300
+    out = {}
+    for on in (True, False):
+        b = fse.Batch(params, fse.C64)
+        enabled, rn = b.mass_renorm()
+        assert enabled and np.all(rn == 1.0)  # on by default, factor 1 before the first call
+        b.set_mass_renorm(on)
+        x = b.pack(states)
+        m0 = b.reduce(x)[:, 0].cpu().numpy()
+        b.step(x, nsteps)
+        m1 = b.reduce(x)[:, 0].cpu().numpy()
+        out[on] = ((m1 - m0) / m0, b.mass_renorm(), b.unpack(x))
+    ref = fse.Batch(params, fse.C128)
+    assert not ref.mass_renorm()[0]  # off for complex128
+    y = ref.pack(states)
+    ref.step(y, nsteps)
+    ry = ref.unpack(y)
+    e_on = [float(np.linalg.norm(a - r) / np.linalg.norm(r)) for a, r in zip(out[True][2], ry)]
+    e_off = [float(np.linalg.norm(a - r) / np.linalg.norm(r)) for a, r in zip(out[False][2], ry)]
+    _note(f"[batch renorm] relative dmass on {np.abs(out[True][0]).max():.2e}, off {np.abs(out[False][0]).max():.2e}; "
+          f"factors {out[True][1][1][:, 0]}; state vs FP64 on {max(e_on):.3e}, off {max(e_off):.3e}")
+    # the exit transform, after the mass is measured, adds its own FP32 rounding (~1e-8)
+    assert np.abs(out[True][0]).max() < 1e-7
+    f = out[True][1][1][:, 0]
+    assert np.all(np.abs(f - 1.0) < 1e-3) and np.any(f != 1.0)
+    # the start mass the call recorded is the reduced input mass
+    assert np.allclose(out[True][1][1][:, 2], m0, rtol=1e-12, atol=0)
+    assert not out[False][1][0]
+    assert sum(e_on) <= sum(e_off) * 1.05
