@@ -368,6 +368,23 @@ def test_large_nonlinear_phases(beta, tol):
     assert err < tol
 
 
+@pytest.mark.parametrize("beta,tol", [(3e3, 1e-5), (3e5, 5e-5)])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_large_nonlinear_phases_complex64(beta, tol, sign):
+    # the FP32 sine/cosine away from |theta| < pi/4: dt*beta*rho reaches ~1 and ~1e2 rad, positive forward and
+    # negative backward in time (quadrants k != 0 of both signs).  The FP32 phase is itself rounded at a few
+    # 2^-24 |theta| (~2e-5 at 1e2 rad), which sets the bound; the oracle's phase is FP64.
+    p = P("local2d").replace(beta=beta)
+    psi0 = _psi0(p, seed=9)
+    ref, _ = _oracle_problem(p).step(psi0, 0.0, sign * p.dt)
+    plan = fse.Plan.from_params(p, fse.C64)
+    x = torch.from_numpy(psi0.astype(np.complex64)).cuda()
+    plan.step(x, 1, sign * p.dt)
+    err = _rel(x.cpu().numpy().astype(np.complex128), ref)
+    _note(f"[parity] complex64 large phase beta={beta:g} sign={sign:+g}: {err:.3e}")
+    assert err < tol
+
+
 def test_deterministic_rerun():
     p = P("coul3d")
     psi0 = _psi0(p, seed=6)
