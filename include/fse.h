@@ -192,7 +192,7 @@ fse_status fse_guard_status(fse_plan plan, int* tripped, double* masses);
 fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stream);
 
 /* Entries of a pass schedule (fse_plan_tune, fse_plan_get_schedule, fse_plan_set_schedule). */
-#define FSE_NSCHED 4
+#define FSE_NSCHED 5
 
 /* Autotuner of the plan's pass schedule.  Times, on the plan's own workspace,
  * the compiled alternatives of its tunable passes and keeps the fastest:
@@ -203,25 +203,28 @@ fse_status fse_step4(fse_plan plan, void* psi, int nsteps, double dt, void* stre
  *             share a table row together; 3D only);
  *   sched[3]  radix plan of the step's column transforms along axis 0 (and
  *             axis 1 in 3D): 0 plain, 1 the alternative where the length has
- *             one (256 as 8.8.4 beside 16.16).
+ *             one (256 as 8.8.4 beside 16.16);
+ *   sched[4]  radix plan of the fused complex-to-real + nonlinear phase pass
+ *             (axis 0): 0 the default (256: 8.8.4 in FP64, 16.16 in
+ *             complex64), 1 the other one, where the length has two (256).
  * Another schedule replaces the current one only when it is at least 1 %
  * faster, so repeated tuning is stable.  Results are cached for the process
  * per device name and architecture, grid, precision and presence of the
  * nonlocal term; with cache_path non-NULL they are also looked up in, and
- * appended to, that text file ("key<TAB>s0 s1 s2 s3" lines), so a cached
+ * appended to, that text file ("key<TAB>s0 s1 s2 s3 s4" lines), so a cached
  * shape is not timed again.  Candidates are timed on whole steps (two TS2
  * steps on the plan's scratch state, every allowed schedule, interleaved over
  * five rounds), since a pass timed alone can stay in the last-level cache.
  * Synchronous on `stream`; allocates the diagnostics buffer and the step's
  * kinetic tables if absent; overwrites the plan's workspace, not the caller's
  * state; the plan's time is unchanged.
- * Without tuning a plan uses the default schedule {0, 0, 1 in 3D FP64 else 0, 0}. */
+ * Without tuning a plan uses the default schedule {0, 0, 1 in 3D FP64 else 0, 0, 0}. */
 fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream);
 
 /* The plan's schedule (sched[FSE_NSCHED], as above) and, if tuned_ms is not
  * NULL, the last measurement: 2^FSE_NSCHED values, the time in ms of one step
- * with schedule {k, c, o, v} at index k + 2c + 4o + 8v (-1 where not
- * measured). */
+ * with schedule {k, c, o, v, f} at index k + 2c + 4o + 8v + 16f (-1 where
+ * not measured). */
 fse_status fse_plan_get_schedule(fse_plan plan, int* sched, double* tuned_ms);
 
 /* Force a schedule (sched[FSE_NSCHED], entries 0 or 1).  FSE_ERR_UNSUPPORTED

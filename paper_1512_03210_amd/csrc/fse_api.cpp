@@ -117,7 +117,7 @@ struct fse_plan_s {
     // 3D only), [3] radix plan of the step's column transforms (1: the
     // alternative where the length has one); defaults set at creation,
     // changed by fse_plan_tune/set_schedule
-    int sched[kNSched] = {0, 0, 0, 0};
+    int sched[kNSched] = {0, 0, 0, 0, 0};
     // dipole with products n_i n_j or an axis that turns in the rotating frame:
     // khat holds the Coulomb-part symbol and each convolution gets a QForm
     bool qf = false;
@@ -647,10 +647,12 @@ fse_status step_impl(fse_plan p, void* psi, int nsteps, double dt, int order, hi
                     PLAUNCH(p, FSE_PASS_CONV, st, conv_line<R>(p, at_plan(tj - tau), tau, st));
                 }
                 PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
-                        L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+                        L::c2r_phase(N0, 0, p->X1, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st,
+                                     p->sched[4]));
             } else {
                 PLAUNCH(p, FSE_PASS_C2R_PHASE, st,
-                        L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st));
+                        L::c2r_phase(N0, 1, nullptr, psi, nullptr, p->C0, pa, p->tw[N0], p->tw[2 * N0], st,
+                                     p->sched[4]));
             }
             void* tab = (j < nw - 1) ? ki_tab : (k == nsteps - 1) ? kh : kf;
             if (p->d == 3)
@@ -945,6 +947,7 @@ bool kin_has_alt(const fse_plan p) { return fse::line_has_alt(p->last()); }
 bool cols_have_alt(const fse_plan p) {
     return fse::col_has_alt(p->N[0]) || (p->d == 3 && fse::col_has_alt(p->N[1]));
 }
+bool fused_has_alt(const fse_plan p) { return fse::fused_has_alt(p->N[0]); }
 bool conv_has_alt(const fse_plan p) {
     const int n = p->last();
     return p->nl && ((2 * n <= 512) ? fse::line_has_alt(2 * n) : fse::line_has_alt(n));
@@ -952,8 +955,8 @@ bool conv_has_alt(const fse_plan p) {
 
 // Times every schedule the plan allows on whole steps (two TS2 steps on the
 // plan's scratch state, so that each pass meets the caches as in a run) and
-// keeps the fastest; tune_ms[k + 2c + 4o + 8v] is the time per step of
-// schedule {k, c, o, v}.  The plan's time is restored.
+// keeps the fastest; tune_ms[k + 2c + 4o + 8v + 16f] is the time per step of
+// schedule {k, c, o, v, f}.  The plan's time is restored.
 template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     fse_status s = ensure_diag(p);
     if (s != FSE_OK) return s;
@@ -968,10 +971,11 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     for (int q = 0; q < kNSched; ++q) keep[q] = p->sched[q];
     for (double& t : p->tune_ms) t = -1.0;
     std::vector<std::array<int, kNSched>> cands;
-    for (int v = 0; v < (cols_have_alt(p) ? 2 : 1); ++v)
-        for (int o = 0; o < ((p->d == 3) ? 2 : 1); ++o)
-            for (int c = 0; c < (conv_has_alt(p) ? 2 : 1); ++c)
-                for (int k = 0; k < (kin_has_alt(p) ? 2 : 1); ++k) cands.push_back({k, c, o, v});
+    for (int f = 0; f < (fused_has_alt(p) ? 2 : 1); ++f)
+        for (int v = 0; v < (cols_have_alt(p) ? 2 : 1); ++v)
+            for (int o = 0; o < ((p->d == 3) ? 2 : 1); ++o)
+                for (int c = 0; c < (conv_has_alt(p) ? 2 : 1); ++c)
+                    for (int k = 0; k < (kin_has_alt(p) ? 2 : 1); ++k) cands.push_back({k, c, o, v, f});
     std::vector<std::function<hipError_t()>> fs;
     for (const auto& cd : cands)
         fs.push_back([=]() {
@@ -988,7 +992,7 @@ template <typename R> fse_status tune_measure(fse_plan p, hipStream_t st) {
     double tbest = 0.0;
     for (size_t c = 0; c < cands.size(); ++c) {
         const auto& cd = cands[c];
-        p->tune_ms[cd[0] + 2 * cd[1] + 4 * cd[2] + 8 * cd[3]] = 0.5 * ms[c];
+        p->tune_ms[cd[0] + 2 * cd[1] + 4 * cd[2] + 8 * cd[3] + 16 * cd[4]] = 0.5 * ms[c];
         if (std::equal(cd.begin(), cd.end(), keep)) {
             best = (int)c;
             tbest = ms[c];
@@ -1927,7 +1931,8 @@ fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream) {
                 *tab = '\0';
                 std::array<int, kNSched> v{};
                 int used = 0;
-                if (key == line && std::sscanf(tab + 1, "%d %d %d %d%n", &v[0], &v[1], &v[2], &v[3], &used) == 4 &&
+                if (key == line &&
+                    std::sscanf(tab + 1, "%d %d %d %d %d%n", &v[0], &v[1], &v[2], &v[3], &v[4], &used) == 5 &&
                     std::all_of(v.begin(), v.end(), [](int x) { return x == 0 || x == 1; }))
                     g_tune_cache[key] = v;
             }
@@ -1942,12 +1947,12 @@ fse_status fse_plan_tune(fse_plan plan, const char* cache_path, void* stream) {
     }
     fse_status s = plan->prec == FSE_C128 ? tune_measure<double>(plan, st) : tune_measure<float>(plan, st);
     if (s != FSE_OK) return s;
-    g_tune_cache[key] = {plan->sched[0], plan->sched[1], plan->sched[2], plan->sched[3]};
+    g_tune_cache[key] = {plan->sched[0], plan->sched[1], plan->sched[2], plan->sched[3], plan->sched[4]};
     if (cache_path) {
         FILE* f = std::fopen(cache_path, "a");
         if (!f) return fail(FSE_ERR_ARG, "cannot append to the tuning cache %s", cache_path);
-        std::fprintf(f, "%s\t%d %d %d %d\n", key.c_str(), plan->sched[0], plan->sched[1], plan->sched[2],
-                     plan->sched[3]);
+        std::fprintf(f, "%s\t%d %d %d %d %d\n", key.c_str(), plan->sched[0], plan->sched[1], plan->sched[2],
+                     plan->sched[3], plan->sched[4]);
         std::fclose(f);
     }
     return FSE_OK;
@@ -1974,6 +1979,8 @@ fse_status fse_plan_set_schedule(fse_plan plan, const int* sched) {
     if (sched[2] == 1 && plan->d != 3) return fail(FSE_ERR_UNSUPPORTED, "the mirrored visit order is 3D only");
     if (sched[3] == 1 && !cols_have_alt(plan))
         return fail(FSE_ERR_UNSUPPORTED, "the column transforms of this plan have no alternative radix plan");
+    if (sched[4] == 1 && !fused_has_alt(plan))
+        return fail(FSE_ERR_UNSUPPORTED, "the fused phase pass of this plan has no second radix plan");
     for (int k = 0; k < kNSched; ++k) plan->sched[k] = sched[k];
     return FSE_OK;
 }

@@ -71,10 +71,30 @@ template <typename R, int N, typename PL = void> struct ColCfg {
 // Radix plan of the fused complex-to-real + nonlinear phase kernel: in FP64
 // it keeps three arrays per thread live, so where the plain plan gives a
 // thread 16 points this one gives it 8 (one more LDS exchange per transform,
-// half the registers per array: occupancy 4 instead of 2).
-template <typename R, int N> struct FusedPlan { using L = FwdPlan<N>; };
-template <> struct FusedPlan<double, 256> { using L = RList<8, 8, 4>; };
-template <typename R, int N> using FusedCfg = ColCfg<R, N, typename FusedPlan<R, N>::L>;
+// half the registers per array: occupancy 4 instead of 2).  FV = 1 is the
+// other of the two 256-point plans (16.16 in FP64, 8.8.4 in FP32; the
+// autotuner times both).
+template <typename R, int N, int FV = 0> struct FusedPlan {
+    static constexpr bool has_alt = false;
+    using L = FwdPlan<N>;
+};
+template <> struct FusedPlan<double, 256, 0> {
+    static constexpr bool has_alt = true;
+    using L = RList<8, 8, 4>;
+};
+template <> struct FusedPlan<double, 256, 1> {
+    static constexpr bool has_alt = true;
+    using L = FwdPlan<256>;
+};
+template <> struct FusedPlan<float, 256, 0> {
+    static constexpr bool has_alt = true;
+    using L = FwdPlan<256>;
+};
+template <> struct FusedPlan<float, 256, 1> {
+    static constexpr bool has_alt = true;
+    using L = RList<8, 8, 4>;
+};
+template <typename R, int N, int FV = 0> using FusedCfg = ColCfg<R, N, typename FusedPlan<R, N, FV>::L>;
 
 // Waves per SIMD that the LDS of one workgroup allows (160 KB per CU, four
 // SIMDs).  Column kernels hold 37-78 KB of LDS, so the LDS caps them at 2-4
@@ -683,15 +703,15 @@ void k_r2c(const void* src, typename CT<R>::T* X1,
 //   y = IFFT_N0(Z') unnormalised, Phi_{2m} = Re y_m, Phi_{2m+1} = Im y_m.
 // The GauSum multiplier already carries 1/prod(2 N_j).
 // ---------------------------------------------------------------------------
-template <typename R, int N0, int MODE>
+template <typename R, int N0, int MODE, int FV = 0>
 __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
                                                                   typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
                                                                   const typename CT<R>::T* twN,
                                                                   const typename CT<R>::T* tw2N, int bx, int by, typename CT<R>::T* lds) {
     using T = typename CT<R>::T;
-    using PL = typename PlanOf<N0, typename FusedPlan<R, N0>::L>::L;
-    using Cf = FusedCfg<R, N0>;
+    using PL = typename PlanOf<N0, typename FusedPlan<R, N0, FV>::L>::L;
+    using Cf = FusedCfg<R, N0, FV>;
     constexpr int W = Cf::W, TPL = Cf::TPL;
     constexpr int P = pitch_cols<N0>(N0 + 1);
     using FI = Fft<T, N0, true, TPL, PL>;                    // inverse transforms, outputs at radix-RK positions
@@ -794,16 +814,16 @@ __device__ __forceinline__ void c2r_phase_body(const typename CT<R>::T* X1,
     }
 }
 
-template <typename R, int N0, int MODE>
-__global__ __launch_bounds__((FusedCfg<R, N0>::NTH))
-FSE_COL_OCC(R, N0, FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), FusedCfg<R, N0>::NTH)
+template <typename R, int N0, int MODE, int FV = 0>
+__global__ __launch_bounds__((FusedCfg<R, N0, FV>::NTH))
+FSE_COL_OCC(R, N0, FusedCfg<R, N0, FV>::W * pitch_cols<N0>(N0 + 1) * csz<R>(), FusedCfg<R, N0, FV>::NTH)
 void k_c2r_phase(const typename CT<R>::T* X1,
                                                                   typename CT<R>::T* S, R* Phi_out,
                                                                   int C, PhaseArgs pa,
                                                                   const typename CT<R>::T* __restrict__ twN,
                                                                   const typename CT<R>::T* __restrict__ tw2N) {
-    __shared__ typename CT<R>::T lds[FusedCfg<R, N0>::W * pitch_cols<N0>(N0 + 1)];
-    c2r_phase_body<R, N0, MODE>(X1, S, Phi_out, C, pa, twN, tw2N, blockIdx.x, blockIdx.y, lds);
+    __shared__ typename CT<R>::T lds[FusedCfg<R, N0, FV>::W * pitch_cols<N0>(N0 + 1)];
+    c2r_phase_body<R, N0, MODE, FV>(X1, S, Phi_out, C, pa, twN, tw2N, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------

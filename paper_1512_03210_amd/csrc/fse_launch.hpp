@@ -34,8 +34,9 @@ template <typename R> struct Launch {
     static hipError_t r2c(int N0, int src, const void* in, void* X1, int C, const void* twN, const void* tw2N,
                           hipStream_t st, int cv = 0);
     // Axis-0 complex-to-real + nonlinear phase; mode 0 full, 1 phase only, 2 potential output only.
+    // fv: the fused kernel's radix plan (FusedPlan; modes 0 and 1, where the length has two).
     static hipError_t c2r_phase(int N0, int mode, const void* X1, void* S, void* Phi, int C, const PhaseArgs& pa,
-                                const void* twN, const void* tw2N, hipStream_t st);
+                                const void* twN, const void* tw2N, hipStream_t st, int fv = 0);
     // Batched 2D pass over `count` equal-size instances (kinds in fse_kernels.hpp).
     static hipError_t batch(int kind, int N0, int N1, void* psi, const BInst* bi, int count, int which, LineIdx li,
                             const void* twN0, const void* tw2N0, const void* twN1, const void* tw2N1,
@@ -111,6 +112,8 @@ hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, b
 bool line_has_alt(int n);
 // Whether the column transform of length n has an alternative radix plan (ColPlanOf).
 bool col_has_alt(int n);
+// Whether the fused complex-to-real + phase kernel of axis length n has a second radix plan (FusedPlan).
+bool fused_has_alt(int n);
 
 hipError_t launch_red_final(const double* partials, int nblk, int nslot, int kind, double vol, double n,
                             double beta, double lam, double Omega, double* out, hipStream_t st);

@@ -57,6 +57,18 @@ bool col_has_alt(int n) {
     }
 }
 
+bool fused_has_alt(int n) {
+    switch (n) {
+#define ALT_CASE(NN) \
+    case NN:         \
+        return FusedPlan<double, NN, 0>::has_alt;
+        FSE_N_SIZES(ALT_CASE)
+#undef ALT_CASE
+        default:
+            return false;
+    }
+}
+
 hipError_t launch_copy16(void* dst, const void* src, long n16, hipStream_t st, bool nontemporal) {
     const long g = (n16 + 1023) / 1024;  // 1024 elements per workgroup
     if (g > 0x7fffffffL) return hipErrorInvalidValue;

@@ -22,7 +22,7 @@ STATUS = {0: "FSE_OK", -1: "FSE_ERR_ARG", -2: "FSE_ERR_UNSUPPORTED", -3: "FSE_ER
           -4: "FSE_ERR_HIP", -5: "FSE_ERR_NUMERIC", -6: "FSE_ERR_STATE"}
 STATUS_CODES = {name: code for code, name in STATUS.items()}
 C128, C64 = 0, 1
-NSCHED = 4  # FSE_NSCHED: entries of a pass schedule
+NSCHED = 5  # FSE_NSCHED: entries of a pass schedule
 K_NONE, K_COULOMB, K_DDI3, K_DDI2 = 0, 1, 2, 3
 KERNEL_KINDS = {"none": K_NONE, "coulomb": K_COULOMB, "ddi3": K_DDI3, "ddi2": K_DDI2}
 
@@ -259,8 +259,8 @@ class Plan:
         return self.schedule()
 
     def schedule(self) -> dict:
-        """{"schedule": [kinetic radix, convolution radix, kinetic order, column plan],
-        "tuned_ms": ms per step of schedule {k, c, o, v} at index k + 2c + 4o + 8v (-1: not timed)}"""
+        """{"schedule": [kinetic radix, convolution radix, kinetic order, column plan, fused phase plan],
+        "tuned_ms": ms per step of schedule {k, c, o, v, f} at index k + 2c + 4o + 8v + 16f (-1: not timed)}"""
         sc = (ctypes.c_int * NSCHED)()
         ms = (ctypes.c_double * (1 << NSCHED))()
         _check(lib().fse_plan_get_schedule(self._h, sc, ms))

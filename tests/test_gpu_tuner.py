@@ -40,6 +40,9 @@ CASES = {
                        beta=30.0, lam=4.0, kernel="ddi3", dt=1e-3, name="cols3d"),
     "cols2d": W.Params(d=2, N=(256, 48), L=(12.0, 6.0), s=0.8, Omega=0.5, gamma=(0.4, 1.1), beta=40.0, lam=2.0,
                        kernel="coulomb", dt=1e-3, name="cols2d"),
+    # 256-point axis 0 in 3D: both column plans and both radix plans of the fused phase pass
+    "fused3d": W.Params(d=3, N=(256, 16, 24), L=(12.0, 4.0, 5.0), s=0.7, Omega=0.5, gamma=(0.3, 1.2, 1.0),
+                        beta=40.0, lam=3.0, kernel="ddi3", dt=1e-3, name="fused3d"),
 }
 _REF = {}
 
@@ -79,7 +82,7 @@ def test_every_schedule_against_oracle(name, prec, tol):
     cd = np.complex128 if prec == fse.C128 else np.complex64
     plan = fse.Plan.from_params(p, prec)
     scheds = _schedules(plan)
-    assert len(scheds) == {"rot3d": 8, "rot2d": 4, "cols3d": 4, "cols2d": 2}[name]
+    assert len(scheds) == {"rot3d": 8, "rot2d": 4, "cols3d": 4, "cols2d": 4, "fused3d": 8}[name]
     for sc in scheds:
         plan.set_schedule(sc)
         plan.time = 0.0
@@ -124,12 +127,29 @@ def test_invalid_schedules_rejected():
     small = fse.Plan.from_params(W.preset("plain2d"), fse.C128)  # 64-point lines: no alternative
     with pytest.raises(fse.FseError):
         small.set_schedule([1, 0, 0])
-    assert small.schedule()["schedule"] == [0, 0, 0, 0]
+    assert small.schedule()["schedule"] == [0, 0, 0, 0, 0]
     with pytest.raises(fse.FseError):
         small.set_schedule([0, 0, 0, 1])  # 64-point columns: no alternative plan
+    with pytest.raises(fse.FseError):
+        small.set_schedule([0, 0, 0, 0, 1])  # 64-point fused pass: one plan
     cols = fse.Plan.from_params(CASES["cols2d"], fse.C128)
     cols.set_schedule([0, 0, 0, 1])
-    assert cols.schedule()["schedule"] == [0, 0, 0, 1]
+    assert cols.schedule()["schedule"] == [0, 0, 0, 1, 0]
+    cols.set_schedule([0, 0, 0, 1, 1])
+    assert cols.schedule()["schedule"] == [0, 0, 0, 1, 1]
+
+
+def test_tuning_a_fused_axis_of_256_points():
+    p = CASES["fused3d"]
+    plan = fse.Plan.from_params(p, fse.C64)
+    r = plan.tune()
+    _note(f"[tuner] fused3d c64: {r}")
+    timed = [i for i, t in enumerate(r["tuned_ms"]) if t > 0]
+    assert len(timed) == 8 and sum(1 for i in timed if i & 16) == 4  # both fused plans timed
+    psi0, ref = _ref("fused3d")
+    x = torch.from_numpy(psi0.astype(np.complex64)).cuda()
+    plan.step(x, 2, p.dt)
+    assert float(np.linalg.norm(x.cpu().numpy() - ref) / np.linalg.norm(ref)) < 1e-5
 
 
 def test_tuning_a_column_axis_of_256_points():
