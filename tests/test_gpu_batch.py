@@ -220,3 +220,26 @@ def test_complex64_batch_mass_renormalisation():
     assert np.allclose(out[True][1][1][:, 2], m0, rtol=1e-12, atol=0)
     assert not out[False][1][0]
     assert sum(e_on) <= sum(e_off) * 1.05
+
+
+def test_batch_mass_renorm_switch_records_the_graph_again():
+    # the same buffer and step count after switching the renormalisation off: the cached graph (which holds the
+    # renormalising passes) must be recorded again, so the second call leaves the factors alone and the mass drifts
+    params = _instances()
+    states = _states(params, seed0=60)
+    b = fse.Batch(params, fse.C64)
+    x = b.pack(states)
+    b.step(x, 200)
+    f1 = b.mass_renorm()[1].copy()
+    m1 = b.reduce(x)[:, 0].cpu().numpy()
+    b.set_mass_renorm(False)
+    b.step(x, 200)
+    enabled, f2 = b.mass_renorm()
+    m2 = b.reduce(x)[:, 0].cpu().numpy()
+    _note(f"[batch renorm] after switching off: relative dmass {np.abs((m2 - m1) / m1).max():.2e}")
+    assert not enabled and np.array_equal(f1, f2)
+    assert np.abs((m2 - m1) / m1).max() > 1e-7
+    b.set_mass_renorm(True)
+    b.step(x, 200)
+    m3 = b.reduce(x)[:, 0].cpu().numpy()
+    assert np.abs((m3 - m2) / m2).max() < 1e-7 and not np.array_equal(b.mass_renorm()[1], f2)
