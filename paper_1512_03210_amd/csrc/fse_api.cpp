@@ -843,14 +843,15 @@ fse_status apply_Lz_impl(fse_plan p, const void* psi, void* out, hipStream_t st,
 // ---------------------------------------------------------------------------
 // Autotuner.  Candidates: the radix schedule of the kinetic line transform
 // (plain or alternative), the radix schedule of the convolution line
-// transform, and the kinetic visit order (3D: plain or mirrored).  Every
-// combination is timed on whole steps over the plan's scratch state (the data
-// does not change the work; timing single passes instead misleads where a
-// repeated pass stays in the last-level cache), and another schedule replaces
-// the current one only if it is 2 % faster, so that repeated tuning gives the
-// same schedule.  Choices are cached per device
-// name, architecture, grid, precision and kernel presence for the process, and
-// optionally in a text file of "key<TAB>k c o" lines.
+// transform, the kinetic visit order (3D: plain or mirrored), the radix plan
+// of the column transforms and that of the fused phase pass (where the
+// lengths have two).  Every combination is timed on whole steps over the
+// plan's scratch state (the data does not change the work; timing single
+// passes instead misleads where a repeated pass stays in the last-level
+// cache), and another schedule replaces the current one only if it is 1 %
+// faster, so that repeated tuning gives the same schedule.  Choices are cached
+// per device name, architecture, grid, precision and kernel presence for the
+// process, and optionally in a text file of "key<TAB>k c o v f" lines.
 // ---------------------------------------------------------------------------
 std::mutex g_tune_mu;
 std::map<std::string, std::array<int, kNSched>> g_tune_cache;
