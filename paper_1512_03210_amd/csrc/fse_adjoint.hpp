@@ -9,8 +9,8 @@
 //             g = K^H g1,  dL/dU += dt q,
 // with g = dL/dRe(psi) + i dL/dIm(psi) for a real loss L.  K and K^H are the
 // kinetic passes with +tau and -tau; Phi is the GauSum convolution, which is
-// self-adjoint (real, even multiplier).  Pointwise work is done in FP64 and
-// stored in the plan's precision.
+// self-adjoint (real, even multiplier).  Pointwise work is done in FP64 (the
+// library's own sine/cosine, fsincos) and stored in the plan's precision.
 #pragma once
 #include "fse_kernels.hpp"
 
@@ -41,7 +41,7 @@ __global__ void k_adj_theta(const typename CT<R>::T* __restrict__ psi1, const R*
         theta[i] = R(th);
         if (psi2) {
             double sn, cs;
-            sincos(th, &sn, &cs);
+            fsincos(th, &sn, &cs);
             psi2[i] = typename CT<R>::T{R(v.x * cs + v.y * sn), R(v.y * cs - v.x * sn)};
         }
     }
@@ -54,7 +54,7 @@ __global__ void k_adj_q(const typename CT<R>::T* __restrict__ g2, const typename
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const double2 v = adj::up(psi1[i]), a = adj::up(g2[i]);
         double sn, cs;
-        sincos((double)theta[i], &sn, &cs);
+        fsincos((double)theta[i], &sn, &cs);
         const double px = v.x * cs + v.y * sn, py = v.y * cs - v.x * sn;  // psi2
         const double qi = a.x * py - a.y * px;                          // Im(conj(a) psi2)
         q[i] = R(qi);
@@ -70,7 +70,7 @@ __global__ void k_adj_g1(typename CT<R>::T* __restrict__ g, const typename CT<R>
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const double2 v = adj::up(psi1[i]), a = adj::up(g[i]);
         double sn, cs;
-        sincos((double)theta[i], &sn, &cs);
+        fsincos((double)theta[i], &sn, &cs);
         double r = bdt * (double)q[i];
         if (Phiq) r += ldt * (double)Phiq[i];
         g[i] = typename CT<R>::T{R(a.x * cs - a.y * sn + 2.0 * r * v.x), R(a.y * cs + a.x * sn + 2.0 * r * v.y)};

@@ -14,9 +14,14 @@ input generators of workloads/ (no library code).
 
 Samples: 2048 points uniform over the grid and 2048 points where
 |psi0| >= 1e-2 max|psi0| (inside the condensate), from a seeded generator.
+With "tiles", dipole3d_256_tiles_step1.txt: one step at 8192 points laid out
+so that every tile of 8 adjacent columns of the axis-0 passes (i1, i2 // 8)
+and of the axis-1 passes (i0, i2 // 8) holds exactly one of them: point k has
+i1 = k // 32, i2 = 8 (k % 32) + i1 % 8, i0 = (i1 + 37 (k % 32)) % 256.
 
 Usage (about 8 minutes per step on one core):
-    python tests/golden/make_dipole3d_256_step.py [steps] [order] [local]   (steps 1 or 2, order 2 or 4; default 1 2)
+    python tests/golden/make_dipole3d_256_step.py [steps] [order] [local|tiles]   (steps 1 or 2, order 2 or 4;
+    default 1 2)
 """
 from __future__ import annotations
 
@@ -44,8 +49,18 @@ def sample_indices(psi0):
     return np.unique(np.concatenate([uni, cor]))
 
 
-def main(steps=1, order=2, local=False):
-    tag = "_local" if local else ("" if order == 2 else f"_order{order}")
+def tile_indices(N):
+    """Flat indices of the tile-covering points (one per 8-column tile of the axis-0 and of the axis-1 passes)."""
+    k = np.arange(N[1] * (N[2] // 8))
+    i1 = k // (N[2] // 8)
+    t2 = k % (N[2] // 8)
+    i2 = 8 * t2 + i1 % 8
+    i0 = (i1 + 37 * t2) % N[0]
+    return np.ravel_multi_index((i0, i1, i2), N)
+
+
+def main(steps=1, order=2, local=False, tiles=False):
+    tag = "_local" if local else ("_tiles" if tiles else ("" if order == 2 else f"_order{order}"))
     OUT = os.path.join(HERE, f"dipole3d_256{tag}_step{steps}.txt")
     p = W.preset(PRESET)
     if local:
@@ -53,7 +68,7 @@ def main(steps=1, order=2, local=False):
     psi0 = W.initial_state(p, seed=SEED)
     prob = scheme.Problem.from_params(p)
     ref, _ = prob.run(psi0, steps, p.dt) if order == 2 else prob.run4(psi0, steps, p.dt)
-    idx = sample_indices(psi0)
+    idx = tile_indices(p.N) if tiles else sample_indices(psi0)
     ii = np.unravel_index(idx, p.N)
     vals = ref.ravel()[idx]
     with open(OUT, "w") as f:
@@ -69,4 +84,4 @@ def main(steps=1, order=2, local=False):
 
 if __name__ == "__main__":
     main(int(sys.argv[1]) if len(sys.argv) > 1 else 1, int(sys.argv[2]) if len(sys.argv) > 2 else 2,
-         len(sys.argv) > 3 and sys.argv[3] == "local")
+         len(sys.argv) > 3 and sys.argv[3] == "local", len(sys.argv) > 3 and sys.argv[3] == "tiles")

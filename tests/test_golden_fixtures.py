@@ -2,7 +2,8 @@
 
 dipole3d_256_step1.txt and dipole3d_256_step2.txt hold one and two of the FP64 oracle's TS2-GauSum steps
 (eqs. tssp1-tssp3) of the 256^3 dipolar workload at sampled points, dipole3d_256_order4_step1.txt one
-fourth-order step, dipole3d_256_local_step{1,2}.txt the same workload with lam = 0;
+fourth-order step, dipole3d_256_local_step{1,2}.txt the same workload with lam = 0,
+dipole3d_256_tiles_step1.txt one step at points that cover every column tile;
 tests/golden/make_dipole3d_256_step.py writes them and the GPU parity suite compares the
 library's steps there.  If the workload's parameters or
 initial state change, the fixtures must be written again: these checks fail first.
@@ -66,6 +67,22 @@ def test_fixture_samples_are_distinct_finite_and_cover_the_condensate(name, step
     assert core.sum() >= 2048
     rel = np.linalg.norm(np.abs(v[core]) - a0[core]) / np.linalg.norm(a0[core])
     assert rel < 0.05
+
+
+def test_tile_fixture_puts_one_point_in_every_column_tile():
+    path = _path("dipole3d_256_tiles_step1.txt")
+    p = _workload(False)
+    h = _header(path)
+    for key, val in [("N", p.N), ("L", p.L), ("beta", p.beta), ("lam", p.lam), ("dt", p.dt)]:
+        assert f"{key}={val}" in h, (key, val, h)
+    assert re.search(r"initial_state\(seed=0\); steps=1;( order=2;)? t0=0", h)
+    r = np.loadtxt(path, comments="#")
+    i0, i1, i2 = (r[:, k].astype(int) for k in range(3))
+    n = p.N[1] * p.N[2] // 8
+    assert r.shape == (n, 5) and np.all(np.isfinite(r[:, 3:]))
+    assert len(set(zip(i1, i2 // 8))) == n  # axis-0 passes: columns (i1, i2), tiles of 8 along i2
+    assert len(set(zip(i0, i2 // 8))) == n  # axis-1 passes: columns (i0, i2)
+    assert len(set(zip(i0, i1))) == n       # distinct lines of the contiguous axis
 
 
 def test_batch_fixture_covers_one_instance_of_each_size():

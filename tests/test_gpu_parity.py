@@ -5,6 +5,7 @@ for complex64 after one step; multi-step drift is bounded loosely and
 printed.  Sizes span several tiles and ragged tails (odd line counts of the
 padded passes, 24-column tiles in complex64).
 """
+import itertools
 import math
 import os
 import sys
@@ -494,15 +495,17 @@ def _golden_samples(path):
 @pytest.mark.parametrize("name,steps,order,local", [
     ("dipole3d_256_step1.txt", 1, 2, False), ("dipole3d_256_step2.txt", 2, 2, False),
     ("dipole3d_256_order4_step1.txt", 1, 4, False), ("dipole3d_256_local_step1.txt", 1, 2, True),
-    ("dipole3d_256_local_step2.txt", 2, 2, True)])
+    ("dipole3d_256_local_step2.txt", 2, 2, True), ("dipole3d_256_tiles_step1.txt", 1, 2, False)])
 @pytest.mark.parametrize("prec,tol", [(fse.C128, 1e-12), (fse.C64, 1e-5)])
 def test_dipole3d_256_steps_against_oracle_samples(name, steps, order, local, prec, tol):
     """One and two TS2 steps and one fourth-order step of the benchmarked
     256^3 dipolar workload, and one and two steps of it without the nonlocal
     term (two steps pass through the merged full-step kinetic junction of
     every inner step), under every pass schedule the tuner can choose, against
-    the oracle at 4096 stored points (tests/golden/make_dipole3d_256_step.py
-    writes them)."""
+    the oracle at stored points (tests/golden/make_dipole3d_256_step.py writes
+    them): 4096 over the grid and the condensate, and for one step 8192 more
+    that put one point in every 8-column tile of the axis-0 and of the axis-1
+    passes."""
     p = W.preset("dipole3d_256")
     if local:
         p = p.replace(lam=0.0)
@@ -510,9 +513,16 @@ def test_dipole3d_256_steps_against_oracle_samples(name, steps, order, local, pr
     psi0 = W.initial_state(p, seed=0)
     plan = fse.Plan.from_params(p, prec)
     it = torch.from_numpy(idx).to("cuda:0")
-    convs = (0,) if local else (0, 1)  # without a convolution there is no convolution schedule
-    for sched in [(k, c, o) for o in (0, 1) for c in convs for k in (0, 1)]:
-        plan.set_schedule(sched)
+    scheds = []
+    for sched in itertools.product((0, 1), repeat=fse.NSCHED):
+        try:  # (without a convolution there is no convolution schedule)
+            plan.set_schedule(list(sched))
+        except fse.FseError:
+            continue
+        scheds.append(sched)
+    assert len(scheds) == (16 if local else 32)
+    for sched in scheds:
+        plan.set_schedule(list(sched))
         plan.time = 0.0
         x = _dev(psi0, prec)
         plan.step(x, steps, p.dt, order=order)
