@@ -240,7 +240,7 @@ def run_batch(steps):
         "steps": steps,
         "value": npts * steps / (ms * 1e-3),
         "unit": "grid-point-steps/s",
-        "dtype": "c64 (FP64 reductions)",
+        "dtype": "f32 (complex64; FP64 reductions)",
         "ms_per_step": ms / steps,
         "fp64_single_one_by_one_value": npts * steps / (ms64 * 1e-3),
         "speedup_vs_fp64_single": ms64 / ms,
@@ -626,7 +626,7 @@ def main():
         r32 = run_precision(p, fse.C64, args.steps, args.warmup, args.prof_steps, args.tune)
         print(f"[bench] c64 {r32['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
         variants["c64"] = {
-            "value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "c64 (FP64 reductions)",
+            "value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32 (complex64; FP64 reductions)",
             "step_hbm_frac": r32["step_hbm_frac"], "model_bytes_per_point": r32["model_bytes_per_point"],
             "speedup_vs_c128": r32["value"] / r64["value"], "passes": r32["passes"], "schedule": r32["schedule"],
         }
@@ -635,7 +635,7 @@ def main():
     rl = run_precision(ql, fse.C128, args.steps, args.warmup, args.prof_steps, args.tune)
     variants["local_c128"] = {
         "workload": "the same 256^3 step without the nonlocal term (lambda = 0)",
-        "value": rl["value"], "ms_per_step": rl["ms_per_step"], "dtype": "c128",
+        "value": rl["value"], "ms_per_step": rl["ms_per_step"], "dtype": "f64",
         "step_hbm_frac": rl["step_hbm_frac"], "model_bytes_per_point": rl["model_bytes_per_point"],
         "passes": rl["passes"],
     }
@@ -713,7 +713,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c128",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": (f"{p.name}: {'x'.join(map(str, p.N))} grid on [-{p.L[0]:g},{p.L[0]:g}]^{p.d}, "
