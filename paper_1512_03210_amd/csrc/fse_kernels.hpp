@@ -1358,7 +1358,10 @@ __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src
                 v[u].x = __builtin_nontemporal_load(&src[i].x);
                 v[u].y = __builtin_nontemporal_load(&src[i].y);
             } else {
-                v[u] = src[i];
+                // (component accesses: a whole-struct copy here made the compiler
+                // move v into LDS)
+                v[u].x = src[i].x;
+                v[u].y = src[i].y;
             }
         }
     }
@@ -1370,7 +1373,8 @@ __global__ __launch_bounds__(256) void k_copy16(double2* dst, const double2* src
                 __builtin_nontemporal_store(v[u].x, &dst[i].x);
                 __builtin_nontemporal_store(v[u].y, &dst[i].y);
             } else {
-                dst[i] = v[u];
+                dst[i].x = v[u].x;
+                dst[i].y = v[u].y;
             }
         }
     }
