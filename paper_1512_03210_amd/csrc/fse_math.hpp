@@ -18,7 +18,8 @@ namespace fse {
 // exact to 1e-23); each FMA forms x - k*Pi exactly before its one rounding,
 // so r is accurate to about an ulp while k*P3 stays far below it (|k| < 2^22;
 // larger arguments carry 0.25 rad of rounding themselves).  Taylor series to
-// degree 15 and 14 (truncation below 1e-14).  Error at most 1.2 ulp of 1 (7e-8);
+// degree 11 and 10 (truncation below 1.1e-10 on |r| <= pi/4, far under the
+// float rounding).  Error at most 1.2 ulp of 1 (7e-8);
 // the float rounding of 1/6 and 1/24 biases s^2 + c^2 by -1e-8 r^4 (below
 // 4e-9, and 2e-11 for the phase angles of a time step, |r| < 0.2).
 // ---------------------------------------------------------------------------
@@ -60,17 +61,13 @@ __device__ __forceinline__ void fsincos(float x, float* s, float* c) {
     r = fmaf(-k, -4.37113883e-08f, r);
     r = fmaf(-k, -1.71512451e-15f, r);
     const float r2 = r * r;
-    float ps = -7.64716374e-13f;  // -1/15!
-    ps = fmaf(ps, r2, 1.60590444e-10f);
-    ps = fmaf(ps, r2, -2.50521079e-08f);
+    float ps = -2.50521079e-08f;  // -1/11!
     ps = fmaf(ps, r2, 2.75573188e-06f);
     ps = fmaf(ps, r2, -1.98412701e-04f);
     ps = fmaf(ps, r2, 8.33333377e-03f);
     ps = fmaf(ps, r2, -1.66666672e-01f);
     const float sn = fmaf(r * r2, ps, r);
-    float pc = 1.14707454e-11f;  // 1/14!
-    pc = fmaf(pc, r2, -2.08767559e-09f);
-    pc = fmaf(pc, r2, 2.75573200e-07f);
+    float pc = 2.75573200e-07f;  // 1/10!
     pc = fmaf(pc, r2, -2.48015876e-05f);
     pc = fmaf(pc, r2, 1.38888892e-03f);
     pc = fmaf(pc, r2, -4.16666679e-02f);
