@@ -493,6 +493,84 @@ struct MidStagesTw<T, M, INV, TPL, NS, RList<R0, Rs...>, WS, TWL, MODE> {
     }
 };
 
+// One component (C = 0: real, 1: imaginary) of a stage's values to / from a
+// line of scalars, at the positions of put and get.
+template <int C, typename T, int M, int TPL, int NS, int RAD, int B>
+__device__ __forceinline__ void put_c(const T (&v)[B][RAD], typename RealOf<T>::R* line, int jt) {
+    using S = Shape<M, TPL, RAD>;
+#pragma unroll
+    for (int b = 0; b < S::B; ++b) {
+        const int j = jt + b * TPL;
+        if (S::active(j)) {
+            const int base = (j / NS) * NS * RAD + j % NS;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) line[padx<M>(base + r * NS)] = (C == 0) ? v[b][r].x : v[b][r].y;
+        }
+    }
+}
+
+template <int C, typename T, int M, int TPL, int RAD, int B>
+__device__ __forceinline__ void get_c(T (&v)[B][RAD], const typename RealOf<T>::R* line, int jt) {
+    using S = Shape<M, TPL, RAD>;
+#pragma unroll
+    for (int b = 0; b < S::B; ++b) {
+        const int j = jt + b * TPL;
+        if (S::active(j)) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                if constexpr (C == 0) v[b][r].x = line[padx<M>(j + r * S::NB)];
+                else v[b][r].y = line[padx<M>(j + r * S::NB)];
+            }
+        }
+    }
+}
+
+// Stage-to-stage exchange through a line of scalars, one component at a time:
+// half the LDS of a complex line, so more lines fit on a CU; four ordering
+// points instead of two.  a: the outputs of a stage of radix RP at stride NSP;
+// b: the inputs of the next stage (radix RN).
+template <typename T, int M, int TPL, int NSP, int RP, int RN, bool WS, int BP, int BN>
+__device__ __forceinline__ void xchg_split(const T (&a)[BP][RP], T (&b)[BN][RN], typename RealOf<T>::R* line, int jt) {
+    lds_sync<WS>();
+    put_c<0, T, M, TPL, NSP, RP>(a, line, jt);
+    lds_sync<WS>();
+    get_c<0, T, M, TPL, RN>(b, line, jt);
+    lds_sync<WS>();
+    put_c<1, T, M, TPL, NSP, RP>(a, line, jt);
+    lds_sync<WS>();
+    get_c<1, T, M, TPL, RN>(b, line, jt);
+}
+
+// The stages after the first with split exchanges.  vp holds the outputs of
+// the previous stage (radix RP at stride NSP); L lists the middle radices
+// left; the last stage (radix RK) writes u.
+template <typename T, int M, bool INV, int TPL, int NSP, int RP, typename L, int RK, bool WS, int TWL> struct SplitStages;
+template <typename T, int M, bool INV, int TPL, int NSP, int RP, int RK, bool WS, int TWL>
+struct SplitStages<T, M, INV, TPL, NSP, RP, RList<>, RK, WS, TWL> {
+    template <int BP, int BK>
+    __device__ __forceinline__ static void run(T (&vp)[BP][RP], T (&u)[BK][RK], typename RealOf<T>::R* line, int jt,
+                                               const T* __restrict__ tw) {
+        TwP<T, M, TPL, M / RK, RK, TWL> tp;
+        tp.load(jt, tw);
+        xchg_split<T, M, TPL, NSP, RP, RK, WS>(vp, u, line, jt);
+        bfly<T, M, INV, TPL, M / RK, RK>(u, jt, tp);
+    }
+};
+template <typename T, int M, bool INV, int TPL, int NSP, int RP, int R0, int... Rs, int RK, bool WS, int TWL>
+struct SplitStages<T, M, INV, TPL, NSP, RP, RList<R0, Rs...>, RK, WS, TWL> {
+    static constexpr int NS = NSP * RP;
+    template <int BP, int BK>
+    __device__ __forceinline__ static void run(T (&vp)[BP][RP], T (&u)[BK][RK], typename RealOf<T>::R* line, int jt,
+                                               const T* __restrict__ tw) {
+        T v[Shape<M, TPL, R0>::B][R0];
+        TwP<T, M, TPL, NS, R0, TWL> tp;
+        tp.load(jt, tw);
+        xchg_split<T, M, TPL, NSP, RP, R0, WS>(vp, v, line, jt);
+        bfly<T, M, INV, TPL, NS, R0>(v, jt, tp);
+        SplitStages<T, M, INV, TPL, NS, R0, RList<Rs...>, RK, WS, TWL>::run(v, u, line, jt, tw);
+    }
+};
+
 // Whole transform with register-resident ends.
 //   in:  v = inputs at positions j + r*M/R0 (first radix R0 of the plan L)
 //   out: u = outputs at positions j + r*M/Rk (last radix Rk)
@@ -501,7 +579,8 @@ struct MidStagesTw<T, M, INV, TPL, NS, RList<R0, Rs...>, WS, TWL, MODE> {
 // reuse).  Single-stage plans use no LDS.  WS: the threads of a line are
 // lanes of one wavefront (see lds_sync).  TWL: twiddle powers read per
 // butterfly (see TwP).
-template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int TWL = 4> struct Fft {
+// XS: split exchanges (xchg_split); `line` then holds M padded scalars.
+template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int TWL = 4, bool XS = false> struct Fft {
     static constexpr int R0 = Head<L>::value;
     static constexpr int RK = Last<L>::value;
     static constexpr int B0 = Shape<M, TPL, R0>::B;
@@ -518,6 +597,10 @@ template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int
 #pragma unroll
                 for (int r = 0; r < R0; ++r) u[b][r] = v[b][r];
             bfly<T, M, INV, TPL, 1, R0>(u, jt, tw);
+        } else if constexpr (XS) {
+            bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
+            SplitStages<T, M, INV, TPL, 1, R0, typename Mid<L>::L, RK, WS, TWL>::run(
+                v, u, reinterpret_cast<typename RealOf<T>::R*>(line), jt, tw);
         } else {
             bfly<T, M, INV, TPL, 1, R0>(v, jt, tw);
             put<T, M, TPL, 1, R0>(v, line, jt);
@@ -537,6 +620,7 @@ template <typename T, int M, bool INV, int TPL, typename L, bool WS = false, int
     template <int MODE>
     __device__ __forceinline__ static void run_tw(T (&v)[B0][R0], T (&u)[BK][RK], T* line, int jt,
                                                   const T* __restrict__ tw, Keep& keep) {
+        static_assert(!XS, "split exchanges take the twiddles from the table");
         if constexpr (NSTAGE == 1) {
             run(v, u, line, jt, tw);
         } else {

@@ -158,6 +158,14 @@ template <typename R, int N, bool CONV, int V = 0> struct LineCfg {
     static constexpr int LPBW = (TPL * SUB >= 64) ? 1 : 64 / (TPL * SUB);  // at least one full wavefront
     static constexpr int LPB = LPB1 < LPBW ? LPBW : LPB1;
     static constexpr int NTH = LPB * TPL * SUB;
+    // FP64 512-point lines of the padded convolution (default radix plan)
+    // exchange one component at a time (xchg_split): half the LDS per line, so
+    // the LDS no longer caps a CU at 17 lines
+    static constexpr bool XS = !CONV && sizeof(R) == 8 && N == 512 && V == 0;
+    static constexpr int LDS = XS ? (LPB * P + 1) / 2 : LPB * P;  // complex elements per workgroup
+    // waves per SIMD asked of the register allocator with split exchanges: the
+    // LDS would allow 8, but 7 and 8 spill (6: 74 VGPRs, no spill)
+    static constexpr int OCC = lds_waves(LDS * (int)sizeof(T), NTH) < 6 ? lds_waves(LDS * (int)sizeof(T), NTH) : 6;
 };
 
 // Calls f(b, r, e) for every position e = j + r*N/RAD the thread owns.
@@ -550,33 +558,12 @@ __global__ __launch_bounds__((LineCfg<R, N, false>::NTH)) void k_lines_deriv(con
 // registers between the forward and the inverse, and only the first N points
 // are stored.
 // ---------------------------------------------------------------------------
-template <typename R, int M, int V = 0, bool QF = false>
-__device__ __forceinline__ void conv_full_body(
-    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
-    const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds, const QForm* qf = nullptr) {
-    using T = typename CT<R>::T;
-    using C = LineCfg<R, M, false, V>;
-    constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
-    constexpr int N = M / 2;
-    constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
-    using FF = Fft<T, M, false, TPL, LineFwd<M, V>, WS, 2>;
-    using FI = Fft<T, M, true, TPL, LineInv<M, V>, WS, 2>;
-    const int jt = threadIdx.x % TPL;
-    // one line per wavefront (TPL = 64): the line index is uniform, so the
-    // line and multiplier-row arithmetic stays in scalar registers and the
-    // loads take a scalar base with 32-bit lane offsets
-    const int dl = (TPL == 64) ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPL) : threadIdx.x / TPL;
-    const int gv = ((LPB == 1) ? xcd_pairs(bx, gridDim.x) : bx) * LPB + dl;
-    const bool valid = gv < nlines;
-    const int gl = valid ? line_at(gv, li) : 0;
-    T* line = lds + dl * P;
-    T* g = data + (long)gl * N;
-    typename FF::In v;
-    typename FF::Out u;
-    // (a line past the end reads line 0 and stores nothing)
-    for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (e < N) ? g[e] : T{0, 0}; });
-    const long row = mult_row(gl, li);
-    R kq[FF::BK][FF::RK];
+// The multiplier of one convolution line at the positions of the forward
+// transform's last stage: the stored row, or with QF the dipolar quadratic form
+// evaluated from it.
+template <typename R, int M, int TPL, int RK, int BK, bool QF>
+__device__ __forceinline__ void conv_mult(R (&kq)[BK][RK], const R* mult, long row, int gl, const LineIdx& li,
+                                          const QForm* qf, int jt) {
     if constexpr (QF) {
         QForm qd = *qf;
         if (qd.tp) qform_fill(qd, *qd.tp + qd.toff, qd.tau);
@@ -588,21 +575,57 @@ __device__ __forceinline__ void conv_full_body(
         const double x0 = (k0 == q->n0) ? 0.0 : a0, x1 = (k1r == q->n1) ? 0.0 : a1;
         const double base = q->m00 * a0 * a0 + q->m11 * a1 * a1 + 2.0 * q->m01 * x0 * x1;
         const double lin = 2.0 * (q->m02 * x0 + q->m12 * x1);
-        for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) {
+        for_pos<M, TPL, RK>(jt, [&](int b, int r, int p) {
             const int k2 = (p <= M / 2) ? p : p - M;
             const double a2 = k2 * q->dk2, x2 = (p == M / 2) ? 0.0 : a2;
             const double Q = base + q->m22 * a2 * a2 + lin * x2;
             kq[b][r] = R(q->c0 + (double)mult[row + min(p, M - p)] * Q);
         });
     } else {
-        for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
+        for_pos<M, TPL, RK>(jt, [&](int b, int r, int p) { kq[b][r] = mult[row + min(p, M - p)]; });
     }
+}
+
+template <typename R, int M, int V = 0, bool QF = false>
+__device__ __forceinline__ void conv_full_body(
+    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
+    const typename CT<R>::T* twM, int bx, int by, typename CT<R>::T* lds, const QForm* qf = nullptr) {
+    using T = typename CT<R>::T;
+    using C = LineCfg<R, M, false, V>;
+    constexpr int P = C::P, TPL = C::TPL, LPB = C::LPB;
+    constexpr int N = M / 2;
+    constexpr bool WS = (64 % TPL) == 0;  // a line's threads share one wavefront
+    constexpr bool XS = C::XS && !QF;  // (the quadratic form needs the registers more than the waves)
+    using FF = Fft<T, M, false, TPL, LineFwd<M, V>, WS, 2, XS>;
+    using FI = Fft<T, M, true, TPL, LineInv<M, V>, WS, 2, XS>;
+    const int jt = threadIdx.x % TPL;
+    // one line per wavefront (TPL = 64): the line index is uniform, so the
+    // line and multiplier-row arithmetic stays in scalar registers and the
+    // loads take a scalar base with 32-bit lane offsets
+    const int dl = (TPL == 64) ? __builtin_amdgcn_readfirstlane(threadIdx.x / TPL) : threadIdx.x / TPL;
+    const int gv = ((LPB == 1) ? xcd_pairs(bx, gridDim.x) : bx) * LPB + dl;
+    const bool valid = gv < nlines;
+    const int gl = valid ? line_at(gv, li) : 0;
+    // (with split exchanges a line is P scalars)
+    T* line = XS ? reinterpret_cast<T*>(reinterpret_cast<R*>(lds) + dl * P) : lds + dl * P;
+    T* g = data + (long)gl * N;
+    typename FF::In v;
+    typename FF::Out u;
+    // (a line past the end reads line 0 and stores nothing)
+    for_pos<M, TPL, FF::R0>(jt, [&](int b, int r, int e) { v[b][r] = (e < N) ? g[e] : T{0, 0}; });
+    const long row = mult_row(gl, li);
+    R kq[FF::BK][FF::RK];
+    // the multiplier row is read while the forward transform runs, except with
+    // split exchanges, which need those registers to fit the occupancy their
+    // LDS allows
+    if constexpr (!XS) conv_mult<R, M, TPL, FF::RK, FF::BK, QF>(kq, mult, row, gl, li, qf, jt);
     // FP32 (bound by VALU issue) with a palindromic plan: the inverse takes the
     // forward's twiddles from registers
     constexpr bool KEEP = sizeof(R) == 4 && std::is_same<LineFwd<M, V>, LineInv<M, V>>::value;
     typename FF::Keep keep;
     if constexpr (KEEP) FF::template run_tw<TW_KEEP>(v, u, line, jt, twM, keep);
     else FF::run(v, u, line, jt, twM);
+    if constexpr (XS) conv_mult<R, M, TPL, FF::RK, FF::BK, QF>(kq, mult, row, gl, li, qf, jt);
     for_pos<M, TPL, FF::RK>(jt, [&](int b, int r, int) {
         u[b][r] = T{u[b][r].x * kq[b][r], u[b][r].y * kq[b][r]};
     });
@@ -628,8 +651,21 @@ template <typename R, int M, int V = 0>
 __global__ __launch_bounds__((LineCfg<R, M, false, V>::NTH)) void k_conv_full(
     typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
     const typename CT<R>::T* twM) {
-    __shared__ typename CT<R>::T lds[LineCfg<R, M, false, V>::LPB * LineCfg<R, M, false, V>::P];
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false, V>::LDS];
     conv_full_body<R, M, V>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds);
+}
+
+// The same with split exchanges (LineCfg::XS), at the occupancy their LDS
+// allows within the registers (a kernel of its own: the occupancy request
+// changes the register allocation of every kernel it is attached to).
+template <typename R, int M>
+__global__ __launch_bounds__((LineCfg<R, M, false>::NTH))
+__attribute__((amdgpu_waves_per_eu(LineCfg<R, M, false>::OCC, 8))) void k_conv_xs(
+    typename CT<R>::T* data, int nlines, const R* mult, LineIdx li,
+    const typename CT<R>::T* twM) {
+    static_assert(LineCfg<R, M, false>::XS, "split-exchange configuration only");
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LDS];
+    conv_full_body<R, M, 0>(data, nlines, mult, li, twM, blockIdx.x, blockIdx.y, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -925,7 +961,7 @@ __global__ __launch_bounds__((LineCfg<R, M, false>::NTH)) void k_b_conv_full(con
                                                                             const typename CT<R>::T* twM) {
     using T = typename CT<R>::T;
     const BInst& b = bi[blockIdx.y];
-    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LPB * LineCfg<R, M, false>::P];
+    __shared__ typename CT<R>::T lds[LineCfg<R, M, false>::LDS];
     conv_full_body<R, M>(static_cast<T*>(b.X1), nlines, static_cast<const R*>(b.khat), li, twM, blockIdx.x, 0, lds);
 }
 
