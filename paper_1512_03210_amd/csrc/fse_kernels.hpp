@@ -60,11 +60,14 @@ template <int N, typename PL> struct PlanOf { using L = PL; };
 template <int N> struct PlanOf<N, void> { using L = ColPlan<N>; };
 
 // Column tile: W columns of 128 B, TPL threads per column (the plan's first
-// radix sets the points per thread); PL = void selects the plain plan.
+// radix sets the points per thread); PL = void selects the plain plan.  A
+// 512-point complex64 tile (64 KB of LDS: two workgroups per CU) takes 1024
+// threads, so that the two workgroups bring 32 waves to the CU, not 16.
 template <typename R, int N, typename PL = void> struct ColCfg {
     static constexpr int W = (sizeof(R) == 8) ? 8 : 16;
     static constexpr int TPL0 = N / Head<typename PlanOf<N, PL>::L>::value;
-    static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 * W > 512 ? 512 / W : TPL0);
+    static constexpr int CAP = (sizeof(R) == 4 && N == 512) ? 1024 : 512;  // threads per workgroup
+    static constexpr int TPL = TPL0 < 4 ? 4 : (TPL0 * W > CAP ? CAP / W : TPL0);
     static constexpr int NTH = W * TPL;
 };
 
