@@ -63,6 +63,9 @@ typedef enum {
     FSE_ERR_NUMERIC = -5,      /* non-finite parameter or result */
     FSE_ERR_STATE = -6         /* call not valid in the plan's current state */
 } fse_status;
+/* A NULL plan or batch handle, or a NULL where a pointer is required, returns
+ * FSE_ERR_ARG (message in fse_last_error) before anything touches the device;
+ * destroying a NULL handle does nothing and returns FSE_OK. */
 
 typedef enum { FSE_C128 = 0, FSE_C64 = 1 } fse_precision;
 

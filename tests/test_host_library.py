@@ -152,3 +152,39 @@ def test_gpu_entry_points_fail_cleanly_without_device():
     st = fse.lib().fse_plan_create(fse.ctypes.byref(h), 2, fse._iarr((64, 64)), fse._darr((8.0, 8.0)), 0.75, 0.5,
                                    fse._darr((1.0, 1.0)), 1.0, 1.0, None, 0, 0.0, None)
     assert st == -4 and not h.value
+
+
+def _declarations():
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "fse.h")).read(), flags=re.S)
+    for m in re.finditer(r"^\s*fse_status\s+(fse_\w+)\s*\(([^)]*)\)\s*;", text, re.M):
+        yield m.group(1), [a.strip() for a in m.group(2).split(",")]
+
+
+def test_null_handles_are_rejected_on_the_host():
+    # every entry point that takes a plan or batch handle (or returns one): NULL and zero arguments give
+    # FSE_ERR_ARG with a message, without a device; destroying NULL is a no-op
+    lib, seen = fse.ctypes.CDLL(fse.lib()._name), 0  # a private wrapper: the binding's argtypes stay as they are
+    for name, args in _declarations():
+        if not args[0].startswith(("fse_plan", "fse_batch")):
+            continue
+        vals, types = [], []
+        for a in args:
+            if "*" in a or a.startswith(("fse_plan", "fse_batch")):
+                vals.append(None), types.append(fse.ctypes.c_void_p)
+            elif a.startswith("double"):
+                vals.append(0.0), types.append(fse.ctypes.c_double)
+            elif a.startswith("size_t"):
+                vals.append(0), types.append(fse.ctypes.c_size_t)
+            else:
+                assert a.startswith("int "), (name, a)
+                vals.append(0), types.append(fse.ctypes.c_int)
+        f = getattr(lib, name)
+        f.argtypes, f.restype = types, fse.ctypes.c_int
+        st = f(*vals)
+        if name.endswith("_destroy"):
+            assert st == 0, name
+        else:
+            assert st == -1, (name, st)
+            assert fse.lib().fse_last_error(), name
+        seen += 1
+    assert seen >= 40
