@@ -36,9 +36,11 @@ def test_load_checks_the_stored_shape(tmp_path):
     prefix = os.path.join(tmp_path, "ck")
     checkpoint.save(prefix, p, torch.zeros(p.N, dtype=torch.complex128), 0.0, fse.C128)
     import json
-    meta = json.load(open(prefix + ".json"))
+    with open(prefix + ".json") as f:
+        meta = json.load(f)
     meta["shape"] = [1, 2]
-    json.dump(meta, open(prefix + ".json", "w"))
+    with open(prefix + ".json", "w") as f:
+        json.dump(meta, f)
     with pytest.raises(ValueError):
         checkpoint.load(prefix, device="cpu")
 
