@@ -538,8 +538,9 @@ class Batch:
         return [h[self.offsets[k]:self.offsets[k + 1]].reshape(self.params[k].N) for k in range(self.count)]
 
     def _check_packed(self, packed):
-        if packed.dtype != self.cdtype or packed.numel() != self.offsets[-1] or not packed.is_contiguous():
-            raise ValueError("packed state has the wrong dtype or size")
+        if (packed.dtype != self.cdtype or packed.numel() != self.offsets[-1] or not packed.is_contiguous()
+                or not packed.is_cuda):
+            raise ValueError("packed state must be a contiguous device tensor of the batch's dtype and size")
 
     def step(self, packed, nsteps: int, stream=None):
         self._check_packed(packed)
