@@ -165,14 +165,26 @@ def _darr(v):
     return (ctypes.c_double * len(v))(*[float(x) for x in v])
 
 
+def _check_axes(d, **arrays):
+    """The library reads d values from each per-axis array: refuse shorter ones here (a d other than 2 or 3 the
+    library rejects before it reads any array)."""
+    if int(d) not in (2, 3):
+        return
+    for name, a in arrays.items():
+        if a is None or len(a) < int(d):
+            raise ValueError(f"{name} needs {int(d)} values (one per axis)")
+
+
 def plan_check(d, N, L, s, Omega, gamma, beta, lam, kernel: Optional[Kernel], precision=C128) -> int:
-    """Host-only validation; returns the status code (no exception)."""
+    """Host-only validation; returns the status code (no exception; arrays shorter than d raise ValueError)."""
+    _check_axes(d, N=N, L=L, gamma=gamma)
     return lib().fse_plan_check(d, _iarr(N), _darr(L), s, Omega, _darr(gamma), beta, lam,
                                 ctypes.byref(kernel) if kernel is not None else None, precision)
 
 
 def gausum_symbol_host(d, N, L, kernel: Kernel) -> np.ndarray:
     """The multiplier on the non-negative frequency octant, shape (N_j + 1,) per axis (host)."""
+    _check_axes(d, N=N, L=L)
     shape = tuple(int(n) + 1 for n in N)
     out = np.zeros(int(np.prod(shape)), dtype=np.float64)
     _check(lib().fse_gausum_symbol_host(d, _iarr(N), _darr(L), ctypes.byref(kernel),
@@ -212,6 +224,7 @@ class Plan:
                  gamma: Sequence[float], beta: float, lam: float, kernel: Optional[Kernel] = None,
                  precision: int = C128, m: float = 0.0, stream=None):
         import torch
+        _check_axes(d, N=N, L=L, gamma=gamma)
         self.d, self.N, self.L = int(d), tuple(int(n) for n in N), tuple(float(x) for x in L)
         self.precision = precision
         self.cdtype = torch.complex128 if precision == C128 else torch.complex64
@@ -279,6 +292,7 @@ class Plan:
             _check(lib().fse_set_lattice(self._h, None, None))
             self._lattice = None
         else:
+            _check_axes(self.d, v=v, k=k)
             _check(lib().fse_set_lattice(self._h, _darr(v), _darr(k)))
             self._lattice = ([float(a) for a in v], [float(a) for a in k])
 

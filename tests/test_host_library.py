@@ -188,3 +188,23 @@ def test_null_handles_are_rejected_on_the_host():
             assert fse.lib().fse_last_error(), name
         seen += 1
     assert seen >= 40
+
+
+def test_per_axis_arrays_shorter_than_d_are_refused_before_the_library():
+    # the library reads d values from N, L and gamma (and from the lattice's v and k): the binding refuses shorter
+    # sequences, which would make it read past the end of a host array
+    k = fse.make_kernel("coulomb", prefactor=1 / (2 * math.pi))
+    for args in (((32, 32), (6.0,) * 3, (1.0,) * 3), ((32,) * 3, (6.0,) * 2, (1.0,) * 3), ((32,) * 3, (6.0,) * 3, (1.0,) * 2)):
+        with pytest.raises(ValueError):
+            fse.plan_check(3, args[0], args[1], 0.8, 0.5, args[2], 10.0, 1.0, k)
+        with pytest.raises(ValueError):
+            fse.Plan(3, args[0], args[1], 0.8, 0.5, args[2], 10.0, 1.0, k)
+    with pytest.raises(ValueError):
+        fse.gausum_symbol_host(3, (32, 32), (6.0,) * 3, k)
+    p = fse.Plan.__new__(fse.Plan)
+    p.d, p._h = 3, None
+    with pytest.raises(ValueError):
+        p.set_lattice(v=(1.0, 1.0), k=(1.0, 1.0, 1.0))
+    with pytest.raises(ValueError):
+        p.set_lattice(v=(1.0, 1.0, 1.0), k=(1.0,))
+    assert fse.plan_check(4, (32,) * 4, (6.0,) * 4, 0.8, 0.5, (1.0,) * 4, 10.0, 1.0, k) == -1  # the library's own check
