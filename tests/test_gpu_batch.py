@@ -68,6 +68,24 @@ def test_batch_matches_oracle_per_instance(prec, tol):
     assert np.allclose(b.times(), [4 * p.dt for p in params], rtol=0, atol=1e-15)
 
 
+def test_batch_fp64_with_512_point_convolution_lines():
+    # a 256-point contiguous axis pads to 512-point convolution lines: in FP64 these exchange one component at a
+    # time through half-size LDS lines, inside the batch's own kernels too
+    base = dict(L=(8.0, 8.0), beta=100.0, lam=1.0, kernel="coulomb", mu=1.0)
+    params = [W.Params(d=2, N=(48, 256), s=0.8, Omega=0.5, gamma=(1.0, 1.2), dt=1e-3, name="w", **base),
+              W.Params(d=2, N=(64, 64), s=0.7, Omega=0.3, gamma=(1.0, 1.0), dt=1e-3, name="s", **base)]
+    states = _states(params, seed0=40)
+    ref = _oracle(params, states, 3)
+    b = fse.Batch(params, fse.C128)
+    x = b.pack(states)
+    b.step(x, 3)
+    torch.cuda.synchronize()
+    for k, (got, r) in enumerate(zip(b.unpack(x), ref)):
+        err = float(np.linalg.norm(got - r) / np.linalg.norm(r))
+        _note(f"[batch] FP64 instance {params[k].name} N={params[k].N}: {err:.3e}")
+        assert err < 1e-11
+
+
 def test_batch_graph_replays_with_eager_work_between():
     params = _instances()
     states = _states(params, seed0=20)
